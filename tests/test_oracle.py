@@ -1,0 +1,382 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is only trusted because these tests tie it to things other than
+itself: the worked examples printed in the paper (Figures 1 and 3), library
+stable sorts, brute force over every tie pattern of tiny inputs, an
+independent formulation of the node power (the "tick" form used in the proof
+of Theorem 3.3), and the invariants of Section 3 (Fact 3.2, the leaf-depth
+identity, Theorem 3.3, Proposition 3.5).  A plausible slip anywhere in the
+oracle (wrong tie rule, off-by-one power, wrong final merge phase, dropped
+reversal) breaks at least one of them.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+# ---------------------------------------------------------------- helpers
+
+def starts_from_lengths(lengths):
+    return np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint64)
+
+
+def ceil_log_plus1(k, x_num, x_den=1):
+    """Least integer c with k**(c-1) >= x_num/x_den, i.e. ceil(log_k(x) + 1)."""
+    c = 0
+    while Fraction(k) ** (c - 1) < Fraction(x_num, x_den):
+        c += 1
+    return c
+
+
+def tick_power(n, s_prev, s_cur, s_next, k):
+    """Power via the tick form from the proof of Theorem 3.3: the least p such
+    that some multiple c*k^-p lies in the half-open midpoint interval (a, b]."""
+    a = Fraction(s_prev + s_cur, 2 * n)
+    b = Fraction(s_cur + s_next, 2 * n)
+    p = 0
+    while True:
+        step = Fraction(1, k ** p)
+        c = (b // step)             # largest tick <= b
+        if c * step > a:
+            return p
+        p += 1
+
+
+def stable_order(keys):
+    return np.argsort(keys, kind="stable")
+
+
+def canonical_nodes(nodes):
+    rows = [(int(v["begin"]), int(v["end"]), int(v["first_boundary"]), int(v["arity"]),
+             int(v["power"]), int(v["depth"])) for v in nodes]
+    return sorted(rows)
+
+
+def check_tree_invariants(tr, k):
+    """Section 3 invariants on one oracle trace."""
+    r, n = tr.r, tr.n
+    rs = tr.run_start.astype(np.int64)
+    L = np.diff(rs)
+    nodes = tr.nodes
+    assert len(nodes) == (r - 1 if r >= 1 else 0) or k > 2
+    # Algorithm 1 builds the same tree (stated right after Algorithm 1).
+    alg1 = oracle.kway_tree(tr.run_start, tr.power)
+    assert canonical_nodes(alg1) == canonical_nodes(nodes)
+    if r <= 1:
+        assert tr.merge_cost == 0
+        return
+    depth = nodes["depth"].astype(np.int64)
+    bnode = tr.boundary_node.astype(np.int64)
+    P = tr.power.astype(np.int64)
+    # every node merges 2..k runs; all its boundaries carry its power
+    assert np.all(nodes["arity"] >= 2) and np.all(nodes["arity"] <= k)
+    assert np.all(nodes["power"][bnode] == P)
+    counts = np.bincount(bnode, minlength=len(nodes))
+    assert np.all(counts == nodes["arity"] - 1)
+    # Fact 3.2: depth(m(B_j)) <= P_j - 1
+    assert np.all(depth[bnode] <= P - 1)
+    # leaf depth d_i = 1 + max(depth m(B_i), depth m(B_{i+1})), outer terms -1
+    bd = np.concatenate([[-1], depth[bnode], [-1]])
+    assert np.array_equal(tr.leaf_depth.astype(np.int64), 1 + np.maximum(bd[:-1], bd[1:]))
+    # merge cost: sum over nodes of merged lengths = sum_i d_i L_i
+    spans = (nodes["end"] - nodes["begin"]).astype(np.int64)
+    assert tr.merge_cost == int(spans.sum()) == int((tr.leaf_depth.astype(np.int64) * L).sum())
+    # powers: 1 <= P_i and P_i, P_{i+1} <= ceil(log_k(1/l_i) + 1) (proof of Thm 3.3)
+    assert np.all(P >= 1)
+    for i in range(r):
+        bound = ceil_log_plus1(k, n, int(L[i]))
+        if i >= 1:
+            assert P[i - 1] <= bound
+        if i + 1 <= r - 1:
+            assert P[i] <= bound
+    # Theorem 3.3 (sharper form from its proof): M/n <= sum l_i ceil(log_k(1/l_i) + 1)
+    rhs = sum(int(Li) * ceil_log_plus1(k, n, int(Li)) for Li in L)
+    assert tr.merge_cost <= rhs
+    H = float(sum((Li / n) * math.log2(n / Li) for Li in L))
+    assert tr.merge_cost <= H * n / math.log2(k) + 2 * n + 1e-6
+    # Proposition 3.5: stack height <= (k-1) * ceil(log_k n + 1)
+    assert tr.max_stack <= (k - 1) * ceil_log_plus1(k, n)
+
+
+def lt(a, b):
+    """Elementwise a < b in the key order (float32: numeric, with -0 < +0)."""
+    if a.dtype == np.float32:
+        return (a < b) | ((a == b) & np.signbit(a) & ~np.signbit(b))
+    return a < b
+
+
+def check_runs(keys, rs, rd):
+    n = keys.size
+    rs = rs.astype(np.int64)
+    assert rs[0] == 0 and rs[-1] == n
+    r = rs.size - 1
+    for i in range(r):
+        s, e = rs[i], rs[i + 1]
+        assert e > s
+        seg = keys[s:e]
+        if e - s >= 2:
+            if rd[i]:
+                assert np.all(lt(seg[1:], seg[:-1]))
+            else:
+                assert not np.any(lt(seg[1:], seg[:-1]))
+        else:
+            assert i == r - 1 and rd[i] == 0     # only the last run can be a single element
+        if e < n:                                # maximal: the next element breaks the run
+            if rd[i]:
+                assert not lt(keys[e:e + 1], keys[e - 1:e])[0]
+            else:
+                assert lt(keys[e:e + 1], keys[e - 1:e])[0]
+
+
+def weak_orderings(n):
+    """Every sequence of length n over {0..m-1} that uses all m values: one
+    representative of every possible pattern of ties and order."""
+    if n == 0:
+        return np.zeros((1, 0), dtype=np.int32)
+    grid = np.array(list(itertools.product(range(n), repeat=n)), dtype=np.int8)
+    srt = np.sort(grid, axis=1)
+    ok = (srt[:, 0] == 0) & np.all(np.diff(srt, axis=1) <= 1, axis=1)
+    return grid[ok].astype(np.int32)
+
+
+FUBINI = [1, 1, 3, 13, 75, 541, 4683, 47293]
+
+
+# ---------------------------------------------------------------- paper pins
+
+def test_fig1_powers(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "fig1.json")))
+    rs = starts_from_lengths(g["run_lengths"])
+    assert int(rs[-1]) == g["n"]
+    assert oracle.powers(rs, 2).tolist() == g["power_k2"]
+    assert oracle.powers(rs, 4).tolist() == g["power_k4"]
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_fig1_trees(golden_dir, k):
+    g = json.load(open(os.path.join(golden_dir, "fig1.json")))
+    rs = starts_from_lengths(g["run_lengths"])
+    tr = oracle.tree_from_runs(rs, k)
+    spans = sorted((int(v["begin"]), int(v["end"])) for v in tr.nodes)
+    want = sorted(tuple(s) for s in g[f"tree_k{k}_spans"])
+    assert spans == want
+    # merge cost is the total length of all merge results (Section 2.3)
+    assert tr.merge_cost == sum(e - b for b, e in want)
+    check_tree_invariants(tr, k)
+
+
+def test_fig3_power(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "fig3.json")))
+    # runs [8,10) and [10,28) of an array of length 40 have midpoints 9/40 and 19/40
+    n, s = 40, (8, 10, 28)
+    assert Fraction(s[0] + s[1], 2 * n) == Fraction(g["a"])
+    assert Fraction(s[1] + s[2], 2 * n) == Fraction(g["b"])
+    assert oracle.power(n, *s, g["k"]) == g["power"]
+
+
+def test_half_open_interval():
+    # a tick exactly at b counts: (1/8, 1/2] contains 1/2 -> P = 1 for k = 2 and 4
+    assert oracle.power(8, 0, 2, 6, 2) == 1
+    assert oracle.power(8, 0, 2, 6, 4) == 1
+    # a tick exactly at a does not: (1/2, 3/4] needs p = 2 for k = 2 (tick 3/4)
+    assert oracle.power(16, 6, 10, 14, 2) == 2
+    # invalid partitions are rejected
+    assert oracle.power(16, 6, 6, 14, 2) == -1
+    assert oracle.power(16, 6, 10, 17, 2) == -1
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 8, 16])
+def test_power_matches_tick_form(k):
+    rng = np.random.default_rng(100 + k)
+    for _ in range(300):
+        n = int(rng.integers(3, 10 ** int(rng.integers(1, 7))))
+        cuts = np.sort(rng.choice(np.arange(1, n), size=2, replace=False))
+        s_prev = int(rng.integers(0, cuts[0]))
+        s = (s_prev, int(cuts[0]), int(cuts[1]))
+        assert oracle.power(n, *s, k) == tick_power(n, *s, k)
+
+
+def test_power_extremes():
+    n = 2 ** 31
+    for s in [(0, 1, 2), (n - 3, n - 2, n - 1), (n - 2, n - 1, n), (0, n // 2, n), (0, 1, n)]:
+        for k in (2, 4, 8):
+            assert oracle.power(n, *s, k) == tick_power(n, *s, k)
+
+
+def test_squish_identity():
+    """Section 3.1: P^(4) = floor((P^(2)-1)/2) + 1; generalised to k = 2^q."""
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        n = int(rng.integers(2, 200000))
+        lengths = workloads._run_lengths(rng, n, lambda g, c: g.integers(1, 1 + int(rng.integers(1, 5000)), size=c))
+        rs = starts_from_lengths(lengths)
+        p2 = oracle.powers(rs, 2).astype(np.int64)
+        for q, k in [(2, 4), (3, 8), (4, 16)]:
+            assert np.array_equal(oracle.powers(rs, k).astype(np.int64), (p2 - 1) // q + 1)
+
+
+def test_merge_cost_ratio_table1(golden_dir):
+    """Hypothesis 3 / Table 1: 4-way merge cost is about 52% of 2-way on random runs.
+    Different random inputs and no minimal run length here, so only a loose band."""
+    g = json.load(open(os.path.join(golden_dir, "table1.json")))
+    paper_ratio = g["merge_cost_k4"] / g["merge_cost_k2"]
+    assert 0.51 < paper_ratio < 0.53
+    keys, _ = workloads.runs_i64(n=1 << 20, seed=11)
+    rs, _ = oracle.runs(keys)
+    m2 = oracle.tree_from_runs(rs, 2).merge_cost
+    m4 = oracle.tree_from_runs(rs, 4).merge_cost
+    assert abs(m4 / m2 - paper_ratio) < 0.08
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("n", range(0, 9))
+def test_bruteforce_sort_all_tie_patterns(n):
+    """Every tie/order pattern of length n (Fubini many): the output is the
+    unique stable sort (library stable argsort), for several k."""
+    rows = weak_orderings(n)
+    if n <= 7:
+        assert rows.shape[0] == FUBINI[n]
+    m = rows.shape[0]
+    flat = rows.reshape(-1)
+    offsets = (np.arange(m + 1, dtype=np.uint64) * n)
+    local = np.tile(np.arange(n, dtype=np.uint32), m)
+    want_perm = np.argsort(rows, axis=1, kind="stable").astype(np.uint32)
+    want_keys = np.take_along_axis(rows, want_perm.astype(np.int64), axis=1)
+    for k in (2, 3, 4):
+        sk, sp, _ = oracle.sort_many(flat, local, offsets, k=k)
+        assert np.array_equal(sk.reshape(m, n), want_keys)
+        assert np.array_equal(sp.reshape(m, n), want_perm)
+    # the same patterns as int64 and float32 keys (spread over negative values)
+    for dt, scale in ((np.int64, -(2 ** 40)), (np.float32, -1.5)):
+        vals = (rows.astype(np.float64) * scale).astype(dt)
+        sk, sp, _ = oracle.sort_many(vals.reshape(-1), local, offsets, k=4)
+        wp = np.argsort(vals, axis=1, kind="stable").astype(np.uint32)
+        assert np.array_equal(sp.reshape(m, n), wp)
+
+
+@pytest.mark.parametrize("n", range(0, 8))
+def test_bruteforce_runs_all_tie_patterns(n):
+    for row in weak_orderings(n):
+        rs, rd = oracle.runs(row)
+        check_runs(row, rs, rd)
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_bruteforce_tree_all_tie_patterns(n, k):
+    for row in weak_orderings(n):
+        sk, sp, tr = oracle.sort(row, np.arange(n, dtype=np.uint32), k=k)
+        assert np.array_equal(sp, stable_order(row))
+        check_runs(row, tr.run_start, tr.run_desc)
+        check_tree_invariants(tr, k)
+
+
+def test_all_run_length_compositions():
+    """Every composition of n <= 12 into run lengths: Algorithm 1 = Algorithm 2
+    and all Section 3 invariants, for k = 2..5 and 8."""
+    for n in range(1, 13):
+        for mask in range(1 << (n - 1)):
+            cuts = [i + 1 for i in range(n - 1) if mask >> i & 1]
+            rs = np.array([0] + cuts + [n], dtype=np.uint64)
+            for k in (2, 3, 4, 5, 8):
+                check_tree_invariants(oracle.tree_from_runs(rs, k), k)
+
+
+# ---------------------------------------------------------------- at scale
+
+@pytest.mark.parametrize("name,n", [("runs_i32", 1 << 18), ("runs_i64", 1 << 18),
+                                    ("perm_i64", 1 << 16), ("ties_i32", 1 << 18)])
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_matches_library_stable_sort(name, n, k):
+    keys, pay = workloads.WORKLOADS[name](n=n)
+    sk, sp, tr = oracle.sort(keys, pay, k=k)
+    order = stable_order(keys)
+    assert np.array_equal(sp, pay[order])
+    assert np.array_equal(sk, keys[order])
+    if k == 4:
+        check_runs(keys, tr.run_start, tr.run_desc)
+        check_tree_invariants(tr, k)
+
+
+def test_permutation_exact():
+    keys, pay = workloads.perm_i64(n=1 << 17, seed=5)
+    sk, sp, _ = oracle.sort(keys, pay, k=4)
+    assert np.array_equal(sk, np.arange(keys.size, dtype=np.int64))
+    inv = np.empty_like(pay)
+    inv[keys] = pay
+    assert np.array_equal(sp, inv)
+
+
+def test_float_total_order():
+    rng = np.random.default_rng(3)
+    specials = np.array([0.0, -0.0, np.inf, -np.inf, 1e-45, -1e-45, 3.4e38, -3.4e38,
+                         1.0, -1.0], dtype=np.float32)
+    vals = np.concatenate([specials, rng.standard_normal(3000).astype(np.float32),
+                           rng.choice(specials, 500)])
+    rng.shuffle(vals)
+    pay = np.arange(vals.size, dtype=np.uint32)
+    sk, sp, _ = oracle.sort(vals, pay, k=4)
+    # numeric order; among equal numbers (only +-0 differ in bits) -0 first; then index
+    neg_bit = np.signbit(vals)
+    want = np.lexsort((pay, ~neg_bit, vals.astype(np.float64)))
+    assert np.array_equal(sp, pay[want])
+    assert np.array_equal(sk.view(np.uint32), vals[want].view(np.uint32))
+
+
+def test_segments_sort_independently():
+    keys, pay, off = workloads.batch_i32(m=40, seed=9, lo_exp=1, hi_exp=12)
+    sk, sp, mc = oracle.sort_many(keys, pay, off, k=4)
+    for i in range(40):
+        s, e = int(off[i]), int(off[i + 1])
+        k1, p1, t1 = oracle.sort(keys[s:e], pay[s:e], k=4)
+        assert np.array_equal(sk[s:e], k1) and np.array_equal(sp[s:e], p1)
+        assert mc[i] == t1.merge_cost
+
+
+# ---------------------------------------------------------------- edge cases
+
+I32 = np.iinfo(np.int32)
+I64 = np.iinfo(np.int64)
+
+EDGE = {
+    "empty": np.zeros(0, np.int32),
+    "one": np.array([5], np.int32),
+    "two_up": np.array([1, 2], np.int32),
+    "two_down": np.array([2, 1], np.int32),
+    "two_eq": np.array([3, 3], np.int32),
+    "all_equal": np.full(1000, 7, np.int32),
+    "ascending": np.arange(1000, dtype=np.int32),
+    "strict_desc": np.arange(1000, 0, -1, dtype=np.int32),
+    "zigzag": np.tile(np.array([1, 0], np.int32), 500),
+    "zigzag_odd": np.concatenate([np.tile(np.array([1, 0], np.int32), 500), [1]]).astype(np.int32),
+    "extremes": np.array([I32.max, I32.min, I32.max, I32.min, 0, I32.min, I32.max], np.int32),
+    "i64_range": np.array([I64.max, I64.min, -1, 0, I64.max, I64.min, 1], np.int64),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+@pytest.mark.parametrize("k", [2, 4])
+def test_edge_cases(name, k):
+    keys = EDGE[name]
+    pay = np.arange(keys.size, dtype=np.uint32)
+    sk, sp, tr = oracle.sort(keys, pay, k=k)
+    assert np.array_equal(sp, stable_order(keys))
+    check_runs(keys, tr.run_start, tr.run_desc)
+    check_tree_invariants(tr, k)
+    if name == "strict_desc":
+        assert tr.r == 1 and tr.run_desc[0] == 1
+    if name == "zigzag":
+        assert tr.r == keys.size // 2 and np.all(tr.run_desc == 1)
+    if name in ("all_equal", "ascending"):
+        assert tr.r == 1 and tr.merge_cost == 0
