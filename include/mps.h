@@ -1,0 +1,127 @@
+/*
+ * mps.h -- C ABI of libmps, a gfx950 (MI355X) implementation of multiway
+ * Powersort (Cawley Gelling, Nebel, Smith, Wild, "Multiway Powersort",
+ * arXiv 2209.06909).
+ *
+ * What the library computes is the paper's problem statement (Section 1 and
+ * Section 2): stably sort an array by first finding its existing runs
+ * (maximal weakly increasing or strictly decreasing segments; decreasing
+ * runs are reversed), giving every run boundary its k-way node power
+ * (Definition 3.1), and merging the runs k-way along the merge tree those
+ * powers define (Algorithm 1; Algorithm 2 builds the same tree).  The result
+ * is the unique stable sort: equal keys keep their input order.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named keys / payload / offsets are DEVICE pointers (memory of
+ *    the current HIP device); trace buffers are HOST pointers.
+ *  - The caller owns keys, payload and offsets; they are sorted in place and
+ *    must stay valid until the work enqueued on `stream` has finished.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls only enqueue work unless a trace is requested (then they wait).
+ *  - Keys are int32, int64 or float32.  float32 keys are ordered by the
+ *    IEEE-754 total order (-0 before +0, NaNs by bit pattern).  The payload
+ *    is an optional uint32 per key that moves with its key (NULL: keys only).
+ *  - Errors are returned as negative mps_status codes before any work is
+ *    enqueued; mps_last_error() gives a message for the calling thread.
+ *    Device faults surface at the caller's next synchronisation.
+ */
+#ifndef MPS_H
+#define MPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPS_OK = 0,
+    MPS_PENDING = 1,          /* serving: request not finished yet */
+    MPS_E_INVALID = -1,       /* bad argument (NULL pointer with n > 0, bad offsets, ...) */
+    MPS_E_NOMEM = -2,         /* workspace too small / allocation failed / over budget */
+    MPS_E_HIP = -3,           /* a HIP runtime call failed */
+    MPS_E_UNSUPPORTED = -4,   /* k not in {2,4,8}, an array longer than 2^31, ... */
+    MPS_E_NOTFOUND = -5,      /* serving: unknown request id */
+    MPS_E_DEVICE = -6         /* a device-side consistency check failed */
+} mps_status;
+
+typedef enum { MPS_I32 = 0, MPS_I64 = 1, MPS_F32 = 2 } mps_key_type;
+
+/* Options.  All fields may be zero for defaults. */
+typedef struct {
+    uint32_t k;                 /* merge arity: 2, 4 (default, the paper's 4-way) or 8 */
+    uint32_t reserved;
+    void *workspace;            /* device memory of >= mps_workspace_bytes(); NULL: the
+                                   library allocates and caches one per device */
+    uint64_t workspace_bytes;
+} mps_opts;
+
+/* What the sort did (filled when a trace pointer is passed; forces a stream
+ * synchronisation).  Counters are always filled; each array is filled only
+ * if the caller supplies it (host memory, room for r_cap runs / nodes;
+ * MPS_E_NOMEM if r_cap is too small). */
+typedef struct {
+    uint64_t r;                 /* runs found (Section 2) */
+    uint64_t n_nodes;           /* internal merge-tree nodes */
+    uint64_t merge_cost;        /* sum of all merge output sizes (Section 2.3) */
+    uint32_t n_levels;          /* 1 + depth of the deepest internal node */
+    uint32_t k;                 /* arity used */
+    uint64_t r_cap;             /* capacity of the arrays below, in runs */
+    uint64_t *run_start;        /* [r+1] first position of every run, run_start[r] = n */
+    uint8_t *run_desc;          /* [r] 1 if the run was strictly decreasing */
+    uint8_t *power;             /* [r-1] power[i-1] = P_i of the boundary starting run i
+                                   (0 where a boundary is also an array edge in a batch) */
+    uint8_t *leaf_depth;        /* [r] depth of every run in the merge tree */
+    uint64_t *node_begin;       /* [n_nodes] element span of every node ... */
+    uint64_t *node_end;         /*            ... in order of their leftmost boundary */
+    uint32_t *node_first;       /* [n_nodes] leftmost boundary index of the node */
+    uint8_t *node_arity;        /* [n_nodes] number of children (2..k) */
+    uint8_t *node_power;        /* [n_nodes] common power of the node's boundaries */
+    uint8_t *node_depth;        /* [n_nodes] depth (root = 0) */
+} mps_trace;
+
+/* Bytes of device workspace needed to sort n elements in m arrays with the
+ * given key type, payload presence and arity.  Returns 0 on bad arguments. */
+uint64_t mps_workspace_bytes(uint64_t n, uint64_t m, mps_key_type kt, int has_payload,
+                             uint32_t k);
+
+/* Stable multiway Powersort of one array of n keys (and payloads) in place:
+ * run detection and reversal (Section 2), node powers (Definition 3.1),
+ * merge tree (Algorithm 1), k-way merges along the tree.  n <= 1 is a no-op;
+ * n > 2^31 gives MPS_E_UNSUPPORTED; keys == NULL with n > 0 gives
+ * MPS_E_INVALID. */
+int mps_sort(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n, void *stream);
+int mps_sort_i32(int32_t *keys, uint32_t *payload, uint64_t n, void *stream);
+int mps_sort_i64(int64_t *keys, uint32_t *payload, uint64_t n, void *stream);
+int mps_sort_f32(float *keys, uint32_t *payload, uint64_t n, void *stream);
+
+/* mps_sort with options and an optional trace (trace may be NULL). */
+int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
+                const mps_opts *opts, mps_trace *trace, void *stream);
+
+/* Batched: m independent arrays packed back to back, array i occupying
+ * [offsets[i], offsets[i+1]) of keys/payload (offsets: device uint64[m+1],
+ * offsets[0] = 0, non-decreasing, offsets[m] = total_n; empty arrays are
+ * allowed).  Every array is sorted on its own, exactly as mps_sort would sort
+ * it alone: runs never cross an array edge and every power is normalised by
+ * its own array's length (Definition 3.1).  All arrays go through one shared
+ * sequence of launches, one per tree level.  h_offsets (host copy, nullable)
+ * is used only to validate; each array must hold at most 2^31 keys. */
+int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload, const uint64_t *offsets,
+                     const uint64_t *h_offsets, uint64_t m, uint64_t total_n,
+                     const mps_opts *opts, mps_trace *trace, void *stream);
+
+/* Fills trace (counters and every array the caller supplies) from the most
+ * recent sort that used `workspace` (the opts->workspace pointer of that
+ * call; NULL: the library-managed workspace of the current device).  Lets a
+ * caller learn r and n_nodes first and size the host arrays afterwards.
+ * Synchronises the device.  MPS_E_NOTFOUND if no such sort exists. */
+int mps_trace_fetch(const void *workspace, mps_trace *trace);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char *mps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,274 @@
+"""Python binding of libmps, the gfx950 multiway-Powersort library.
+
+Argument marshalling only: every step of the sort runs in the HIP kernels of
+``_lib/libmps.so`` behind the C ABI declared in ``include/mps.h``.  PyTorch
+supplies device memory (the workspace is a torch tensor) and the stream.
+There is no CPU fallback: if the library is not built, or no GPU is present,
+the calls raise.
+
+    import torch, paper_2209_06909_amd as mps
+    keys = torch.tensor([...], dtype=torch.int64, device="cuda")
+    idx = torch.arange(keys.numel(), dtype=torch.int32, device="cuda")
+    mps.sort(keys, idx)                 # stable, in place; idx becomes the permutation
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmps.so")
+
+MPS_OK, MPS_PENDING = 0, 1
+_STATUS = {-1: "MPS_E_INVALID", -2: "MPS_E_NOMEM", -3: "MPS_E_HIP", -4: "MPS_E_UNSUPPORTED",
+           -5: "MPS_E_NOTFOUND", -6: "MPS_E_DEVICE"}
+KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
+
+EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
+            "mps_sort_ex", "mps_sort_batched", "mps_trace_fetch", "mps_last_error"]
+
+
+class MpsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class _Trace(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_uint64), ("n_nodes", ctypes.c_uint64),
+                ("merge_cost", ctypes.c_uint64), ("n_levels", ctypes.c_uint32),
+                ("k", ctypes.c_uint32), ("r_cap", ctypes.c_uint64),
+                ("run_start", ctypes.c_void_p), ("run_desc", ctypes.c_void_p),
+                ("power", ctypes.c_void_p), ("leaf_depth", ctypes.c_void_p),
+                ("node_begin", ctypes.c_void_p), ("node_end", ctypes.c_void_p),
+                ("node_first", ctypes.c_void_p), ("node_arity", ctypes.c_void_p),
+                ("node_power", ctypes.c_void_p), ("node_depth", ctypes.c_void_p)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmps.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing; build it with "
+                                  "`python -m paper_2209_06909_amd.build`")
+            l = ctypes.CDLL(LIB_PATH)
+            P, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+            l.mps_workspace_bytes.argtypes = [u64, u64, i32, i32, u32]
+            l.mps_workspace_bytes.restype = u64
+            l.mps_sort.argtypes = [P, i32, P, u64, P]
+            l.mps_sort.restype = i32
+            for name in ("mps_sort_i32", "mps_sort_i64", "mps_sort_f32"):
+                getattr(l, name).argtypes = [P, P, u64, P]
+                getattr(l, name).restype = i32
+            l.mps_sort_ex.argtypes = [P, i32, P, u64, ctypes.POINTER(_Opts), ctypes.POINTER(_Trace), P]
+            l.mps_sort_ex.restype = i32
+            l.mps_sort_batched.argtypes = [P, i32, P, P, P, u64, u64, ctypes.POINTER(_Opts),
+                                           ctypes.POINTER(_Trace), P]
+            l.mps_sort_batched.restype = i32
+            l.mps_trace_fetch.argtypes = [P, ctypes.POINTER(_Trace)]
+            l.mps_trace_fetch.restype = i32
+            l.mps_last_error.argtypes = []
+            l.mps_last_error.restype = ctypes.c_char_p
+            _lib = l
+        return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise MpsError(rc, lib().mps_last_error().decode())
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def key_type_of(t) -> int:
+    torch = _torch()
+    kt = {torch.int32: KEY_I32, torch.int64: KEY_I64, torch.float32: KEY_F32}.get(t.dtype)
+    if kt is None:
+        raise TypeError(f"unsupported key dtype {t.dtype} (int32, int64, float32)")
+    return kt
+
+
+def workspace_bytes(n: int, m: int = 1, key_type: int = KEY_I32, has_payload: bool = True,
+                    k: int = 4) -> int:
+    return int(lib().mps_workspace_bytes(n, m, key_type, int(has_payload), k))
+
+
+_ws = {}
+_ws_lock = threading.Lock()
+
+
+def _workspace(device, nbytes: int):
+    """A cached torch uint8 buffer of at least nbytes on `device`."""
+    torch = _torch()
+    key = (device.type, device.index)
+    with _ws_lock:
+        buf = _ws.get(key)
+        if buf is None or buf.numel() < nbytes:
+            _ws.pop(key, None)
+            buf = torch.empty(int(nbytes * 1.05) + 4096, dtype=torch.uint8, device=device)
+            _ws[key] = buf
+        return buf
+
+
+def _check_tensors(keys, payload):
+    torch = _torch()
+    if not keys.is_cuda:
+        raise ValueError("keys must be a GPU tensor")
+    if not keys.is_contiguous():
+        raise ValueError("keys must be contiguous")
+    if payload is not None:
+        if payload.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("payload must be int32 or uint32 (4 bytes per key)")
+        if payload.device != keys.device or not payload.is_contiguous():
+            raise ValueError("payload must be contiguous and on the keys' device")
+        if payload.numel() != keys.numel():
+            raise ValueError("payload and keys differ in length")
+
+
+@dataclass
+class Trace:
+    """Runs, powers and merge-tree nodes of one sort (host numpy arrays)."""
+    r: int
+    n_nodes: int
+    merge_cost: int
+    n_levels: int
+    k: int
+    run_start: np.ndarray | None = None    # uint64[r+1]
+    run_desc: np.ndarray | None = None     # uint8[r]
+    power: np.ndarray | None = None        # uint8[r-1]
+    leaf_depth: np.ndarray | None = None   # uint8[r]
+    node_begin: np.ndarray | None = None   # uint64[n_nodes], ordered by first boundary
+    node_end: np.ndarray | None = None
+    node_first: np.ndarray | None = None   # uint32
+    node_arity: np.ndarray | None = None   # uint8
+    node_power: np.ndarray | None = None   # uint8
+    node_depth: np.ndarray | None = None   # uint8
+
+
+def _fetch_trace(ws_ptr, t: _Trace, arrays: bool) -> Trace:
+    tr = Trace(r=int(t.r), n_nodes=int(t.n_nodes), merge_cost=int(t.merge_cost),
+               n_levels=int(t.n_levels), k=int(t.k))
+    if not arrays:
+        return tr
+    r, nn = tr.r, tr.n_nodes
+    cap = max(r + 1, nn, 1)
+    bufs = dict(run_start=np.zeros(cap, np.uint64), run_desc=np.zeros(cap, np.uint8),
+                power=np.zeros(cap, np.uint8), leaf_depth=np.zeros(cap, np.uint8),
+                node_begin=np.zeros(cap, np.uint64), node_end=np.zeros(cap, np.uint64),
+                node_first=np.zeros(cap, np.uint32), node_arity=np.zeros(cap, np.uint8),
+                node_power=np.zeros(cap, np.uint8), node_depth=np.zeros(cap, np.uint8))
+    t2 = _Trace()
+    t2.r_cap = cap
+    for name, a in bufs.items():
+        setattr(t2, name, a.ctypes.data)
+    _check(lib().mps_trace_fetch(ws_ptr, ctypes.byref(t2)))
+    tr.run_start = bufs["run_start"][: r + 1]
+    tr.run_desc = bufs["run_desc"][:r]
+    tr.power = bufs["power"][: max(r - 1, 0)]
+    tr.leaf_depth = bufs["leaf_depth"][:r]
+    for name in ("node_begin", "node_end", "node_first", "node_arity", "node_power", "node_depth"):
+        setattr(tr, name, bufs[name][:nn])
+    return tr
+
+
+def _stream_ptr(device, stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
+         stream=None):
+    """Stable multiway Powersort of a 1-D GPU tensor, in place.
+
+    keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
+    payload: optional int32/uint32 tensor of the same length, permuted with the keys.
+    trace: if True, synchronise and return a Trace (runs, powers, nodes, merge cost).
+    """
+    _check_tensors(keys, payload)
+    kt = key_type_of(keys)
+    n = keys.numel()
+    dev = keys.device
+    need = workspace_bytes(max(n, 2), 1, kt, payload is not None, k)
+    if need == 0:
+        raise MpsError(-4, f"unsupported arity k={k}")
+    ws = _workspace(dev, need)
+    opts = _Opts(k=k, reserved=0, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
+    t = _Trace() if trace else None
+    _check(lib().mps_sort_ex(ctypes.c_void_p(keys.data_ptr()), kt,
+                             ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
+                             n, ctypes.byref(opts), ctypes.byref(t) if t is not None else None,
+                             _stream_ptr(dev, stream)))
+    if t is None:
+        return None
+    if n <= 1:
+        tr = Trace(r=n, n_nodes=0, merge_cost=0, n_levels=0, k=k)
+        if trace_arrays:
+            tr.run_start = np.array([0, 1] if n else [0], np.uint64)
+            tr.run_desc = np.zeros(n, np.uint8)
+            tr.power = np.zeros(0, np.uint8)
+            tr.leaf_depth = np.zeros(n, np.uint8)
+            for name in ("node_begin", "node_end"):
+                setattr(tr, name, np.zeros(0, np.uint64))
+            tr.node_first = np.zeros(0, np.uint32)
+            for name in ("node_arity", "node_power", "node_depth"):
+                setattr(tr, name, np.zeros(0, np.uint8))
+        return tr
+    return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)
+
+
+def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
+                 trace_arrays: bool = True, stream=None, host_offsets=None):
+    """Sort m independent arrays packed back to back in `keys` (and `payload`).
+
+    offsets: GPU int64/uint64 tensor of m+1 entries (offsets[0] = 0, offsets[m] = len(keys)).
+    Every array is sorted exactly as sort() would sort it alone.
+    """
+    torch = _torch()
+    _check_tensors(keys, payload)
+    if offsets.dtype not in (torch.int64, torch.uint64) or not offsets.is_contiguous():
+        raise TypeError("offsets must be a contiguous int64/uint64 tensor")
+    if offsets.device != keys.device:
+        raise ValueError("offsets must be on the keys' device")
+    kt = key_type_of(keys)
+    m = offsets.numel() - 1
+    n = keys.numel()
+    dev = keys.device
+    hoff = None
+    if host_offsets is not None:
+        hoff = np.ascontiguousarray(host_offsets, dtype=np.uint64)
+    need = workspace_bytes(max(n, 2), max(m, 1), kt, payload is not None, k)
+    if need == 0:
+        raise MpsError(-4, f"unsupported arity k={k}")
+    ws = _workspace(dev, need)
+    opts = _Opts(k=k, reserved=0, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
+    t = _Trace() if trace else None
+    _check(lib().mps_sort_batched(
+        ctypes.c_void_p(keys.data_ptr()), kt,
+        ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
+        ctypes.c_void_p(offsets.data_ptr()),
+        hoff.ctypes.data_as(ctypes.c_void_p) if hoff is not None else None,
+        max(m, 0), n, ctypes.byref(opts), ctypes.byref(t) if t is not None else None,
+        _stream_ptr(dev, stream)))
+    if t is None:
+        return None
+    return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)

@@ -1,0 +1,427 @@
+// mps_api.hip -- host planner and C ABI of libmps.
+//
+// A sort is a fixed sequence of launches on one stream; every data-dependent
+// quantity (run count, node counts per level, tiles per level) lives in the
+// device-resident Plan and is read by the kernels themselves, so a sort
+// enqueues without any host synchronisation (and can be captured in a HIP
+// graph).  Levels are launched for every depth the powers allow; levels
+// deeper than the actual tree find zero tiles and return at once.
+#include <mutex>
+#include <string>
+#include <vector>
+#include <map>
+#include <cstring>
+
+#include "mps.h"
+#include "mps_internal.h"
+
+namespace mps {
+
+// Zero the plan and (for single-array calls) write the 2-entry offsets.
+__global__ void k_init(Plan *plan, uint64_t *seg_off, uint64_t n, uint64_t m, uint32_t kt,
+                       uint32_t has_payload, uint32_t k, int single) {
+  uint64_t *p = reinterpret_cast<uint64_t *>(plan);
+  for (size_t i = threadIdx.x; i < sizeof(Plan) / 8; i += blockDim.x) p[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    plan->n = n;
+    plan->m = m;
+    plan->kt = kt;
+    plan->has_payload = has_payload;
+    plan->k = k;
+    if (single) {
+      seg_off[0] = 0;
+      seg_off[1] = n;
+    }
+  }
+}
+
+__global__ void k_check_offsets(const uint64_t *off, uint64_t m, uint64_t total, Plan *plan) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t a = off[i], b = off[i + 1];
+    bool bad = b < a || (b - a) > (1ull << 31) || (i == 0 && a != 0) || (i + 1 == m && b != total);
+    if (bad) atomicOr(&plan->error, 2u);
+  }
+}
+
+}  // namespace mps
+
+using namespace mps;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return fail(MPS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+extern "C" const char *mps_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------- layout
+namespace {
+
+struct Layout {
+  size_t total = 0;
+  size_t alt_keys, alt_vals, seg_off, dbits, det_agg, det_zin, det_off, run_start, run_desc,
+      power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
+      dist0, dist1, leaf_depth, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_base,
+      tj, plan;
+  uint64_t rmax, nbb, tiles_max, tj_cap;
+  int levels;
+};
+
+size_t take(size_t &cur, size_t bytes) {
+  size_t at = (cur + 255) & ~(size_t)255;
+  cur = at + bytes;
+  return at;
+}
+
+int levels_for(uint64_t n, uint32_t k) {
+  // every power satisfies k^(P-1) < 2n, so depths are < P <= this bound
+  int p = 0;
+  unsigned __int128 v = 1;
+  while (v < (unsigned __int128)2 * n) {
+    v *= k;
+    p++;
+  }
+  return p < 1 ? 1 : p;
+}
+
+bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layout &L) {
+  if (N == 0 || m == 0) return false;
+  size_t ks = kt == MPS_I64 ? 8 : 4;
+  uint64_t rmax = N / 2 + m + 2;
+  if (rmax > N + 1) rmax = N + 1;
+  uint64_t nwords = (N + 63) / 64;
+  uint64_t nblk = (N + 16383) / 16384;
+  uint64_t nbb = (rmax + 1 + 1023) / 1024 + 1;
+  uint64_t tiles_max = N / kTileSize + 2;
+  int levels = levels_for(N, k);
+  if (levels >= kMaxLevels) return false;
+  size_t c = 0;
+  L.plan = take(c, sizeof(Plan));    // first: a later trace fetch finds it at the base
+  L.alt_keys = take(c, N * ks);
+  L.alt_vals = take(c, payload ? N * 4 : 0);
+  L.seg_off = take(c, 16);
+  L.dbits = take(c, nwords * 8 + 8);
+  L.det_agg = take(c, nblk * sizeof(DetAgg));
+  L.det_zin = take(c, nblk * 8);
+  L.det_off = take(c, nblk * 8);
+  L.run_start = take(c, (rmax + 1) * 8);
+  L.run_desc = take(c, rmax);
+  L.power = take(c, rmax + 1);
+  L.ansv_bl = take(c, nbb * kVMax * 4);
+  L.ansv_bf = take(c, nbb * kVMax * 4);
+  L.ansv_cl = take(c, nbb * kVMax * 4);
+  L.ansv_cr = take(c, nbb * kVMax * 4);
+  L.Ls = take(c, (rmax + 1) * 4);
+  L.Rs = take(c, (rmax + 1) * 4);
+  L.Le = take(c, (rmax + 1) * 4);
+  L.Re = take(c, (rmax + 1) * 4);
+  L.nd_arity = take(c, rmax + 1);
+  L.nd_mem = take(c, (rmax + 1) * (k - 1) * 4);
+  L.jump0 = take(c, (rmax + 1) * 4);
+  L.jump1 = take(c, (rmax + 1) * 4);
+  L.dist0 = take(c, rmax + 1);
+  L.dist1 = take(c, rmax + 1);
+  L.leaf_depth = take(c, rmax);
+  L.lvl_cnt = take(c, nbb * kMaxLevels * 4);
+  L.lvl_tot = take(c, kMaxLevels * 8);
+  L.lvl_list = take(c, rmax * 4);
+  L.lvl_np = take(c, (rmax + 2) * 8);
+  L.scan_tmp = take(c, (rmax / 1024 + 2) * 8);
+  L.corank = take(c, tiles_max * k * 4);
+  L.tile_base = take(c, (kMaxLevels + 1) * 8);
+  L.tj_cap = (tiles_max + 1) * (uint64_t)levels + 64;
+  L.tj = take(c, L.tj_cap * 4);
+  L.total = c + 256;
+  L.rmax = rmax;
+  L.nbb = nbb;
+  L.tiles_max = tiles_max;
+  L.levels = levels;
+  return true;
+}
+
+int check_k(uint32_t &k) {
+  if (k == 0) k = 4;
+  if (k != 2 && k != 4 && k != 8)
+    return fail(MPS_E_UNSUPPORTED, "k must be 2, 4 or 8");
+  return MPS_OK;
+}
+
+// Library-managed workspace, one per device, grown on demand.
+std::mutex g_ws_mu;
+std::map<int, std::pair<void *, size_t>> g_ws;
+
+int get_workspace(size_t need, void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto &e = g_ws[dev];
+  if (e.second < need) {
+    if (e.first) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(e.first));
+      e.first = nullptr;
+      e.second = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) return fail(MPS_E_NOMEM, "workspace allocation failed");
+    e.first = p;
+    e.second = need;
+  }
+  *out = e.first;
+  return MPS_OK;
+}
+
+template <typename T> T *at(void *base, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+// Copies the trace of the sort that last used the workspace at `base`.
+int fill_trace(void *base, mps_trace *tr) {
+  Plan plan;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
+  if (plan.error)
+    return fail(MPS_E_DEVICE, "device-side consistency check failed (code " + std::to_string(plan.error) + ")");
+  tr->r = plan.r;
+  tr->n_nodes = plan.n_nodes;
+  tr->merge_cost = plan.merge_cost;
+  tr->n_levels = plan.n_levels;
+  tr->k = plan.k;
+  Layout L;
+  if (plan.n < 2 || !make_layout(plan.n, plan.m, (int)plan.kt, plan.has_payload != 0, plan.k, L))
+    return MPS_OK;
+  const uint64_t r = plan.r;
+  bool want_runs = tr->run_start || tr->run_desc || tr->power || tr->leaf_depth;
+  bool want_nodes = tr->node_begin || tr->node_end || tr->node_first || tr->node_arity ||
+                    tr->node_power || tr->node_depth;
+  if (!want_runs && !want_nodes) return MPS_OK;
+  if (tr->r_cap < r + 1)
+    return fail(MPS_E_NOMEM, "trace r_cap too small (need r+1 = " + std::to_string(r + 1) + ")");
+  std::vector<uint64_t> rs(r + 1);
+  HIP_TRY(hipMemcpy(rs.data(), at<uint64_t>(base, L.run_start), (r + 1) * 8, hipMemcpyDeviceToHost));
+  std::vector<uint8_t> P(r + 1);
+  HIP_TRY(hipMemcpy(P.data(), at<uint8_t>(base, L.power), r + 1, hipMemcpyDeviceToHost));
+  if (tr->run_start) memcpy(tr->run_start, rs.data(), (r + 1) * 8);
+  if (tr->run_desc && r) HIP_TRY(hipMemcpy(tr->run_desc, at<uint8_t>(base, L.run_desc), r, hipMemcpyDeviceToHost));
+  if (tr->power && r > 1) memcpy(tr->power, P.data() + 1, r - 1);
+  if (tr->leaf_depth && r)
+    HIP_TRY(hipMemcpy(tr->leaf_depth, at<uint8_t>(base, L.leaf_depth), r, hipMemcpyDeviceToHost));
+  if (want_nodes && r > 1) {
+    std::vector<uint32_t> Ls(r + 1), Rs(r + 1), Le(r + 1);
+    std::vector<uint8_t> ar(r + 1), dep(r + 1);
+    HIP_TRY(hipMemcpy(Ls.data(), at<uint32_t>(base, L.Ls), (r + 1) * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(Rs.data(), at<uint32_t>(base, L.Rs), (r + 1) * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(Le.data(), at<uint32_t>(base, L.Le), (r + 1) * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ar.data(), at<uint8_t>(base, L.nd_arity), r + 1, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dep.data(), at<uint8_t>(base, L.dist0), r + 1, hipMemcpyDeviceToHost));
+    uint64_t c = 0;
+    for (uint64_t i = 1; i < r; i++) {
+      if (P[i] == 0 || P[Le[i]] >= P[i]) continue;  // group leaders are the nodes
+      if (c >= tr->r_cap) return fail(MPS_E_NOMEM, "trace r_cap too small for nodes");
+      if (tr->node_begin) tr->node_begin[c] = rs[Ls[i]];
+      if (tr->node_end) tr->node_end[c] = rs[Rs[i]];
+      if (tr->node_first) tr->node_first[c] = (uint32_t)i;
+      if (tr->node_arity) tr->node_arity[c] = ar[i];
+      if (tr->node_power) tr->node_power[c] = P[i];
+      if (tr->node_depth) tr->node_depth[c] = dep[i];
+      c++;
+    }
+    if (c != plan.n_nodes) return fail(MPS_E_DEVICE, "node count mismatch in trace");
+  }
+  return MPS_OK;
+}
+
+void *g_last_base[64];  // library-managed workspace base per device (for mps_trace_fetch)
+
+int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint64_t m,
+             uint64_t N, const mps_opts *opts, mps_trace *trace, hipStream_t s) {
+  uint32_t k = opts ? opts->k : 0;
+  int rc = check_k(k);
+  if (rc) return rc;
+  Layout L;
+  if (!make_layout(N, m, kt, payload != nullptr, k, L)) return fail(MPS_E_INVALID, "bad sizes");
+  void *base = nullptr;
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < L.total)
+      return fail(MPS_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    base = opts->workspace;
+  } else {
+    rc = get_workspace(L.total, &base);
+    if (rc) return rc;
+  }
+  base = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(base) + 255) & ~(uintptr_t)255);
+
+  Work w{};
+  w.N = N;
+  w.m = m;
+  w.rmax = L.rmax;
+  w.k = (int)k;
+  w.logk = k == 2 ? 1 : (k == 4 ? 2 : 3);
+  w.tile = kTileSize;
+  w.alt_keys = at<void>(base, L.alt_keys);
+  w.alt_vals = payload ? at<uint32_t>(base, L.alt_vals) : nullptr;
+  w.seg_off_local = at<uint64_t>(base, L.seg_off);
+  w.off = d_off ? d_off : w.seg_off_local;
+  w.dbits = at<uint64_t>(base, L.dbits);
+  w.det_agg = at<DetAgg>(base, L.det_agg);
+  w.det_zin = at<uint64_t>(base, L.det_zin);
+  w.det_off = at<uint64_t>(base, L.det_off);
+  w.run_start = at<uint64_t>(base, L.run_start);
+  w.run_desc = at<uint8_t>(base, L.run_desc);
+  w.power = at<uint8_t>(base, L.power);
+  w.ansv_bl = at<uint32_t>(base, L.ansv_bl);
+  w.ansv_bf = at<uint32_t>(base, L.ansv_bf);
+  w.ansv_cl = at<uint32_t>(base, L.ansv_cl);
+  w.ansv_cr = at<uint32_t>(base, L.ansv_cr);
+  w.Ls = at<uint32_t>(base, L.Ls);
+  w.Rs = at<uint32_t>(base, L.Rs);
+  w.Le = at<uint32_t>(base, L.Le);
+  w.Re = at<uint32_t>(base, L.Re);
+  w.nd_arity = at<uint8_t>(base, L.nd_arity);
+  w.nd_mem = at<uint32_t>(base, L.nd_mem);
+  w.jump0 = at<uint32_t>(base, L.jump0);
+  w.jump1 = at<uint32_t>(base, L.jump1);
+  w.dist0 = at<uint8_t>(base, L.dist0);
+  w.dist1 = at<uint8_t>(base, L.dist1);
+  w.leaf_depth = at<uint8_t>(base, L.leaf_depth);
+  w.lvl_cnt = at<uint32_t>(base, L.lvl_cnt);
+  w.lvl_list = at<uint32_t>(base, L.lvl_list);
+  w.lvl_np = at<uint64_t>(base, L.lvl_np);
+  w.scan_tmp = at<uint64_t>(base, L.scan_tmp);
+  w.corank = at<uint32_t>(base, L.corank);
+  w.plan = at<Plan>(base, L.plan);
+  uint64_t *lvl_tot = at<uint64_t>(base, L.lvl_tot);
+  uint64_t *tile_base = at<uint64_t>(base, L.tile_base);
+  uint32_t *tj = at<uint32_t>(base, L.tj);
+
+  const unsigned gtree = (unsigned)(L.nbb < 4096 ? L.nbb : 4096);
+
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.plan, w.seg_off_local, N, m, (uint32_t)kt,
+                     payload ? 1u : 0u, k, d_off ? 0 : 1);
+  if (d_off)
+    hipLaunchKernelGGL(k_check_offsets, dim3(64), dim3(256), 0, s, d_off, m, N, w.plan);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_detect(kt, keys, w, s));
+  HIP_TRY(launch_tree(w, trace ? 1 : 0, lvl_tot, tile_base, tj, gtree, s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_place(kt, keys, payload, w, s));
+  for (int d = L.levels - 1; d >= 0; d--) {
+    LevelArgs a;
+    bool out_user = (d & 1) == 0;
+    a.in_keys = out_user ? w.alt_keys : keys;
+    a.in_vals = payload ? (out_user ? w.alt_vals : payload) : nullptr;
+    a.out_keys = out_user ? keys : w.alt_keys;
+    a.out_vals = payload ? (out_user ? payload : w.alt_vals) : nullptr;
+    HIP_TRY(launch_level(kt, a, w, tj, tile_base, d, s));
+  }
+  if (!(opts && opts->workspace)) {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) g_last_base[dev] = base;
+  }
+  if (trace) return fill_trace(base, trace);
+  return MPS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C entry points
+extern "C" uint64_t mps_workspace_bytes(uint64_t n, uint64_t m, mps_key_type kt, int has_payload,
+                                        uint32_t k) {
+  if (k == 0) k = 4;
+  if (k != 2 && k != 4 && k != 8) return 0;
+  if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return 0;
+  Layout L;
+  if (!make_layout(n < 2 ? 2 : n, m < 1 ? 1 : m, kt, has_payload != 0, k, L)) return 0;
+  return L.total;
+}
+
+extern "C" int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
+                           const mps_opts *opts, mps_trace *trace, void *stream) {
+  g_err.clear();
+  if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
+  if (n > 0 && !keys) return fail(MPS_E_INVALID, "keys is NULL");
+  if (n > (1ull << 31)) return fail(MPS_E_UNSUPPORTED, "arrays longer than 2^31 are not supported");
+  if (n <= 1) {
+    if (trace) {
+      uint32_t k = opts && opts->k ? opts->k : 4;
+      trace->r = n;
+      trace->n_nodes = 0;
+      trace->merge_cost = 0;
+      trace->n_levels = 0;
+      trace->k = k;
+      if (n == 1) {
+        if (trace->r_cap < 2 && (trace->run_start || trace->run_desc || trace->leaf_depth))
+          return fail(MPS_E_NOMEM, "trace r_cap too small");
+        if (trace->run_start) { trace->run_start[0] = 0; trace->run_start[1] = 1; }
+        if (trace->run_desc) trace->run_desc[0] = 0;
+        if (trace->leaf_depth) trace->leaf_depth[0] = 0;
+      } else if (trace->run_start && trace->r_cap >= 1) {
+        trace->run_start[0] = 0;
+      }
+    }
+    return MPS_OK;
+  }
+  return run_sort(keys, kt, payload, nullptr, 1, n, opts, trace, (hipStream_t)stream);
+}
+
+extern "C" int mps_sort(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n, void *stream) {
+  return mps_sort_ex(keys, kt, payload, n, nullptr, nullptr, stream);
+}
+extern "C" int mps_sort_i32(int32_t *keys, uint32_t *payload, uint64_t n, void *stream) {
+  return mps_sort_ex(keys, MPS_I32, payload, n, nullptr, nullptr, stream);
+}
+extern "C" int mps_sort_i64(int64_t *keys, uint32_t *payload, uint64_t n, void *stream) {
+  return mps_sort_ex(keys, MPS_I64, payload, n, nullptr, nullptr, stream);
+}
+extern "C" int mps_sort_f32(float *keys, uint32_t *payload, uint64_t n, void *stream) {
+  return mps_sort_ex(keys, MPS_F32, payload, n, nullptr, nullptr, stream);
+}
+
+extern "C" int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload,
+                                const uint64_t *offsets, const uint64_t *h_offsets, uint64_t m,
+                                uint64_t total_n, const mps_opts *opts, mps_trace *trace,
+                                void *stream) {
+  g_err.clear();
+  if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
+  if (m == 0 || total_n == 0) {
+    if (trace) memset(trace, 0, offsetof(mps_trace, r_cap));
+    return MPS_OK;
+  }
+  if (!keys || !offsets) return fail(MPS_E_INVALID, "keys or offsets is NULL");
+  if (total_n > (1ull << 40)) return fail(MPS_E_UNSUPPORTED, "total too large");
+  if (h_offsets) {
+    if (h_offsets[0] != 0 || h_offsets[m] != total_n) return fail(MPS_E_INVALID, "offsets must run from 0 to total_n");
+    for (uint64_t i = 0; i < m; i++) {
+      if (h_offsets[i + 1] < h_offsets[i]) return fail(MPS_E_INVALID, "offsets must be non-decreasing");
+      if (h_offsets[i + 1] - h_offsets[i] > (1ull << 31)) return fail(MPS_E_UNSUPPORTED, "an array is longer than 2^31");
+    }
+  }
+  return run_sort(keys, kt, payload, offsets, m, total_n, opts, trace, (hipStream_t)stream);
+}
+
+extern "C" int mps_trace_fetch(const void *workspace, mps_trace *trace) {
+  g_err.clear();
+  if (!trace) return fail(MPS_E_INVALID, "trace is NULL");
+  void *base = nullptr;
+  if (workspace) {
+    base = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~(uintptr_t)255);
+  } else {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64 || !g_last_base[dev]) return fail(MPS_E_NOTFOUND, "no sort has used the library workspace");
+    base = g_last_base[dev];
+  }
+  return fill_trace(base, trace);
+}

@@ -1,0 +1,150 @@
+// mps_internal.h -- shared definitions of the gfx950 multiway-Powersort kernels.
+//
+// Everything here is integer work: keys are compared through an order-
+// preserving map to unsigned integers (sign-bit flip for signed integers, the
+// IEEE-754 total-order bit flip for float32), so no floating point is used.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mps {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxLevels = 64;       // bound on merge-tree depth (powers fit in a byte)
+constexpr int kVMax = 40;            // powers are < kVMax (k=2: P <= ceil(log2(2n)) <= 33)
+constexpr uint32_t kNone32 = 0xFFFFFFFFu;
+constexpr uint64_t kNone64 = ~0ull;
+
+// Key traits: storage type U and the order-preserving map to unsigned O.
+template <int KT> struct Key;
+template <> struct Key<0> {  // int32
+  using U = uint32_t;
+  __device__ static inline uint32_t ord(uint32_t b) { return b ^ 0x80000000u; }
+  __device__ static inline uint32_t unord(uint32_t o) { return o ^ 0x80000000u; }
+};
+template <> struct Key<1> {  // int64
+  using U = uint64_t;
+  __device__ static inline uint64_t ord(uint64_t b) { return b ^ 0x8000000000000000ull; }
+  __device__ static inline uint64_t unord(uint64_t o) { return o ^ 0x8000000000000000ull; }
+};
+template <> struct Key<2> {  // float32, IEEE-754 total order
+  using U = uint32_t;
+  __device__ static inline uint32_t ord(uint32_t b) {
+    return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+  }
+  __device__ static inline uint32_t unord(uint32_t o) {
+    return (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
+  }
+};
+
+// Device-resident plan: everything the per-level launches need, written by
+// the planning kernels so that no host synchronisation is required.
+struct Plan {
+  uint64_t n;                        // total elements
+  uint64_t m;                        // arrays
+  uint32_t kt, has_payload, k, pad;  // what the workspace was laid out for
+  uint64_t r;                        // runs found
+  uint64_t n_nodes;                  // internal merge-tree nodes
+  uint32_t n_levels;                 // 1 + deepest internal-node depth (0: nothing to merge)
+  uint32_t error;                    // nonzero: a device-side check failed
+  uint64_t merge_cost;               // filled only when a trace is requested
+  uint64_t lvl_begin[kMaxLevels + 1];  // level-sorted node list offsets
+  uint64_t lvl_total[kMaxLevels];    // sum of node sizes per level
+  uint64_t lvl_tiles[kMaxLevels];    // merge tiles per level
+};
+
+// Run-detection block aggregate (16384 positions per block).
+struct DetAgg {
+  uint64_t lz;    // last position in the block whose direction-change bit is 0 (kNone64: none)
+  uint64_t fz;    // first such position (block end if none)
+  uint64_t cnt;   // breaks at or after fz (they do not depend on earlier blocks)
+};
+
+// Device views of the workspace.
+struct Work {
+  uint64_t N, m, rmax;
+  int k, logk, tile;
+  void *alt_keys;
+  uint32_t *alt_vals;
+  const uint64_t *off;               // segment offsets [m+1]
+  uint64_t *seg_off_local;           // 2-entry offsets for single-array calls
+  uint64_t *dbits;
+  DetAgg *det_agg;
+  uint64_t *det_zin, *det_off;
+  uint64_t *run_start;               // [rmax+1]
+  uint8_t *run_desc;                 // [rmax]
+  uint8_t *power;                    // [rmax+1], power[0] = power[r] = 0
+  uint32_t *ansv_bl, *ansv_bf, *ansv_cl, *ansv_cr;   // [nbb * kVMax]
+  uint32_t *Ls, *Rs, *Le, *Re;       // [rmax+1]
+  uint8_t *nd_arity;                 // [rmax+1] (indexed by leader boundary)
+  uint32_t *nd_mem;                  // [(rmax+1)*(k-1)]
+  uint32_t *jump0, *jump1;           // [rmax+1]
+  uint8_t *dist0, *dist1;            // [rmax+1]
+  uint8_t *leaf_depth;               // [rmax]
+  uint32_t *lvl_cnt;                 // [nbb * kMaxLevels]
+  uint32_t *lvl_list;                // [rmax]
+  uint64_t *lvl_np;                  // [rmax+1] exclusive prefix of node sizes
+  uint64_t *scan_tmp;                // [nbb + 1024]
+  uint32_t *corank;                  // [(N/tile + 2) * k]
+  Plan *plan;
+};
+
+// ---------------------------------------------------------------- wave helpers
+__device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ inline uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint32_t shfl32(uint32_t v, int src) { return __shfl(v, src); }
+template <typename T> __device__ inline T shfl_any(T v, int src);
+template <> __device__ inline uint32_t shfl_any<uint32_t>(uint32_t v, int src) { return shfl32(v, src); }
+template <> __device__ inline uint64_t shfl_any<uint64_t>(uint64_t v, int src) { return shfl64(v, src); }
+
+// The segment containing position p (p < N): last i with off[i] <= p; that
+// segment is non-empty because it contains p.
+__device__ inline uint32_t seg_of(const uint64_t *off, uint64_t m, uint64_t p) {
+  uint64_t lo = 0, hi = m;  // answer in [0, m)
+  while (hi - lo > 1) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= p) lo = mid; else hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
+__device__ inline bool is_seg_start(const uint64_t *off, uint64_t m, uint64_t p) {
+  return off[seg_of(off, m, p)] == p;
+}
+
+// Bit b set iff position w0+b starts a non-empty segment.
+__device__ inline uint64_t seg_start_mask(const uint64_t *off, uint64_t m, uint64_t w0) {
+  uint64_t lo = 0, hi = m + 1;  // first i with off[i] >= w0
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] < w0) lo = mid + 1; else hi = mid;
+  }
+  uint64_t mask = 0;
+  for (uint64_t i = lo; i < m && off[i] < w0 + 64; i++)
+    if (off[i + 1] > off[i]) mask |= 1ull << (off[i] - w0);
+  return mask;
+}
+
+// ---------------------------------------------------------------- host entry points
+struct LevelArgs {
+  const void *in_keys;
+  const uint32_t *in_vals;
+  void *out_keys;
+  uint32_t *out_vals;
+};
+
+constexpr int kTileSize = 2048;   // outputs per merge tile
+
+hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s);
+hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
+                       uint32_t *tj, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
+hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                        const uint64_t *tile_base, int level, hipStream_t s);
+
+}  // namespace mps

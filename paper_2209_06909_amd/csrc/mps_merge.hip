@@ -1,0 +1,474 @@
+// mps_merge.hip -- leaf placement and the per-level k-way merges.
+//
+// Buffers alternate by depth: a node at depth d writes buffer d mod 2
+// (buffer 0 is the caller's array, buffer 1 the workspace copy), so it always
+// reads its children from the other buffer.  Levels run deepest first; a
+// node's children (depth d+1) are complete before it runs and nothing else
+// inside its span is still needed, so no level needs a third buffer.
+//
+// Leaves start in buffer 0.  A leaf at odd depth is copied to buffer 1; a
+// strictly decreasing run is reversed on the way (paper, Section 2: such runs
+// hold no equal keys, so reversing keeps the sort stable).
+//
+// Each level is cut into tiles of exactly `tile` outputs over the
+// concatenation of its nodes (a tile may cover the tail of one node, whole
+// small nodes and the head of another).  For every tile boundary a co-rank
+// step finds how many elements of each child precede it in the stable merged
+// order (key, then child index: equal keys keep their input order, as in the
+// paper's merges where the left run wins ties).  A workgroup then stages the
+// tile's input slices in LDS and merges them by a binary tree of 2-way
+// merge-path merges (log2 k stages), all in LDS, and writes the tile back
+// with coalesced stores.
+#include "mps_internal.h"
+
+namespace mps {
+
+// ---------------------------------------------------------------- placement
+constexpr int kPlaceThreads = 256;
+constexpr uint64_t kPlaceBlock = 4096;
+
+__device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, uint64_t e) {
+  // last j in [lo, hi] with rs[j] <= e
+  while (hi > lo) {
+    uint64_t mid = (lo + hi + 1) >> 1;
+    if (rs[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename U>
+__global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
+                                                         uint32_t *__restrict__ vals,
+                                                         U *__restrict__ akeys,
+                                                         uint32_t *__restrict__ avals, uint64_t N,
+                                                         const uint64_t *__restrict__ rs,
+                                                         const uint8_t *__restrict__ desc,
+                                                         const uint8_t *__restrict__ leaf_depth,
+                                                         const Plan *__restrict__ plan) {
+  __shared__ uint64_t sJ[2];
+  const uint64_t r = plan->r;
+  const uint64_t nblk = (N + kPlaceBlock - 1) / kPlaceBlock;
+  for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
+    if (threadIdx.x == 0) {
+      sJ[0] = run_of(rs, 0, r - 1, bs);
+      sJ[1] = run_of(rs, sJ[0], r - 1, be - 1);
+    }
+    __syncthreads();
+    uint64_t j0 = sJ[0], j1 = sJ[1];
+    for (uint64_t e = bs + threadIdx.x; e < be; e += kPlaceThreads) {
+      uint64_t j = run_of(rs, j0, j1, e);
+      uint64_t s = rs[j], f = rs[j + 1];
+      bool odd = leaf_depth[j] & 1, dsc = desc[j];
+      if (odd) {
+        uint64_t dst = dsc ? s + f - 1 - e : e;
+        akeys[dst] = keys[e];
+        if (vals) avals[dst] = vals[e];
+      } else if (dsc && e - s < (f - s) / 2) {
+        uint64_t m = s + f - 1 - e;
+        U a = keys[e], c = keys[m];
+        keys[e] = c;
+        keys[m] = a;
+        if (vals) {
+          uint32_t x = vals[e], y = vals[m];
+          vals[e] = y;
+          vals[m] = x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- node access
+struct NodeIn {
+  uint64_t c[9];   // child boundaries: c[0] = span start, c[d] = span end
+  int d;
+};
+
+// Child boundaries of node v; false (and nothing read through a bad index)
+// if the node record is inconsistent.
+template <int K>
+__device__ inline bool load_node(uint32_t v, uint64_t r, const uint64_t *rs, const uint32_t *Ls,
+                                 const uint32_t *Rs, const uint32_t *mem,
+                                 const uint8_t *arity, NodeIn &nd) {
+  if (v >= r) return false;
+  int d = arity[v];
+  if (d < 2 || d > K) return false;
+  nd.d = d;
+  uint32_t l = Ls[v], rr = Rs[v];
+  if (l >= v || rr > r || rr <= v) return false;
+  nd.c[0] = rs[l];
+  uint32_t prev = l;
+  for (int j = 1; j < d; j++) {
+    uint32_t b = mem[(uint64_t)v * (K - 1) + (j - 1)];
+    if (b <= prev || b >= rr) return false;
+    nd.c[j] = rs[b];
+    prev = b;
+  }
+  nd.c[d] = rs[rr];
+  return true;
+}
+
+// Stable order across children: (key, child index).
+template <typename O>
+__device__ inline bool st_less(O x, int a, O y, int b) {
+  return x < y || (x == y && a < b);
+}
+
+// ---------------------------------------------------------------- co-rank
+// Cut of a node at output rank q: c_j = number of elements of child j among
+// the first q outputs.  Windows [lo_j, hi_j] always contain c_j.  Each round
+// splits the remaining rank over the windows proportionally, checks whether
+// the split is a consistent cut (largest taken < smallest untaken in the
+// stable order) and otherwise shrinks the window of the largest taken element
+// from above and that of the smallest untaken element from below.
+template <int KT, int K>
+__global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__restrict__ in_keys,
+                                                const uint64_t *__restrict__ rs,
+                                                const uint32_t *__restrict__ Ls,
+                                                const uint32_t *__restrict__ Rs,
+                                                const uint32_t *__restrict__ mem,
+                                                const uint8_t *__restrict__ arity,
+                                                const uint32_t *__restrict__ list,
+                                                const uint64_t *__restrict__ np,
+                                                const uint32_t *__restrict__ tj,
+                                                const uint64_t *__restrict__ tile_base,
+                                                Plan *__restrict__ plan, int level,
+                                                int tile, uint32_t *__restrict__ cr) {
+  using O = typename Key<KT>::U;
+  const uint64_t tiles = plan->lvl_tiles[level];
+  if (tiles == 0) return;
+  const uint64_t r = plan->r;
+  const uint64_t lb = plan->lvl_begin[level];
+  const uint64_t nlev = plan->lvl_begin[level + 1] - lb;
+  const uint64_t np0 = np[lb];
+  const uint32_t *tjl = tj + tile_base[level];
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tiles;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t out[K];
+    for (int j = 0; j < K; j++) out[j] = 0;
+    if (t > 0) {
+      uint64_t Q = t * (uint64_t)tile;
+      uint32_t jn = tjl[t];
+      uint64_t q = jn < nlev ? Q - (np[lb + jn] - np0) : 0;
+      NodeIn nd;
+      if (jn >= nlev || !load_node<K>(list[lb + jn], r, rs, Ls, Rs, mem, arity, nd) ||
+          q >= nd.c[nd.d] - nd.c[0]) {
+        atomicOr(&plan->error, 128u);
+        q = 0;
+      }
+      if (q > 0) {
+        const int d = nd.d;
+        uint64_t lo[K], hi[K], mm[K];
+        for (int j = 0; j < K; j++) {
+          uint64_t len = j < d ? nd.c[j + 1] - nd.c[j] : 0;
+          lo[j] = 0;
+          hi[j] = len < q ? len : q;
+        }
+        for (int it = 0; it < 4096; it++) {
+          uint64_t slo = 0, W = 0;
+          for (int j = 0; j < d; j++) { slo += lo[j]; W += hi[j] - lo[j]; }
+          uint64_t rem = q - slo;
+          if (rem == 0) { for (int j = 0; j < d; j++) mm[j] = 0; break; }
+          if (rem == W) { for (int j = 0; j < d; j++) mm[j] = hi[j] - lo[j]; break; }
+          uint64_t sm = 0;
+          for (int j = 0; j < d; j++) {
+            uint64_t w = hi[j] - lo[j];
+            mm[j] = (w * rem) / W;  // w < 2^31, rem < 2^32
+            sm += mm[j];
+          }
+          for (int j = 0; j < d && sm < rem; j++)
+            if (mm[j] < hi[j] - lo[j]) { mm[j]++; sm++; }
+          int a = -1, b = -1;
+          O xa = 0, yb = 0;
+          for (int j = 0; j < d; j++) {
+            uint64_t w = hi[j] - lo[j];
+            uint64_t base = nd.c[j] + lo[j];
+            if (mm[j] > 0) {
+              O x = Key<KT>::ord(in_keys[base + mm[j] - 1]);
+              if (a < 0 || !st_less(x, j, xa, a)) { xa = x; a = j; }
+            }
+            if (mm[j] < w) {
+              O y = Key<KT>::ord(in_keys[base + mm[j]]);
+              if (b < 0 || st_less(y, j, yb, b)) { yb = y; b = j; }
+            }
+          }
+          // Consistent cut: the largest taken element precedes the smallest
+          // untaken one.  Within one child positions decide, so a == b is
+          // always consistent; across children (key, child) decides.
+          if (a < 0 || b < 0 || a == b || st_less(xa, a, yb, b)) break;
+          hi[a] = lo[a] + mm[a] - 1;
+          lo[b] = lo[b] + mm[b] + 1;
+        }
+        for (int j = 0; j < d; j++) out[j] = (uint32_t)(lo[j] + mm[j]);
+      }
+    }
+    for (int j = 0; j < K; j++) cr[t * K + j] = out[j];
+  }
+}
+
+// ---------------------------------------------------------------- tile merge
+template <typename O, int K, int TILE>
+struct MergeSmem {
+  static constexpr int kMaxSlices = TILE + 2 * K + 2;
+  static constexpr int kMaxPieces = TILE / 2 + 4;
+  static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
+  static constexpr size_t kAux = kBuf > (size_t)kMaxSlices * 8 ? kBuf : (size_t)kMaxSlices * 8;
+  alignas(16) unsigned char bufA[kBuf];
+  alignas(16) unsigned char bufB[kAux];       // also holds slice global starts during setup
+  uint64_t pc_out[kMaxPieces];
+  uint16_t sl_off[kMaxSlices];
+  uint16_t pc_loff[kMaxPieces];
+  uint16_t pc_sl[kMaxPieces];
+  uint64_t scan[256];
+  uint64_t misc[8];
+};
+
+template <typename T>
+__device__ inline int ub16(const uint16_t *a, int n, T x) {
+  // first index in [0, n) with a[i] > x
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if ((T)a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <int KT, int K, int TILE, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_merge(
+    const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
+    typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
+    const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
+    const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
+    const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
+    const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
+    const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level,
+    const uint32_t *__restrict__ cr) {
+  using Kt = Key<KT>;
+  using O = typename Kt::U;
+  constexpr int E = TILE / THREADS;
+  constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
+  __shared__ MergeSmem<O, K, TILE> sm;
+  O *kA = reinterpret_cast<O *>(sm.bufA);
+  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
+  O *kB = reinterpret_cast<O *>(sm.bufB);
+  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
+  uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufB);
+  const bool has_vals = in_vals != nullptr;
+
+  const uint64_t tiles = plan->lvl_tiles[level];
+  if (tiles == 0) return;
+  const uint64_t rr_total = plan->r;
+  const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
+  const uint64_t np0 = np[lb];
+  const uint64_t L = np[le] - np0;
+  const uint32_t *tjl = tj + tile_base[level];
+  const int t = threadIdx.x;
+
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t Q0 = tile * TILE;
+    const uint64_t Q1 = Q0 + TILE < L ? Q0 + TILE : L;
+    const int Tt = (int)(Q1 - Q0);
+    const uint64_t j0 = tjl[tile];
+    uint64_t j1;
+    {
+      uint64_t jn = tjl[tile + 1];
+      if (Q1 == L) j1 = (le - lb) - 1;
+      else j1 = (np[lb + jn] - np0 == Q1) ? jn - 1 : jn;
+    }
+    const int P = (int)(j1 - j0 + 1);
+    if (t == 0) sm.misc[0] = 0;
+    __syncthreads();
+    if (j1 < j0 || j1 >= le - lb || P + 1 > MergeSmem<O, K, TILE>::kMaxPieces) {  // cannot happen: pieces hold >= 2 keys
+      if (t == 0) atomicOr(&plan->error, 16u);
+      continue;
+    }
+
+    // ---- piece and slice tables
+    uint64_t carry_len = 0, carry_sl = 0;
+    for (int pbase = 0; pbase < P; pbase += THREADS) {
+      int p = pbase + t;
+      NodeIn nd;
+      uint32_t c0[K], c1[K];
+      uint64_t plen = 0;
+      int pd = 0;
+      if (p < P) {
+        uint64_t j = j0 + p;
+        if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
+          sm.misc[0] = 1;
+          nd.d = 2;
+          nd.c[0] = nd.c[1] = nd.c[2] = 0;
+        }
+        pd = nd.d;
+        bool first = p == 0, last = p == P - 1;
+        bool cut_end = last && Q1 < np[lb + j + 1] - np0;
+        for (int jj = 0; jj < K; jj++) {
+          if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
+          uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
+          c0[jj] = first ? cr[tile * K + jj] : 0;
+          c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
+          if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
+            sm.misc[0] = 1;
+            c0[jj] = c1[jj] = 0;
+          }
+          plen += c1[jj] - c0[jj];
+        }
+      }
+      // block exclusive scan of (plen, pd) packed: high 32 bits slices, low 32 bits length
+      uint64_t packed = ((uint64_t)pd << 32) | plen;
+      sm.scan[t] = packed;
+      __syncthreads();
+      for (int o = 1; o < THREADS; o <<= 1) {
+        uint64_t y = t >= o ? sm.scan[t - o] : 0;
+        __syncthreads();
+        sm.scan[t] += y;
+        __syncthreads();
+      }
+      uint64_t ex = sm.scan[t] - packed;
+      uint64_t tot = sm.scan[THREADS - 1];
+      __syncthreads();
+      if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
+          carry_sl + (ex >> 32) + pd < (uint64_t)MergeSmem<O, K, TILE>::kMaxSlices) {
+        uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
+        uint64_t sl0 = carry_sl + (ex >> 32);
+        sm.pc_loff[p] = (uint16_t)loff;
+        sm.pc_sl[p] = (uint16_t)sl0;
+        sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
+        uint64_t acc = loff;
+        for (int jj = 0; jj < pd; jj++) {
+          sm.sl_off[sl0 + jj] = (uint16_t)acc;
+          sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
+          acc += c1[jj] - c0[jj];
+        }
+      }
+      carry_len += tot & 0xFFFFFFFFull;
+      carry_sl += tot >> 32;
+    }
+    const int S = (int)carry_sl;
+    if (carry_len != (uint64_t)Tt || S + 1 > MergeSmem<O, K, TILE>::kMaxSlices) sm.misc[0] = 1;
+    __syncthreads();
+    if (sm.misc[0]) {  // the tile's co-ranks do not add up: flag it and leave the tile alone
+      if (t == 0) atomicOr(&plan->error, 32u);
+      __syncthreads();
+      continue;
+    }
+    if (t == 0) {
+      sm.pc_loff[P] = (uint16_t)Tt;
+      sm.pc_sl[P] = (uint16_t)S;
+      sm.sl_off[S] = (uint16_t)Tt;
+    }
+    __syncthreads();
+
+    // ---- stage the tile's inputs in LDS
+    for (int e = t; e < Tt; e += THREADS) {
+      int s = ub16(sm.sl_off, S + 1, e) - 1;
+      uint64_t g = sl_g[s] + (uint64_t)(e - sm.sl_off[s]);
+      kA[e] = Kt::ord(in_keys[g]);
+      if (has_vals) vA[e] = in_vals[g];
+    }
+    __syncthreads();
+
+    // ---- log2(K) stages of pairwise merge-path merges
+    O *ks = kA, *kd = kB;
+    uint32_t *vs = vA, *vd = vB;
+    for (int st = 1; st <= LOGK; st++) {
+      int e = t * E;
+      const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
+      while (e < e_end) {
+        int s = ub16(sm.sl_off, S + 1, e) - 1;
+        int p = ub16(sm.pc_sl, P + 1, s) - 1;
+        int s0 = sm.pc_sl[p];
+        int pd = sm.pc_sl[p + 1] - s0;
+        int jj = s - s0;
+        int h = 1 << (st - 1);
+        int g0 = (jj >> st) << st;
+        int iM = g0 + h < pd ? g0 + h : pd;
+        int iR = g0 + 2 * h < pd ? g0 + 2 * h : pd;
+        int u0 = sm.sl_off[s0 + g0], u1 = sm.sl_off[s0 + iM], u2 = sm.sl_off[s0 + iR];
+        int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
+        int lo = diag - nR > 0 ? diag - nR : 0;
+        int hi = diag < nL ? diag : nL;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (ks[u0 + mid] <= ks[u1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
+        }
+        int ia = u0 + lo, ib = u1 + diag - lo;
+        int stop = e_end < u2 ? e_end : u2;
+        if (stop <= e) break;  // cannot happen with valid tables (e < u2)
+        for (; e < stop; e++) {
+          bool takeL = ib >= u2 || (ia < u1 && ks[ia] <= ks[ib]);
+          int src = takeL ? ia : ib;
+          kd[e] = ks[src];
+          if (has_vals) vd[e] = vs[src];
+          if (takeL) ia++; else ib++;
+        }
+      }
+      __syncthreads();
+      O *tk = ks; ks = kd; kd = tk;
+      uint32_t *tv = vs; vs = vd; vd = tv;
+    }
+
+    // ---- write back
+    for (int e = t; e < Tt; e += THREADS) {
+      int p = ub16(sm.pc_loff, P + 1, e) - 1;
+      uint64_t g = sm.pc_out[p] + (uint64_t)(e - sm.pc_loff[p]);
+      out_keys[g] = Kt::unord(ks[e]);
+      if (has_vals) out_vals[g] = vs[e];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- host side
+hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s) {
+  uint64_t nblk = (w.N + kPlaceBlock - 1) / kPlaceBlock;
+  unsigned g = (unsigned)(nblk < 8192 ? nblk : 8192);
+  if (g == 0) return hipSuccess;
+  if (kt == 1)
+    hipLaunchKernelGGL(k_place<uint64_t>, dim3(g), dim3(kPlaceThreads), 0, s, (uint64_t *)keys, vals,
+                       (uint64_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
+                       w.leaf_depth, w.plan);
+  else
+    hipLaunchKernelGGL(k_place<uint32_t>, dim3(g), dim3(kPlaceThreads), 0, s, (uint32_t *)keys, vals,
+                       (uint32_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
+                       w.leaf_depth, w.plan);
+  return hipGetLastError();
+}
+
+constexpr int kMergeThreads = 256;
+constexpr int kTile = kTileSize;
+
+template <int KT, int K>
+static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
+                           const uint64_t *tile_base, int level, hipStream_t s) {
+  using U = typename Key<KT>::U;
+  unsigned gc = 1024, gm = 4096;
+  hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
+                     w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
+                     tile_base, w.plan, level, kTile, w.corank);
+  hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads>), dim3(gm), dim3(kMergeThreads), 0, s,
+                     (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals, w.run_start,
+                     w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base,
+                     w.plan, level, w.corank);
+}
+
+hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                        const uint64_t *tile_base, int level, hipStream_t s) {
+  switch (w.k * 4 + kt) {
+    case 2 * 4 + 0: launch_level_t<0, 2>(a, w, tj, tile_base, level, s); break;
+    case 2 * 4 + 1: launch_level_t<1, 2>(a, w, tj, tile_base, level, s); break;
+    case 2 * 4 + 2: launch_level_t<2, 2>(a, w, tj, tile_base, level, s); break;
+    case 4 * 4 + 0: launch_level_t<0, 4>(a, w, tj, tile_base, level, s); break;
+    case 4 * 4 + 1: launch_level_t<1, 4>(a, w, tj, tile_base, level, s); break;
+    case 4 * 4 + 2: launch_level_t<2, 4>(a, w, tj, tile_base, level, s); break;
+    case 8 * 4 + 0: launch_level_t<0, 8>(a, w, tj, tile_base, level, s); break;
+    case 8 * 4 + 1: launch_level_t<1, 8>(a, w, tj, tile_base, level, s); break;
+    case 8 * 4 + 2: launch_level_t<2, 8>(a, w, tj, tile_base, level, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mps

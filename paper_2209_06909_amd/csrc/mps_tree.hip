@@ -1,0 +1,577 @@
+// mps_tree.hip -- node powers and the merge tree, built without a stack.
+//
+// Powers (paper, Definition 3.1): with A = s_{i-1}+s_i and B = s_i+s_{i+1}
+// the run midpoints are a = A/2n and b = B/2n.  The 2-way power is the
+// index of the first binary digit in which a and b differ; with 32-bit
+// fixed point x = floor(A*2^31/n), y = floor(B*2^31/n) (exact prefixes of
+// the binary expansions, and x != y because b - a >= 1/n) it is
+// clz32(x ^ y) + 1.  For k = 2^q the k-way power groups q binary digits per
+// base-k digit: P_k = floor((P_2 - 1)/q) + 1 (Section 3.1, the "squish" of
+// adjacent levels).
+//
+// Tree (Algorithm 1): a node is a maximal group of equal-power boundaries
+// with only larger powers between them, delimited by the nearest strictly
+// smaller powers on both sides.  Those nearest-smaller positions come from a
+// ballot-based all-nearest-smaller-values pass (powers are small integers).
+// The parent of a node is the node owning the larger of its two delimiting
+// powers; depths follow by pointer jumping.  Segment edges (and the array
+// ends) carry power 0, below every real power, so nothing merges across them.
+#include "mps_internal.h"
+
+namespace mps {
+
+constexpr int kTreeThreads = 1024;   // boundaries per block
+constexpr int kTreeWaves = kTreeThreads / kWave;
+
+// ---------------------------------------------------------------- powers
+__global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
+                                                const uint64_t *__restrict__ off, uint64_t m,
+                                                Plan *__restrict__ plan, int logk,
+                                                uint8_t *__restrict__ P) {
+  const uint64_t r = plan->r;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= r;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint8_t p = 0;
+    if (i > 0 && i < r) {
+      uint64_t s = rs[i];
+      uint32_t sg = seg_of(off, m, s);
+      uint64_t base = off[sg];
+      if (s != base) {
+        uint64_t n = off[sg + 1] - base;
+        uint64_t A = (rs[i - 1] - base) + (s - base);
+        uint64_t B = (s - base) + (rs[i + 1] - base);
+        uint32_t x = (uint32_t)((A << 31) / n);
+        uint32_t y = (uint32_t)((B << 31) / n);
+        uint32_t p2 = (uint32_t)__clz(x ^ y) + 1;
+        uint32_t pk = (p2 - 1) / (uint32_t)logk + 1;
+        if (x == y || pk >= (uint32_t)kVMax) {  // impossible: b - a >= 1/n, n <= 2^31
+          atomicOr(&plan->error, 8u);
+          pk = kVMax - 1;
+        }
+        p = (uint8_t)pk;
+      }
+    }
+    P[i] = p;
+  }
+}
+
+// ---------------------------------------------------------------- ANSV
+// Per block of 1024 boundaries: for every value v in [1, kVMax], the last
+// (stored +1; 0 = none) and first (kNone32 = none) boundary with power < v.
+__device__ inline void wave_masks(const uint8_t *__restrict__ P, uint64_t r, uint64_t i,
+                                  uint64_t *masks /* [kVMax] per wave, LDS */, int lane) {
+  uint32_t p = i <= r ? P[i] : 255u;
+  for (int v = 1; v <= kVMax; v++) {
+    uint64_t mk = ballot64(p < (uint32_t)v);
+    if (lane == 0) masks[v - 1] = mk;
+  }
+}
+
+__global__ __launch_bounds__(kTreeThreads) void k_ansv_block(const uint8_t *__restrict__ P,
+                                                             const Plan *__restrict__ plan,
+                                                             uint32_t *__restrict__ BL,
+                                                             uint32_t *__restrict__ BF) {
+  __shared__ uint64_t sM[kTreeWaves][kVMax];
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
+    uint64_t i = b * kTreeThreads + t;
+    wave_masks(P, r, i, sM[w], lane);
+    __syncthreads();
+    if (t < kVMax) {
+      uint32_t last = 0, first = kNone32;
+      for (int ww = 0; ww < kTreeWaves; ww++) {
+        uint64_t mk = sM[ww][t];
+        if (!mk) continue;
+        uint64_t base = b * kTreeThreads + (uint64_t)ww * kWave;
+        if (first == kNone32) first = (uint32_t)(base + __ffsll((long long)mk) - 1);
+        last = (uint32_t)(base + 63 - __clzll(mk)) + 1;
+      }
+      BL[b * kVMax + t] = last;
+      BF[b * kVMax + t] = first;
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per value v: exclusive prefix max of BL and exclusive suffix
+// min of BF over the blocks.
+__global__ __launch_bounds__(kTreeThreads) void k_ansv_scan(const uint32_t *__restrict__ BL,
+                                                            const uint32_t *__restrict__ BF,
+                                                            const Plan *__restrict__ plan,
+                                                            uint32_t *__restrict__ CL,
+                                                            uint32_t *__restrict__ CR) {
+  __shared__ uint32_t s[kTreeThreads];
+  __shared__ uint32_t carry;
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int v = blockIdx.x, t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < nbb; base += kTreeThreads) {
+    uint64_t b = base + t;
+    uint32_t x = b < nbb ? BL[b * kVMax + v] : 0;
+    s[t] = x;
+    __syncthreads();
+    for (int d = 1; d < kTreeThreads; d <<= 1) {
+      uint32_t o = t >= d ? s[t - d] : 0;
+      __syncthreads();
+      if (o > s[t]) s[t] = o;
+      __syncthreads();
+    }
+    uint32_t ex = t > 0 ? s[t - 1] : 0;
+    if (carry > ex) ex = carry;
+    if (b < nbb) CL[b * kVMax + v] = ex;
+    __syncthreads();
+    if (t == kTreeThreads - 1 && s[t] > carry) carry = s[t];
+    __syncthreads();
+  }
+  if (t == 0) carry = kNone32;
+  __syncthreads();
+  for (uint64_t done = 0; done < nbb; done += kTreeThreads) {
+    // process blocks from the end: slot t holds block nbb-1-(done+t)
+    uint64_t rb = done + t;
+    uint32_t x = rb < nbb ? BF[(nbb - 1 - rb) * kVMax + v] : kNone32;
+    s[t] = x;
+    __syncthreads();
+    for (int d = 1; d < kTreeThreads; d <<= 1) {
+      uint32_t o = t >= d ? s[t - d] : kNone32;
+      __syncthreads();
+      if (o < s[t]) s[t] = o;
+      __syncthreads();
+    }
+    uint32_t ex = t > 0 ? s[t - 1] : kNone32;
+    if (carry < ex) ex = carry;
+    if (rb < nbb) CR[(nbb - 1 - rb) * kVMax + v] = ex;
+    __syncthreads();
+    if (t == kTreeThreads - 1 && s[t] < carry) carry = s[t];
+    __syncthreads();
+  }
+}
+
+// Nearest strictly smaller (Ls, Rs) and smaller-or-equal (Le, Re) powers on
+// both sides of every boundary 1 <= i < r with power > 0.
+__global__ __launch_bounds__(kTreeThreads) void k_ansv_final(
+    const uint8_t *__restrict__ P, Plan *__restrict__ plan, const uint32_t *__restrict__ CL,
+    const uint32_t *__restrict__ CR, uint32_t *__restrict__ Ls, uint32_t *__restrict__ Rs,
+    uint32_t *__restrict__ Le, uint32_t *__restrict__ Re) {
+  __shared__ uint64_t sM[kTreeWaves][kVMax];
+  __shared__ uint32_t sPL[kTreeWaves][kVMax];   // last+1 in earlier waves (0 = none)
+  __shared__ uint32_t sPR[kTreeWaves][kVMax];   // first in later waves (kNone32 = none)
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
+    uint64_t i = b * kTreeThreads + t;
+    wave_masks(P, r, i, sM[w], lane);
+    __syncthreads();
+    if (t < kVMax) {
+      uint32_t last = 0;
+      for (int ww = 0; ww < kTreeWaves; ww++) {
+        sPL[ww][t] = last;
+        uint64_t mk = sM[ww][t];
+        if (mk) last = (uint32_t)(b * kTreeThreads + (uint64_t)ww * kWave + 63 - __clzll(mk)) + 1;
+      }
+      uint32_t first = kNone32;
+      for (int ww = kTreeWaves - 1; ww >= 0; ww--) {
+        sPR[ww][t] = first;
+        uint64_t mk = sM[ww][t];
+        if (mk) first = (uint32_t)(b * kTreeThreads + (uint64_t)ww * kWave + __ffsll((long long)mk) - 1);
+      }
+    }
+    __syncthreads();
+    if (i > 0 && i < r) {
+      uint32_t p = P[i];
+      if (p > 0) {
+        uint64_t below = (1ull << lane) - 1;
+        uint64_t above = ~below & ~(1ull << lane);
+        uint64_t wbase = b * kTreeThreads + (uint64_t)w * kWave;
+        uint32_t res[4];
+        for (int q = 0; q < 2; q++) {
+          int vi = (int)p - 1 + q;  // q=0: power < p (strict); q=1: power <= p
+          uint64_t mk = sM[w][vi] & below;
+          uint32_t L;
+          if (mk) L = (uint32_t)(wbase + 63 - __clzll(mk));
+          else if (sPL[w][vi]) L = sPL[w][vi] - 1;
+          else L = CL[b * kVMax + vi] - 1;
+          uint64_t mr = sM[w][vi] & above;
+          uint32_t R;
+          if (mr) R = (uint32_t)(wbase + __ffsll((long long)mr) - 1);
+          else if (sPR[w][vi] != kNone32) R = sPR[w][vi];
+          else R = CR[b * kVMax + vi];
+          if (L >= i || R <= i || R > r) {  // P[0] = P[r] = 0 make both always exist
+            atomicOr(&plan->error, 64u);
+            L = 0;
+            R = (uint32_t)r;
+          }
+          res[q * 2] = L;
+          res[q * 2 + 1] = R;
+        }
+        Ls[i] = res[0];
+        Rs[i] = res[1];
+        Le[i] = res[2];
+        Re[i] = res[3];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- nodes
+// Leader of the equal-power group containing boundary i: follow the chain of
+// nearest smaller-or-equal boundaries while the power stays equal.  A group
+// has at most k-1 members (the "m <= k-1" statement after Algorithm 1).
+__device__ inline uint32_t group_leader(const uint8_t *P, const uint32_t *Le, uint32_t i,
+                                        uint32_t *slot) {
+  uint32_t p = P[i], j = i, s = 0;
+  while (s < 64 && P[Le[j]] == p) {
+    j = Le[j];
+    s++;
+  }
+  *slot = s;
+  return j;
+}
+
+__global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
+                                               const uint32_t *__restrict__ Ls,
+                                               const uint32_t *__restrict__ Rs,
+                                               const uint32_t *__restrict__ Le,
+                                               const uint32_t *__restrict__ Re, Plan *plan, int k,
+                                               uint32_t *__restrict__ mem,
+                                               uint8_t *__restrict__ arity,
+                                               uint32_t *__restrict__ jump,
+                                               uint8_t *__restrict__ dist) {
+  const uint64_t r = plan->r;
+  for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
+       ii += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t i = (uint32_t)ii;
+    uint32_t p = P[i];
+    if (p == 0) continue;
+    uint32_t slot;
+    uint32_t lead = group_leader(P, Le, i, &slot);
+    if ((int)slot > k - 2) {
+      atomicOr(&plan->error, 1u);
+      continue;
+    }
+    mem[(uint64_t)lead * (k - 1) + slot] = i;
+    if (P[Re[i]] < p) arity[lead] = (uint8_t)(slot + 2);
+    if (slot == 0) {
+      uint32_t l = Ls[i], rr = Rs[i];
+      uint32_t pb = P[l] >= P[rr] ? l : rr;
+      if (P[pb] == 0) {
+        jump[i] = i;
+        dist[i] = 0;
+      } else {
+        uint32_t s2;
+        jump[i] = group_leader(P, Le, pb, &s2);
+        dist[i] = 1;
+      }
+    }
+  }
+}
+
+__device__ inline bool is_leader(const uint8_t *P, const uint32_t *Le, uint32_t i) {
+  uint32_t p = P[i];
+  return p > 0 && P[Le[i]] < p;
+}
+
+__global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ P,
+                                              const uint32_t *__restrict__ Le,
+                                              const Plan *__restrict__ plan,
+                                              const uint32_t *__restrict__ jin,
+                                              const uint8_t *__restrict__ din,
+                                              uint32_t *__restrict__ jout,
+                                              uint8_t *__restrict__ dout) {
+  const uint64_t r = plan->r;
+  for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
+       ii += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t i = (uint32_t)ii;
+    if (!is_leader(P, Le, i)) continue;
+    uint32_t j = jin[i];
+    dout[i] = din[i] + din[j];
+    jout[i] = jin[j];
+  }
+}
+
+// Leaf depth: run j sits between boundaries j and j+1 and hangs below the
+// node owning the larger of their powers (the leaf-depth identity in the
+// proof of Theorem 3.3); both 0 means the run is a whole segment.
+__global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
+                                                const uint32_t *__restrict__ Le,
+                                                const uint8_t *__restrict__ dist,
+                                                const uint64_t *__restrict__ rs, Plan *plan,
+                                                int want_cost, uint8_t *__restrict__ leaf_depth) {
+  const uint64_t r = plan->r;
+  uint64_t cost = 0;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < r;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t pa = P[j], pb = P[j + 1];
+    uint32_t b = pa >= pb ? (uint32_t)j : (uint32_t)(j + 1);
+    uint8_t d = 0;
+    if (P[b] > 0) {
+      uint32_t s;
+      d = (uint8_t)(dist[group_leader(P, Le, b, &s)] + 1);
+    }
+    leaf_depth[j] = d;
+    if (want_cost) cost += (uint64_t)d * (rs[j + 1] - rs[j]);
+  }
+  if (want_cost) {
+    for (int o = 32; o > 0; o >>= 1) cost += __shfl_down(cost, o);
+    if ((threadIdx.x & 63) == 0 && cost) atomicAdd((unsigned long long *)&plan->merge_cost, (unsigned long long)cost);
+  }
+}
+
+// ---------------------------------------------------------------- level lists
+// Stable counting sort of the nodes (leaders) by depth.
+__global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__restrict__ P,
+                                                            const uint32_t *__restrict__ Le,
+                                                            const uint8_t *__restrict__ dist,
+                                                            const Plan *__restrict__ plan,
+                                                            uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t sc[kMaxLevels];
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int t = threadIdx.x;
+  for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
+    if (t < kMaxLevels) sc[t] = 0;
+    __syncthreads();
+    uint64_t i = b * kTreeThreads + t;
+    if (i > 0 && i < r && is_leader(P, Le, (uint32_t)i)) atomicAdd(&sc[dist[i]], 1u);
+    __syncthreads();
+    if (t < kMaxLevels) cnt[b * kMaxLevels + t] = sc[t];
+    __syncthreads();
+  }
+}
+
+// One workgroup per depth: exclusive prefix over blocks (in place) and the total.
+__global__ __launch_bounds__(kTreeThreads) void k_lvl_scan(uint32_t *__restrict__ cnt,
+                                                           Plan *__restrict__ plan,
+                                                           uint64_t *__restrict__ totals) {
+  __shared__ uint32_t s[kTreeThreads];
+  __shared__ uint64_t carry;
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int d = blockIdx.x, t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < nbb; base += kTreeThreads) {
+    uint64_t b = base + t;
+    uint32_t x = b < nbb ? cnt[b * kMaxLevels + d] : 0;
+    s[t] = x;
+    __syncthreads();
+    for (int o = 1; o < kTreeThreads; o <<= 1) {
+      uint32_t y = t >= o ? s[t - o] : 0;
+      __syncthreads();
+      s[t] += y;
+      __syncthreads();
+    }
+    if (b < nbb) cnt[b * kMaxLevels + d] = (uint32_t)(carry + s[t] - x);
+    __syncthreads();
+    if (t == kTreeThreads - 1) carry += s[t];
+    __syncthreads();
+  }
+  if (t == 0) totals[d] = carry;
+}
+
+__global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals) {
+  if (threadIdx.x != 0) return;
+  uint64_t acc = 0;
+  uint32_t nl = 0;
+  for (int d = 0; d < kMaxLevels; d++) {
+    plan->lvl_begin[d] = acc;
+    acc += totals[d];
+    if (totals[d]) nl = d + 1;
+  }
+  plan->lvl_begin[kMaxLevels] = acc;
+  plan->n_nodes = acc;
+  plan->n_levels = nl;
+}
+
+__global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
+    const uint8_t *__restrict__ P, const uint32_t *__restrict__ Le,
+    const uint8_t *__restrict__ dist, const Plan *__restrict__ plan,
+    const uint32_t *__restrict__ cnt, uint32_t *__restrict__ list) {
+  __shared__ uint32_t sw[kTreeWaves][kMaxLevels];
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
+    uint64_t i = b * kTreeThreads + t;
+    bool lead = i > 0 && i < r && is_leader(P, Le, (uint32_t)i);
+    int myd = lead ? dist[i] : -1;
+    uint32_t rank = 0;
+    for (int d = 0; d < kMaxLevels; d++) {
+      uint64_t mk = ballot64(myd == d);
+      if (myd == d) rank = __popcll(mk & ((1ull << lane) - 1));
+      if (lane == 0) sw[w][d] = __popcll(mk);
+    }
+    __syncthreads();
+    if (t < kMaxLevels) {
+      uint32_t acc = 0;
+      for (int ww = 0; ww < kTreeWaves; ww++) {
+        uint32_t c = sw[ww][t];
+        sw[ww][t] = acc;
+        acc += c;
+      }
+    }
+    __syncthreads();
+    if (lead) {
+      uint64_t pos = plan->lvl_begin[myd] + cnt[b * kMaxLevels + myd] + sw[w][myd] + rank;
+      list[pos] = (uint32_t)i;
+    }
+    __syncthreads();
+  }
+}
+
+// Node sizes in list order (into np, scanned afterwards).
+__global__ __launch_bounds__(256) void k_node_sizes(const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ Ls,
+                                                    const uint32_t *__restrict__ Rs,
+                                                    const uint64_t *__restrict__ rs,
+                                                    const Plan *__restrict__ plan,
+                                                    uint64_t *__restrict__ np) {
+  const uint64_t nn = plan->n_nodes;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nn;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t v = list[j];
+    np[j] = rs[Rs[v]] - rs[Ls[v]];
+  }
+}
+
+// ---------------------------------------------------------------- u64 exclusive scan
+// In place over a[0..n) with n = plan->n_nodes; a[n] receives the total.
+constexpr int kScanBlk = 1024;
+
+__device__ inline uint64_t blk_incl_sum(uint64_t v, uint64_t *s) {
+  int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanBlk; o <<= 1) {
+    uint64_t y = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += y;
+    __syncthreads();
+  }
+  uint64_t r = s[t];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_scan_sums(const uint64_t *__restrict__ a,
+                                                        const Plan *__restrict__ plan,
+                                                        uint64_t *__restrict__ bsum) {
+  __shared__ uint64_t s[kScanBlk];
+  const uint64_t n = plan->n_nodes;
+  const uint64_t nb = (n + kScanBlk - 1) / kScanBlk;
+  for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    uint64_t i = b * kScanBlk + threadIdx.x;
+    uint64_t v = blk_incl_sum(i < n ? a[i] : 0, s);
+    if (threadIdx.x == kScanBlk - 1) bsum[b] = v;
+  }
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_scan_top(uint64_t *__restrict__ bsum,
+                                                       const Plan *__restrict__ plan) {
+  __shared__ uint64_t s[kScanBlk];
+  __shared__ uint64_t carry;
+  const uint64_t n = plan->n_nodes;
+  const uint64_t nb = (n + kScanBlk - 1) / kScanBlk;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < nb; base += kScanBlk) {
+    uint64_t b = base + threadIdx.x;
+    uint64_t x = b < nb ? bsum[b] : 0;
+    uint64_t inc = blk_incl_sum(x, s);
+    if (b < nb) bsum[b] = carry + inc - x;
+    __syncthreads();
+    if (threadIdx.x == kScanBlk - 1) carry += inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_scan_apply(uint64_t *__restrict__ a,
+                                                         const Plan *__restrict__ plan,
+                                                         const uint64_t *__restrict__ bsum) {
+  __shared__ uint64_t s[kScanBlk];
+  const uint64_t n = plan->n_nodes;
+  const uint64_t nb = (n + kScanBlk - 1) / kScanBlk;
+  for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    uint64_t i = b * kScanBlk + threadIdx.x;
+    uint64_t x = i < n ? a[i] : 0;
+    uint64_t inc = blk_incl_sum(x, s);
+    if (i < n) a[i] = bsum[b] + inc - x;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a[n] = bsum[nb];
+}
+
+// Per-level totals and tile counts; tile tables are laid out level after level.
+__global__ void k_lvl_tiles(Plan *plan, const uint64_t *__restrict__ np, int tile,
+                            uint64_t *__restrict__ tile_base) {
+  if (threadIdx.x != 0) return;
+  uint64_t acc = 0;
+  for (int d = 0; d < kMaxLevels; d++) {
+    uint64_t lb = plan->lvl_begin[d], le = plan->lvl_begin[d + 1];
+    uint64_t tot = np[le] - np[lb];
+    plan->lvl_total[d] = tot;
+    uint64_t tiles = (tot + tile - 1) / tile;
+    plan->lvl_tiles[d] = tiles;
+    tile_base[d] = acc;
+    acc += tiles + 1;
+  }
+  tile_base[kMaxLevels] = acc;
+}
+
+// Tile -> node map: every node j of level d writes its index for the tile
+// boundaries t*tile that fall inside it (t*tile in [np_j, np_{j+1})).
+__global__ __launch_bounds__(256) void k_tile_map(const uint64_t *__restrict__ np,
+                                                  const Plan *__restrict__ plan, int tile,
+                                                  const uint64_t *__restrict__ tile_base,
+                                                  uint32_t *__restrict__ tj) {
+  const uint64_t nn = plan->n_nodes;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nn;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    int d = 0;
+    while (plan->lvl_begin[d + 1] <= g) d++;
+    uint64_t lb = plan->lvl_begin[d];
+    uint64_t a = np[g] - np[lb], e = np[g + 1] - np[lb];
+    uint64_t t0 = (a + tile - 1) / tile, t1 = (e + tile - 1) / tile;
+    for (uint64_t t = t0; t < t1; t++) tj[tile_base[d] + t] = (uint32_t)(g - lb);
+    if (g + 1 == plan->lvl_begin[d + 1]) {
+      // closing entry: boundary at (or past) the level end
+      uint64_t tiles = plan->lvl_tiles[d];
+      tj[tile_base[d] + tiles] = (uint32_t)(g + 1 - lb);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host side
+hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
+                       uint32_t *tj, unsigned gtree, hipStream_t s) {
+  const dim3 g256(1024), b256(256);
+  hipLaunchKernelGGL(k_powers, g256, b256, 0, s, w.run_start, w.off, w.m, w.plan, w.logk, w.power);
+  hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
+  hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
+  hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);
+  hipLaunchKernelGGL(k_nodes, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0);
+  for (int round = 0; round < 6; round++) {  // depths < 64
+    bool even = (round & 1) == 0;
+    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.power, w.Le, w.plan, even ? w.jump0 : w.jump1,
+                       even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0, even ? w.dist1 : w.dist0);
+  }
+  hipLaunchKernelGGL(k_leaves, g256, b256, 0, s, w.power, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.leaf_depth);
+  hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.plan, w.lvl_cnt);
+  hipLaunchKernelGGL(k_lvl_scan, dim3(kMaxLevels), dim3(kTreeThreads), 0, s, w.lvl_cnt, w.plan, lvl_tot);
+  hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot);
+  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.plan, w.lvl_cnt, w.lvl_list);
+  hipLaunchKernelGGL(k_node_sizes, g256, b256, 0, s, w.lvl_list, w.Ls, w.Rs, w.run_start, w.plan, w.lvl_np);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
+  hipLaunchKernelGGL(k_scan_apply, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
+  hipLaunchKernelGGL(k_lvl_tiles, dim3(1), dim3(64), 0, s, w.plan, w.lvl_np, kTileSize, tile_base);
+  hipLaunchKernelGGL(k_tile_map, g256, b256, 0, s, w.lvl_np, w.plan, kTileSize, tile_base, tj);
+  return hipGetLastError();
+}
+
+}  // namespace mps

@@ -1,0 +1,59 @@
+"""The C-ABI library (no GPU needed): it loads, exports every function that
+include/mps.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2209_06909_amd as mps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mps.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mps_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mps.lib()
+    names = declared_functions()
+    assert "mps_sort" in names and "mps_sort_batched" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(mps.EXPORTED)
+
+
+def test_workspace_bytes_host_logic():
+    lib = mps.lib()
+    a = lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 1, 4)
+    b = lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I64, 1, 4)
+    c = lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 0, 4)
+    assert a > 0 and b > a and c < a
+    assert lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 1, 3) == 0   # k must be 2, 4 or 8
+    assert lib.mps_workspace_bytes(1 << 20, 1, 7, 1, 4) == 0             # unknown key type
+    # the ping-pong buffer alone is n*(key+payload) bytes
+    assert b >= (1 << 20) * 12
+
+
+def test_argument_errors_need_no_gpu():
+    lib = mps.lib()
+    assert lib.mps_sort(None, mps.KEY_I32, None, 10, None) == -1           # keys NULL, n > 0
+    assert b"NULL" in lib.mps_last_error()
+    assert lib.mps_sort(None, 9, None, 10, None) == -1                     # bad key type
+    fake = ctypes.c_void_p(1 << 40)                                        # never dereferenced
+    assert lib.mps_sort(fake, mps.KEY_I32, None, (1 << 31) + 1, None) == -4
+    opts = mps._Opts(k=3)
+    assert lib.mps_sort_ex(fake, mps.KEY_I32, None, 100, ctypes.byref(opts), None, None) == -4
+    assert lib.mps_sort(fake, mps.KEY_I32, None, 1, None) == 0            # n <= 1 is a no-op
+    assert lib.mps_sort(fake, mps.KEY_I32, None, 0, None) == 0
+    # batched: bad host offsets are rejected before any launch
+    off = (ctypes.c_uint64 * 3)(0, 5, 4)
+    assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 2, 4, None, None, None) == -1
+    off = (ctypes.c_uint64 * 3)(0, 3, 7)
+    assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 2, 8, None, None, None) == -1
+    off = (ctypes.c_uint64 * 2)(0, (1 << 31) + 5)
+    assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 1, (1 << 31) + 5, None, None,
+                                None) == -4
