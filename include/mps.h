@@ -47,10 +47,14 @@ typedef enum {
 
 typedef enum { MPS_I32 = 0, MPS_I64 = 1, MPS_F32 = 2 } mps_key_type;
 
+/* Option flags (mps_opts.flags). */
+#define MPS_OPT_TIME_LEVELS 1u  /* record HIP events around every level's co-rank and merge
+                                   launches (read them with mps_last_level_stats) */
+
 /* Options.  All fields may be zero for defaults. */
 typedef struct {
     uint32_t k;                 /* merge arity: 2, 4 (default, the paper's 4-way) or 8 */
-    uint32_t reserved;
+    uint32_t flags;             /* MPS_OPT_* bits */
     void *workspace;            /* device memory of >= mps_workspace_bytes(); NULL: the
                                    library allocates and caches one per device */
     uint64_t workspace_bytes;
@@ -117,6 +121,16 @@ int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload, const uint6
  * caller learn r and n_nodes first and size the host arrays afterwards.
  * Synchronises the device.  MPS_E_NOTFOUND if no such sort exists. */
 int mps_trace_fetch(const void *workspace, mps_trace *trace);
+
+/* Per-level figures of the most recent sort on the current device that was
+ * run with MPS_OPT_TIME_LEVELS: the number of merge levels, and for each
+ * level d < min(cap, n_levels) the number of elements its merges output
+ * (the level's share of the merge cost, Section 2.3) and the durations of
+ * its co-rank and merge launches in milliseconds (HIP events on the sort's
+ * stream).  Any output pointer may be NULL.  Waits for that sort to finish.
+ * MPS_E_NOTFOUND if there was no such sort. */
+int mps_last_level_stats(uint32_t cap, uint32_t *n_levels, uint64_t *level_elems,
+                         float *corank_ms, float *merge_ms);
 
 /* Message describing the last error of the calling thread ("" if none). */
 const char *mps_last_error(void);

@@ -29,7 +29,8 @@ _STATUS = {-1: "MPS_E_INVALID", -2: "MPS_E_NOMEM", -3: "MPS_E_HIP", -4: "MPS_E_U
 KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
 
 EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
-            "mps_sort_ex", "mps_sort_batched", "mps_trace_fetch", "mps_last_error"]
+            "mps_sort_ex", "mps_sort_batched", "mps_trace_fetch", "mps_last_level_stats",
+            "mps_last_error"]
 
 
 class MpsError(RuntimeError):
@@ -38,8 +39,11 @@ class MpsError(RuntimeError):
         self.code = code
 
 
+OPT_TIME_LEVELS = 1
+
+
 class _Opts(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    _fields_ = [("k", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
 
 
@@ -66,6 +70,12 @@ def lib() -> ctypes.CDLL:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is missing; build it with "
                                   "`python -m paper_2209_06909_amd.build`")
+            # torch ships its own HIP runtime; load it first so that libmps binds to
+            # that same runtime (its libamdhip64 soname) instead of bringing in a second one.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             l = ctypes.CDLL(LIB_PATH)
             P, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
             l.mps_workspace_bytes.argtypes = [u64, u64, i32, i32, u32]
@@ -82,6 +92,8 @@ def lib() -> ctypes.CDLL:
             l.mps_sort_batched.restype = i32
             l.mps_trace_fetch.argtypes = [P, ctypes.POINTER(_Trace)]
             l.mps_trace_fetch.restype = i32
+            l.mps_last_level_stats.argtypes = [u32, P, P, P, P]
+            l.mps_last_level_stats.restype = i32
             l.mps_last_error.argtypes = []
             l.mps_last_error.restype = ctypes.c_char_p
             _lib = l
@@ -197,7 +209,7 @@ def _stream_ptr(device, stream):
 
 
 def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
-         stream=None):
+         stream=None, time_levels: bool = False):
     """Stable multiway Powersort of a 1-D GPU tensor, in place.
 
     keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
@@ -212,7 +224,8 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
-    opts = _Opts(k=k, reserved=0, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
+    opts = _Opts(k=k, flags=OPT_TIME_LEVELS if time_levels else 0, workspace=ws.data_ptr(),
+                 workspace_bytes=ws.numel())
     t = _Trace() if trace else None
     _check(lib().mps_sort_ex(ctypes.c_void_p(keys.data_ptr()), kt,
                              ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
@@ -260,7 +273,7 @@ def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
-    opts = _Opts(k=k, reserved=0, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
+    opts = _Opts(k=k, flags=0, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
     t = _Trace() if trace else None
     _check(lib().mps_sort_batched(
         ctypes.c_void_p(keys.data_ptr()), kt,
@@ -272,3 +285,16 @@ def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
     if t is None:
         return None
     return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)
+
+
+def level_stats(cap: int = 64):
+    """Per-level (merged elements, co-rank ms, merge ms) of the last sort run with
+    time_levels=True on the current device; waits for it to finish."""
+    nl = ctypes.c_uint32(0)
+    elems = np.zeros(cap, np.uint64)
+    cms = np.zeros(cap, np.float32)
+    mms = np.zeros(cap, np.float32)
+    _check(lib().mps_last_level_stats(cap, ctypes.byref(nl), elems.ctypes.data, cms.ctypes.data,
+                                      mms.ctypes.data))
+    n = min(int(nl.value), cap)
+    return elems[:n].copy(), cms[:n].copy(), mms[:n].copy()

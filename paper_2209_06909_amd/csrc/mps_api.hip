@@ -245,6 +245,15 @@ int fill_trace(void *base, mps_trace *tr) {
 
 void *g_last_base[64];  // library-managed workspace base per device (for mps_trace_fetch)
 
+// Per-device record of the last sort that asked for level timing.
+struct LevelTiming {
+  std::vector<hipEvent_t> ev;  // 3 per level: before co-rank, before merge, after merge
+  int levels = 0;
+  void *base = nullptr;        // its workspace (holds the plan)
+};
+std::mutex g_time_mu;
+LevelTiming g_time[64];
+
 int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint64_t m,
              uint64_t N, const mps_opts *opts, mps_trace *trace, hipStream_t s) {
   uint32_t k = opts ? opts->k : 0;
@@ -317,6 +326,21 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   HIP_TRY(launch_tree(w, trace ? 1 : 0, lvl_tot, tile_base, tj, gtree, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_place(kt, keys, payload, w, s));
+  LevelTiming *tm = nullptr;
+  if (opts && (opts->flags & MPS_OPT_TIME_LEVELS)) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    tm = &g_time[dev];
+    while (tm->ev.size() < (size_t)L.levels * 3) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      tm->ev.push_back(e);
+    }
+    tm->levels = L.levels;
+    tm->base = base;
+  }
   for (int d = L.levels - 1; d >= 0; d--) {
     LevelArgs a;
     bool out_user = (d & 1) == 0;
@@ -324,7 +348,12 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
     a.in_vals = payload ? (out_user ? w.alt_vals : payload) : nullptr;
     a.out_keys = out_user ? keys : w.alt_keys;
     a.out_vals = payload ? (out_user ? payload : w.alt_vals) : nullptr;
-    HIP_TRY(launch_level(kt, a, w, tj, tile_base, d, s));
+    if (tm) {
+      HIP_TRY(launch_level_timed(kt, a, w, tj, tile_base, d, s, tm->ev[3 * d], tm->ev[3 * d + 1],
+                                 tm->ev[3 * d + 2]));
+    } else {
+      HIP_TRY(launch_level(kt, a, w, tj, tile_base, d, s));
+    }
   }
   if (!(opts && opts->workspace)) {
     int dev = 0;
@@ -424,4 +453,29 @@ extern "C" int mps_trace_fetch(const void *workspace, mps_trace *trace) {
     base = g_last_base[dev];
   }
   return fill_trace(base, trace);
+}
+
+extern "C" int mps_last_level_stats(uint32_t cap, uint32_t *n_levels, uint64_t *level_elems,
+                                    float *corank_ms, float *merge_ms) {
+  g_err.clear();
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_time_mu);
+  LevelTiming &tm = g_time[dev];
+  if (!tm.base || tm.levels == 0) return fail(MPS_E_NOTFOUND, "no timed sort on this device");
+  Plan plan;
+  HIP_TRY(hipEventSynchronize(tm.ev[2]));  // level 0's merge is the last launch
+  HIP_TRY(hipMemcpy(&plan, tm.base, sizeof(Plan), hipMemcpyDeviceToHost));
+  uint32_t nl = plan.n_levels;
+  if (n_levels) *n_levels = nl;
+  for (uint32_t d = 0; d < nl && d < cap && d < (uint32_t)tm.levels; d++) {
+    if (level_elems) level_elems[d] = plan.lvl_total[d];
+    float a = 0, b = 0;
+    HIP_TRY(hipEventElapsedTime(&a, tm.ev[3 * d], tm.ev[3 * d + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, tm.ev[3 * d + 1], tm.ev[3 * d + 2]));
+    if (corank_ms) corank_ms[d] = a;
+    if (merge_ms) merge_ms[d] = b;
+  }
+  return MPS_OK;
 }

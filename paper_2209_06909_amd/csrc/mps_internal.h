@@ -146,5 +146,10 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                         const uint64_t *tile_base, int level, hipStream_t s);
+// Same, with events recorded before the co-rank, between co-rank and merge,
+// and after the merge launch (all on stream s).
+hipError_t launch_level_timed(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                              const uint64_t *tile_base, int level, hipStream_t s,
+                              hipEvent_t e0, hipEvent_t e1, hipEvent_t e2);
 
 }  // namespace mps

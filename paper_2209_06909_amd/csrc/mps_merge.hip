@@ -442,33 +442,49 @@ constexpr int kTile = kTileSize;
 
 template <int KT, int K>
 static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
-                           const uint64_t *tile_base, int level, hipStream_t s) {
+                           const uint64_t *tile_base, int level, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1, hipEvent_t e2) {
   using U = typename Key<KT>::U;
   unsigned gc = 1024, gm = 4096;
+  if (e0) (void)hipEventRecord(e0, s);
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
                      tile_base, w.plan, level, kTile, w.corank);
+  if (e1) (void)hipEventRecord(e1, s);
   hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads>), dim3(gm), dim3(kMergeThreads), 0, s,
                      (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals, w.run_start,
                      w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base,
                      w.plan, level, w.corank);
+  if (e2) (void)hipEventRecord(e2, s);
+}
+
+static hipError_t dispatch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                                 const uint64_t *tile_base, int level, hipStream_t s,
+                                 hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+  switch (w.k * 4 + kt) {
+    case 2 * 4 + 0: launch_level_t<0, 2>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 2 * 4 + 1: launch_level_t<1, 2>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 2 * 4 + 2: launch_level_t<2, 2>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 4 * 4 + 0: launch_level_t<0, 4>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 4 * 4 + 1: launch_level_t<1, 4>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 4 * 4 + 2: launch_level_t<2, 4>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 8 * 4 + 0: launch_level_t<0, 8>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 8 * 4 + 1: launch_level_t<1, 8>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 8 * 4 + 2: launch_level_t<2, 8>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_level_timed(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                              const uint64_t *tile_base, int level, hipStream_t s,
+                              hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+  return dispatch_level(kt, a, w, tj, tile_base, level, s, e0, e1, e2);
 }
 
 hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                         const uint64_t *tile_base, int level, hipStream_t s) {
-  switch (w.k * 4 + kt) {
-    case 2 * 4 + 0: launch_level_t<0, 2>(a, w, tj, tile_base, level, s); break;
-    case 2 * 4 + 1: launch_level_t<1, 2>(a, w, tj, tile_base, level, s); break;
-    case 2 * 4 + 2: launch_level_t<2, 2>(a, w, tj, tile_base, level, s); break;
-    case 4 * 4 + 0: launch_level_t<0, 4>(a, w, tj, tile_base, level, s); break;
-    case 4 * 4 + 1: launch_level_t<1, 4>(a, w, tj, tile_base, level, s); break;
-    case 4 * 4 + 2: launch_level_t<2, 4>(a, w, tj, tile_base, level, s); break;
-    case 8 * 4 + 0: launch_level_t<0, 8>(a, w, tj, tile_base, level, s); break;
-    case 8 * 4 + 1: launch_level_t<1, 8>(a, w, tj, tile_base, level, s); break;
-    case 8 * 4 + 2: launch_level_t<2, 8>(a, w, tj, tile_base, level, s); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return dispatch_level(kt, a, w, tj, tile_base, level, s, nullptr, nullptr, nullptr);
 }
 
 }  // namespace mps
