@@ -87,6 +87,7 @@ struct Work {
   uint64_t *lvl_np;                  // [rmax+1] exclusive prefix of node sizes
   uint64_t *scan_tmp;                // [nbb + 1024]
   uint32_t *corank;                  // [(N/tile + 2) * k]
+  void *tile_desc;                   // [(N/tile + 2)] per-tile merge descriptors
   Plan *plan;
 };
 
@@ -139,6 +140,7 @@ struct LevelArgs {
 };
 
 constexpr int kTileSize = 2048;   // outputs per merge tile
+constexpr int kTileDescBytes = 256;  // >= sizeof(TileDesc<8>)
 
 hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s);
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,

@@ -209,6 +209,103 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
 }
 
 // ---------------------------------------------------------------- tile merge
+// A tile covers output positions [Q0, Q1) of the level's node concatenation;
+// j0/j1 are the first and last node it touches.
+struct TileGeom {
+  uint64_t Q0, Q1, j0, j1;
+  bool ok;
+};
+
+__device__ inline TileGeom tile_geom(uint64_t tile, int tsize, uint64_t L, uint64_t nlev,
+                                     const uint64_t *np, uint64_t lb, uint64_t np0,
+                                     const uint32_t *tjl) {
+  TileGeom g;
+  g.Q0 = tile * (uint64_t)tsize;
+  g.Q1 = g.Q0 + tsize < L ? g.Q0 + tsize : L;
+  g.j0 = tjl[tile];
+  if (g.Q1 == L) {
+    g.j1 = nlev - 1;
+  } else {
+    uint64_t jn = tjl[tile + 1];
+    g.j1 = (jn < nlev && np[lb + jn] - np0 == g.Q1) ? jn - 1 : jn;
+  }
+  g.ok = g.j0 <= g.j1 && g.j1 < nlev;
+  return g;
+}
+
+// Per-tile descriptor for tiles that touch at most two nodes (the common case
+// once nodes are larger than a tile): global start and length of every input
+// slice and the output start of every piece, so that the merge kernel does not
+// chase node records through dependent global loads.
+template <int K>
+struct TileDesc {
+  uint64_t out[2];
+  uint64_t src[2][K];
+  uint32_t len[2][K];
+  uint32_t d[2];
+  uint32_t npieces;   // 1 or 2: use this descriptor; 0: general setup; kBadTile: inconsistent
+  uint32_t total;
+};
+constexpr uint32_t kBadTile = 0xFFFFFFFFu;
+static_assert(sizeof(TileDesc<8>) <= kTileDescBytes, "tile descriptor slot too small");
+
+template <int K>
+__global__ __launch_bounds__(256) void k_tile_desc(
+    const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
+    const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
+    const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
+    const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
+    const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level, int tsize,
+    const uint32_t *__restrict__ cr, TileDesc<K> *__restrict__ desc) {
+  const uint64_t tiles = plan->lvl_tiles[level];
+  if (tiles == 0) return;
+  const uint64_t r = plan->r;
+  const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
+  const uint64_t nlev = le - lb;
+  const uint64_t np0 = np[lb];
+  const uint64_t L = np[le] - np0;
+  const uint32_t *tjl = tj + tile_base[level];
+  for (uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; tile < tiles;
+       tile += (uint64_t)gridDim.x * blockDim.x) {
+    TileDesc<K> D;
+    TileGeom g = tile_geom(tile, tsize, L, nlev, np, lb, np0, tjl);
+    D.total = (uint32_t)(g.Q1 - g.Q0);
+    D.npieces = 0;
+    for (int p = 0; p < 2; p++) {
+      D.out[p] = 0;
+      D.d[p] = 0;
+      for (int j = 0; j < K; j++) { D.src[p][j] = 0; D.len[p][j] = 0; }
+    }
+    if (!g.ok) {
+      D.npieces = kBadTile;
+    } else if (g.j1 - g.j0 + 1 <= 2) {
+      const int P = (int)(g.j1 - g.j0 + 1);
+      uint64_t sum = 0;
+      bool bad = false;
+      for (int p = 0; p < P && !bad; p++) {
+        uint64_t j = g.j0 + p;
+        NodeIn nd;
+        if (!load_node<K>(list[lb + j], r, rs, Ls, Rs, mem, arity, nd)) { bad = true; break; }
+        bool first = p == 0;
+        bool cut_end = p == P - 1 && g.Q1 < np[lb + j + 1] - np0;
+        D.d[p] = (uint32_t)nd.d;
+        D.out[p] = nd.c[0] + (first ? g.Q0 - (np[lb + j] - np0) : 0);
+        for (int jj = 0; jj < nd.d; jj++) {
+          uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
+          uint32_t c0 = first ? cr[tile * K + jj] : 0;
+          uint32_t c1 = cut_end ? cr[(tile + 1) * K + jj] : len;
+          if (c1 > len || c0 > c1) { bad = true; break; }
+          D.src[p][jj] = nd.c[jj] + c0;
+          D.len[p][jj] = c1 - c0;
+          sum += c1 - c0;
+        }
+      }
+      D.npieces = (bad || sum != D.total) ? kBadTile : (uint32_t)P;
+    }
+    desc[tile] = D;
+  }
+}
+
 template <typename O, int K, int TILE>
 struct MergeSmem {
   static constexpr int kMaxSlices = TILE + 2 * K + 2;
@@ -222,7 +319,7 @@ struct MergeSmem {
   uint16_t pc_loff[kMaxPieces];
   uint16_t pc_sl[kMaxPieces];
   uint64_t scan[256];
-  uint64_t misc[8];
+  int misc[8];
 };
 
 template <typename T>
@@ -236,6 +333,8 @@ __device__ inline int ub16(const uint16_t *a, int n, T x) {
   return lo;
 }
 
+constexpr int kFewSlices = 2 * 8 + 1;   // loop over slices/pieces instead of searching
+
 template <int KT, int K, int TILE, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_merge(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
@@ -245,12 +344,13 @@ __global__ __launch_bounds__(THREADS) void k_merge(
     const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
     const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
     const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level,
-    const uint32_t *__restrict__ cr) {
+    const uint32_t *__restrict__ cr, const TileDesc<K> *__restrict__ desc) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
+  using SM = MergeSmem<O, K, TILE>;
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
-  __shared__ MergeSmem<O, K, TILE> sm;
+  __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
   uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
   O *kB = reinterpret_cast<O *>(sm.bufB);
@@ -262,111 +362,158 @@ __global__ __launch_bounds__(THREADS) void k_merge(
   if (tiles == 0) return;
   const uint64_t rr_total = plan->r;
   const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
+  const uint64_t nlev = le - lb;
   const uint64_t np0 = np[lb];
   const uint64_t L = np[le] - np0;
   const uint32_t *tjl = tj + tile_base[level];
   const int t = threadIdx.x;
 
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const uint64_t Q0 = tile * TILE;
-    const uint64_t Q1 = Q0 + TILE < L ? Q0 + TILE : L;
-    const int Tt = (int)(Q1 - Q0);
-    const uint64_t j0 = tjl[tile];
-    uint64_t j1;
-    {
-      uint64_t jn = tjl[tile + 1];
-      if (Q1 == L) j1 = (le - lb) - 1;
-      else j1 = (np[lb + jn] - np0 == Q1) ? jn - 1 : jn;
-    }
-    const int P = (int)(j1 - j0 + 1);
-    if (t == 0) sm.misc[0] = 0;
-    __syncthreads();
-    if (j1 < j0 || j1 >= le - lb || P + 1 > MergeSmem<O, K, TILE>::kMaxPieces) {  // cannot happen: pieces hold >= 2 keys
-      if (t == 0) atomicOr(&plan->error, 16u);
-      continue;
-    }
-
-    // ---- piece and slice tables
-    uint64_t carry_len = 0, carry_sl = 0;
-    for (int pbase = 0; pbase < P; pbase += THREADS) {
-      int p = pbase + t;
-      NodeIn nd;
-      uint32_t c0[K], c1[K];
-      uint64_t plen = 0;
-      int pd = 0;
-      if (p < P) {
-        uint64_t j = j0 + p;
-        if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
-          sm.misc[0] = 1;
-          nd.d = 2;
-          nd.c[0] = nd.c[1] = nd.c[2] = 0;
-        }
-        pd = nd.d;
-        bool first = p == 0, last = p == P - 1;
-        bool cut_end = last && Q1 < np[lb + j + 1] - np0;
-        for (int jj = 0; jj < K; jj++) {
-          if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
-          uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
-          c0[jj] = first ? cr[tile * K + jj] : 0;
-          c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
-          if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
-            sm.misc[0] = 1;
-            c0[jj] = c1[jj] = 0;
+    // ---- setup: piece and slice tables in LDS
+    if (t == 0) {
+      const TileDesc<K> &D = desc[tile];
+      uint32_t np_ = D.npieces;
+      sm.misc[0] = np_ == kBadTile ? 1 : 0;
+      sm.misc[1] = (int)D.total;
+      sm.misc[2] = np_ == kBadTile ? 0 : (int)np_;   // pieces (0: general setup below)
+      if (np_ == 1 || np_ == 2) {
+        int s = 0, off = 0;
+        for (int p = 0; p < (int)np_; p++) {
+          sm.pc_loff[p] = (uint16_t)off;
+          sm.pc_sl[p] = (uint16_t)s;
+          sm.pc_out[p] = D.out[p];
+          for (int j = 0; j < (int)D.d[p]; j++) {
+            sm.sl_off[s] = (uint16_t)off;
+            sl_g[s] = D.src[p][j];
+            off += (int)D.len[p][j];
+            s++;
           }
-          plen += c1[jj] - c0[jj];
         }
+        sm.pc_loff[np_] = (uint16_t)off;
+        sm.pc_sl[np_] = (uint16_t)s;
+        sm.sl_off[s] = (uint16_t)off;
+        sm.misc[3] = s;
       }
-      // block exclusive scan of (plen, pd) packed: high 32 bits slices, low 32 bits length
-      uint64_t packed = ((uint64_t)pd << 32) | plen;
-      sm.scan[t] = packed;
-      __syncthreads();
-      for (int o = 1; o < THREADS; o <<= 1) {
-        uint64_t y = t >= o ? sm.scan[t - o] : 0;
-        __syncthreads();
-        sm.scan[t] += y;
-        __syncthreads();
-      }
-      uint64_t ex = sm.scan[t] - packed;
-      uint64_t tot = sm.scan[THREADS - 1];
-      __syncthreads();
-      if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
-          carry_sl + (ex >> 32) + pd < (uint64_t)MergeSmem<O, K, TILE>::kMaxSlices) {
-        uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
-        uint64_t sl0 = carry_sl + (ex >> 32);
-        sm.pc_loff[p] = (uint16_t)loff;
-        sm.pc_sl[p] = (uint16_t)sl0;
-        sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
-        uint64_t acc = loff;
-        for (int jj = 0; jj < pd; jj++) {
-          sm.sl_off[sl0 + jj] = (uint16_t)acc;
-          sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
-          acc += c1[jj] - c0[jj];
-        }
-      }
-      carry_len += tot & 0xFFFFFFFFull;
-      carry_sl += tot >> 32;
     }
-    const int S = (int)carry_sl;
-    if (carry_len != (uint64_t)Tt || S + 1 > MergeSmem<O, K, TILE>::kMaxSlices) sm.misc[0] = 1;
     __syncthreads();
-    if (sm.misc[0]) {  // the tile's co-ranks do not add up: flag it and leave the tile alone
+    if (sm.misc[0]) {
       if (t == 0) atomicOr(&plan->error, 32u);
       __syncthreads();
       continue;
     }
-    if (t == 0) {
-      sm.pc_loff[P] = (uint16_t)Tt;
-      sm.pc_sl[P] = (uint16_t)S;
-      sm.sl_off[S] = (uint16_t)Tt;
+    const int Tt = sm.misc[1];
+    int P = sm.misc[2];
+    int S = sm.misc[3];
+    if (P == 0) {
+      // general setup: the tile spans many small nodes
+      TileGeom g = tile_geom(tile, TILE, L, nlev, np, lb, np0, tjl);
+      P = (int)(g.j1 - g.j0 + 1);
+      if (!g.ok || P + 1 > SM::kMaxPieces) {
+        if (t == 0) atomicOr(&plan->error, 16u);
+        __syncthreads();
+        continue;
+      }
+      const uint64_t Q0 = g.Q0, Q1 = g.Q1, j0 = g.j0;
+      uint64_t carry_len = 0, carry_sl = 0;
+      if (t == 0) sm.misc[4] = 0;
+      __syncthreads();
+      for (int pbase = 0; pbase < P; pbase += THREADS) {
+        int p = pbase + t;
+        NodeIn nd;
+        uint32_t c0[K], c1[K];
+        uint64_t plen = 0;
+        int pd = 0;
+        if (p < P) {
+          uint64_t j = j0 + p;
+          if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
+            sm.misc[4] = 1;
+            nd.d = 2;
+            nd.c[0] = nd.c[1] = nd.c[2] = 0;
+          }
+          pd = nd.d;
+          bool first = p == 0, last = p == P - 1;
+          bool cut_end = last && Q1 < np[lb + j + 1] - np0;
+          for (int jj = 0; jj < K; jj++) {
+            if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
+            uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
+            c0[jj] = first ? cr[tile * K + jj] : 0;
+            c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
+            if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
+              sm.misc[4] = 1;
+              c0[jj] = c1[jj] = 0;
+            }
+            plen += c1[jj] - c0[jj];
+          }
+        }
+        uint64_t packed = ((uint64_t)pd << 32) | plen;
+        sm.scan[t] = packed;
+        __syncthreads();
+        for (int o = 1; o < THREADS; o <<= 1) {
+          uint64_t y = t >= o ? sm.scan[t - o] : 0;
+          __syncthreads();
+          sm.scan[t] += y;
+          __syncthreads();
+        }
+        uint64_t ex = sm.scan[t] - packed;
+        uint64_t tot = sm.scan[THREADS - 1];
+        __syncthreads();
+        if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
+            carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
+          uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
+          uint64_t sl0 = carry_sl + (ex >> 32);
+          sm.pc_loff[p] = (uint16_t)loff;
+          sm.pc_sl[p] = (uint16_t)sl0;
+          sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
+          uint64_t acc = loff;
+          for (int jj = 0; jj < pd; jj++) {
+            sm.sl_off[sl0 + jj] = (uint16_t)acc;
+            sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
+            acc += c1[jj] - c0[jj];
+          }
+        }
+        carry_len += tot & 0xFFFFFFFFull;
+        carry_sl += tot >> 32;
+      }
+      S = (int)carry_sl;
+      if (carry_len != (uint64_t)Tt || S + 1 > SM::kMaxSlices) sm.misc[4] = 1;
+      __syncthreads();
+      if (sm.misc[4]) {  // the tile's co-ranks do not add up: flag it and leave it alone
+        if (t == 0) atomicOr(&plan->error, 32u);
+        __syncthreads();
+        continue;
+      }
+      if (t == 0) {
+        sm.pc_loff[P] = (uint16_t)Tt;
+        sm.pc_sl[P] = (uint16_t)S;
+        sm.sl_off[S] = (uint16_t)Tt;
+      }
+      __syncthreads();
     }
-    __syncthreads();
 
-    // ---- stage the tile's inputs in LDS
-    for (int e = t; e < Tt; e += THREADS) {
-      int s = ub16(sm.sl_off, S + 1, e) - 1;
-      uint64_t g = sl_g[s] + (uint64_t)(e - sm.sl_off[s]);
-      kA[e] = Kt::ord(in_keys[g]);
-      if (has_vals) vA[e] = in_vals[g];
+    // ---- stage the tile's inputs in LDS (key order-mapped).  Every thread
+    // first issues all of its E global loads, then writes LDS, so the load
+    // latency is paid once per tile rather than once per element.
+    {
+      O kreg[E];
+      uint32_t vreg[E];
+#pragma unroll
+      for (int i = 0; i < E; i++) {
+        int e = t + i * THREADS;
+        if (e < Tt) {
+          int s = ub16(sm.sl_off, S + 1, e) - 1;
+          uint64_t g = sl_g[s] + (uint64_t)(e - sm.sl_off[s]);
+          kreg[i] = in_keys[g];
+          vreg[i] = has_vals ? in_vals[g] : 0u;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < E; i++) {
+        int e = t + i * THREADS;
+        if (e < Tt) {
+          kA[e] = Kt::ord(kreg[i]);
+          if (has_vals) vA[e] = vreg[i];
+        }
+      }
     }
     __syncthreads();
 
@@ -397,12 +544,19 @@ __global__ __launch_bounds__(THREADS) void k_merge(
         int ia = u0 + lo, ib = u1 + diag - lo;
         int stop = e_end < u2 ? e_end : u2;
         if (stop <= e) break;  // cannot happen with valid tables (e < u2)
+        // heads kept in registers; one LDS key load per output
+        O ka = ks[ia < TILE ? ia : TILE - 1];
+        O kb = ks[ib < TILE ? ib : TILE - 1];
         for (; e < stop; e++) {
-          bool takeL = ib >= u2 || (ia < u1 && ks[ia] <= ks[ib]);
+          bool takeL = ib >= u2 || (ia < u1 && ka <= kb);
           int src = takeL ? ia : ib;
-          kd[e] = ks[src];
+          kd[e] = takeL ? ka : kb;
           if (has_vals) vd[e] = vs[src];
-          if (takeL) ia++; else ib++;
+          ia += takeL ? 1 : 0;
+          ib += takeL ? 0 : 1;
+          int nx = takeL ? ia : ib;
+          O kn = ks[nx < TILE ? nx : TILE - 1];
+          if (takeL) ka = kn; else kb = kn;
         }
       }
       __syncthreads();
@@ -410,12 +564,16 @@ __global__ __launch_bounds__(THREADS) void k_merge(
       uint32_t *tv = vs; vs = vd; vd = tv;
     }
 
-    // ---- write back
-    for (int e = t; e < Tt; e += THREADS) {
-      int p = ub16(sm.pc_loff, P + 1, e) - 1;
-      uint64_t g = sm.pc_out[p] + (uint64_t)(e - sm.pc_loff[p]);
-      out_keys[g] = Kt::unord(ks[e]);
-      if (has_vals) out_vals[g] = vs[e];
+    // ---- write back (coalesced per piece)
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      int e = t + i * THREADS;
+      if (e < Tt) {
+        int p = P == 1 ? 0 : ub16(sm.pc_loff, P + 1, e) - 1;
+        uint64_t g = sm.pc_out[p] + (uint64_t)(e - sm.pc_loff[p]);
+        out_keys[g] = Kt::unord(ks[e]);
+        if (has_vals) out_vals[g] = vs[e];
+      }
     }
     __syncthreads();
   }
@@ -445,16 +603,20 @@ static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj
                            const uint64_t *tile_base, int level, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1, hipEvent_t e2) {
   using U = typename Key<KT>::U;
-  unsigned gc = 1024, gm = 4096;
+  unsigned gc = 512, gm = 4096;
   if (e0) (void)hipEventRecord(e0, s);
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
                      tile_base, w.plan, level, kTile, w.corank);
+  TileDesc<K> *desc = reinterpret_cast<TileDesc<K> *>(w.tile_desc);
+  hipLaunchKernelGGL((k_tile_desc<K>), dim3(gc), dim3(256), 0, s, w.run_start, w.Ls, w.Rs,
+                     w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level,
+                     kTile, w.corank, desc);
   if (e1) (void)hipEventRecord(e1, s);
   hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads>), dim3(gm), dim3(kMergeThreads), 0, s,
                      (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals, w.run_start,
                      w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base,
-                     w.plan, level, w.corank);
+                     w.plan, level, w.corank, desc);
   if (e2) (void)hipEventRecord(e2, s);
 }
 

@@ -523,26 +523,32 @@ __global__ void k_lvl_tiles(Plan *plan, const uint64_t *__restrict__ np, int til
   tile_base[kMaxLevels] = acc;
 }
 
-// Tile -> node map: every node j of level d writes its index for the tile
-// boundaries t*tile that fall inside it (t*tile in [np_j, np_{j+1})).
+// Tile -> node map for every level at once: entry t of level d holds the
+// index (within the level's node list) of the node containing output
+// position t*tile; entry `tiles` holds the level's node count.  One thread per
+// tile, binary search over the level's node prefix sums.
 __global__ __launch_bounds__(256) void k_tile_map(const uint64_t *__restrict__ np,
                                                   const Plan *__restrict__ plan, int tile,
                                                   const uint64_t *__restrict__ tile_base,
                                                   uint32_t *__restrict__ tj) {
-  const uint64_t nn = plan->n_nodes;
-  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nn;
+  const uint64_t total = tile_base[kMaxLevels];
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (uint64_t)gridDim.x * blockDim.x) {
     int d = 0;
-    while (plan->lvl_begin[d + 1] <= g) d++;
-    uint64_t lb = plan->lvl_begin[d];
-    uint64_t a = np[g] - np[lb], e = np[g + 1] - np[lb];
-    uint64_t t0 = (a + tile - 1) / tile, t1 = (e + tile - 1) / tile;
-    for (uint64_t t = t0; t < t1; t++) tj[tile_base[d] + t] = (uint32_t)(g - lb);
-    if (g + 1 == plan->lvl_begin[d + 1]) {
-      // closing entry: boundary at (or past) the level end
-      uint64_t tiles = plan->lvl_tiles[d];
-      tj[tile_base[d] + tiles] = (uint32_t)(g + 1 - lb);
+    while (tile_base[d + 1] <= g) d++;
+    uint64_t t = g - tile_base[d];
+    uint64_t lb = plan->lvl_begin[d], le = plan->lvl_begin[d + 1];
+    if (t >= plan->lvl_tiles[d]) {
+      tj[g] = (uint32_t)(le - lb);
+      continue;
     }
+    uint64_t Q = np[lb] + t * (uint64_t)tile;
+    uint64_t lo = lb, hi = le - 1;   // last j with np[j] <= Q
+    while (hi > lo) {
+      uint64_t mid = (lo + hi + 1) >> 1;
+      if (np[mid] <= Q) lo = mid; else hi = mid - 1;
+    }
+    tj[g] = (uint32_t)(lo - lb);
   }
 }
 
@@ -570,7 +576,7 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
   hipLaunchKernelGGL(k_scan_apply, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_lvl_tiles, dim3(1), dim3(64), 0, s, w.plan, w.lvl_np, kTileSize, tile_base);
-  hipLaunchKernelGGL(k_tile_map, g256, b256, 0, s, w.lvl_np, w.plan, kTileSize, tile_base, tj);
+  hipLaunchKernelGGL(k_tile_map, dim3(2048), b256, 0, s, w.lvl_np, w.plan, kTileSize, tile_base, tj);
   return hipGetLastError();
 }
 
