@@ -91,6 +91,20 @@ struct Work {
   Plan *plan;
 };
 
+// ---------------------------------------------------------------- barriers
+// Workgroup barrier that orders LDS only: waits for this wave's LDS
+// operations (lgkmcnt(0); the gfx9 s_waitcnt encoding keeps vmcnt and expcnt
+// at their maxima) and joins s_barrier.  Unlike __syncthreads it does not wait
+// for outstanding global loads and stores, so prefetched loads stay in flight
+// across it.  Only for code where no global memory is exchanged between the
+// workgroup's threads.
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------- wave helpers
 __device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
 

@@ -306,20 +306,39 @@ __global__ __launch_bounds__(256) void k_tile_desc(
   }
 }
 
+// Small tables of one descriptor-described tile (double-buffered: the next
+// tile's tables are built while the current tile is merged).
+enum { kTabNone = 0, kTabFast = 1, kTabGeneral = 2, kTabBad = 3 };
+
+template <int K>
+struct SmallTab {
+  uint64_t sl_g[2 * K];
+  uint64_t pc_out[2];
+  uint16_t sl_off[2 * K + 2];
+  uint16_t pc_loff[3];
+  uint16_t pc_sl[3];
+  int S, P, Tt, kind;
+};
+
 template <typename O, int K, int TILE>
 struct MergeSmem {
   static constexpr int kMaxSlices = TILE + 2 * K + 2;
   static constexpr int kMaxPieces = TILE / 2 + 4;
   static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
   static constexpr size_t kAux = kBuf > (size_t)kMaxSlices * 8 ? kBuf : (size_t)kMaxSlices * 8;
+  static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
   alignas(16) unsigned char bufA[kBuf];
   alignas(16) unsigned char bufB[kAux];       // also holds slice global starts during setup
+  // tables of the general (many small nodes) path
   uint64_t pc_out[kMaxPieces];
   uint16_t sl_off[kMaxSlices];
   uint16_t pc_loff[kMaxPieces];
   uint16_t pc_sl[kMaxPieces];
   uint64_t scan[256];
   int misc[8];
+  // descriptor path
+  SmallTab<K> tab[2];
+  alignas(16) uint32_t raw[kDescWords];
 };
 
 template <typename T>
@@ -333,9 +352,180 @@ __device__ inline int ub16(const uint16_t *a, int n, T x) {
   return lo;
 }
 
-constexpr int kFewSlices = 2 * 8 + 1;   // loop over slices/pieces instead of searching
+// Thread 0: build a small table from the raw descriptor words in LDS.
+template <int K>
+__device__ inline void build_small(SmallTab<K> &T, const TileDesc<K> &D, bool exists) {
+  if (!exists) { T.kind = kTabNone; return; }
+  uint32_t np = D.npieces;
+  T.Tt = (int)D.total;
+  if (np == kBadTile || np > 2) { T.kind = kTabBad; return; }
+  if (np == 0) { T.kind = kTabGeneral; return; }
+  int s = 0, off = 0;
+  for (int p = 0; p < (int)np; p++) {
+    T.pc_loff[p] = (uint16_t)off;
+    T.pc_sl[p] = (uint16_t)s;
+    T.pc_out[p] = D.out[p];
+    int d = (int)D.d[p];
+    if (d > K) d = K;
+    for (int j = 0; j < d; j++) {
+      T.sl_off[s] = (uint16_t)off;
+      T.sl_g[s] = D.src[p][j];
+      off += (int)D.len[p][j];
+      s++;
+    }
+  }
+  T.pc_loff[np] = (uint16_t)off;
+  T.pc_sl[np] = (uint16_t)s;
+  T.sl_off[s] = (uint16_t)off;
+  T.S = s;
+  T.P = (int)np;
+  T.kind = off == T.Tt ? kTabFast : kTabBad;
+}
 
-template <int KT, int K, int TILE, int THREADS>
+// Global addresses of a thread's E positions (t + i*THREADS).  Positions past
+// the tile end are clamped to its last element (loaded, never used), so the
+// loads that follow form one straight-line block: the compiler then issues
+// all of them before the first wait instead of waiting between them.
+template <int E, int THREADS>
+__device__ inline void addr_search(uint64_t (&g)[E], const uint16_t *sl_off,
+                                   const uint64_t *sl_g, int S, int Tt, int t) {
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    int e = t + i * THREADS;
+    int ec = e < Tt ? e : Tt - 1;
+    int s = ub16(sl_off, S + 1, ec) - 1;
+    g[i] = sl_g[s] + (uint64_t)(ec - sl_off[s]);
+  }
+}
+
+// Same for a descriptor tile (at most MAXS slices): branch-free selects over
+// the slice starts instead of a search.
+template <int E, int THREADS, int MAXS>
+__device__ inline void addr_select(uint64_t (&g)[E], const uint16_t *sl_off,
+                                   const uint64_t *sl_g, int S, int Tt, int t) {
+  int so[MAXS];
+  uint64_t sg[MAXS];
+#pragma unroll
+  for (int j = 0; j < MAXS; j++) {
+    so[j] = sl_off[j];
+    sg[j] = sl_g[j];
+  }
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    int e = t + i * THREADS;
+    int ec = e < Tt ? e : Tt - 1;
+    uint64_t a = sg[0] + (uint64_t)(ec - so[0]);
+#pragma unroll
+    for (int j = 1; j < MAXS; j++) {
+      bool in = j < S && so[j] <= ec;
+      a = in ? sg[j] + (uint64_t)(ec - so[j]) : a;
+    }
+    g[i] = a;
+  }
+}
+
+template <typename O, int E, bool HV>
+__device__ inline void issue_at(O (&kreg)[E], uint32_t (&vreg)[E], const O *in_keys,
+                                const uint32_t *in_vals, const uint64_t (&g)[E]) {
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    kreg[i] = in_keys[g[i]];
+    if (HV) vreg[i] = in_vals[g[i]];
+  }
+}
+
+template <typename Kt, typename O, int E, int THREADS>
+__device__ inline void commit_loads(const O (&kreg)[E], const uint32_t (&vreg)[E], O *kA,
+                                    uint32_t *vA, bool has_vals, int Tt, int t) {
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    int e = t + i * THREADS;
+    if (e < Tt) {
+      kA[e] = Kt::ord(kreg[i]);
+      if (has_vals) vA[e] = vreg[i];
+    }
+  }
+}
+
+// log2(K) stages of pairwise merge-path merges in LDS; returns which buffer
+// holds the result (0: A, 1: B).
+template <typename O, int K, int TILE, int THREADS>
+__device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, bool has_vals,
+                                   const uint16_t *sl_off, int S, const uint16_t *pc_sl, int P,
+                                   int Tt, int t) {
+  constexpr int E = TILE / THREADS;
+  constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
+  O *ks = kA, *kd = kB;
+  uint32_t *vs = vA, *vd = vB;
+  for (int st = 1; st <= LOGK; st++) {
+    int e = t * E;
+    const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
+    while (e < e_end) {
+      int s = ub16(sl_off, S + 1, e) - 1;
+      int p = P == 1 ? 0 : ub16(pc_sl, P + 1, s) - 1;
+      int s0 = pc_sl[p];
+      int pd = pc_sl[p + 1] - s0;
+      int jj = s - s0;
+      int h = 1 << (st - 1);
+      int g0 = (jj >> st) << st;
+      int iM = g0 + h < pd ? g0 + h : pd;
+      int iR = g0 + 2 * h < pd ? g0 + 2 * h : pd;
+      int u0 = sl_off[s0 + g0], u1 = sl_off[s0 + iM], u2 = sl_off[s0 + iR];
+      int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
+      int lo = diag - nR > 0 ? diag - nR : 0;
+      int hi = diag < nL ? diag : nL;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (ks[u0 + mid] <= ks[u1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
+      }
+      int ia = u0 + lo, ib = u1 + diag - lo;
+      int stop = e_end < u2 ? e_end : u2;
+      if (stop <= e) break;  // cannot happen with valid tables (e < u2)
+      // heads kept in registers; one LDS key load per output
+      O ka = ks[ia < TILE ? ia : TILE - 1];
+      O kb = ks[ib < TILE ? ib : TILE - 1];
+      for (; e < stop; e++) {
+        bool takeL = ib >= u2 || (ia < u1 && ka <= kb);
+        int src = takeL ? ia : ib;
+        kd[e] = takeL ? ka : kb;
+        if (has_vals) vd[e] = vs[src];
+        ia += takeL ? 1 : 0;
+        ib += takeL ? 0 : 1;
+        int nx = takeL ? ia : ib;
+        O kn = ks[nx < TILE ? nx : TILE - 1];
+        if (takeL) ka = kn; else kb = kn;
+      }
+    }
+    lds_barrier();
+    O *tk = ks; ks = kd; kd = tk;
+    uint32_t *tv = vs; vs = vd; vd = tv;
+  }
+  return (LOGK & 1) ? 1 : 0;
+}
+
+template <typename Kt, typename O, int E, int THREADS>
+__device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
+                                  uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
+                                  const uint64_t *pc_out, int P, int Tt, int t) {
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    int e = t + i * THREADS;
+    if (e < Tt) {
+      int p = P == 1 ? 0 : ub16(pc_loff, P + 1, e) - 1;
+      uint64_t g = pc_out[p] + (uint64_t)(e - pc_loff[p]);
+      out_keys[g] = Kt::unord(ks[e]);
+      if (has_vals) out_vals[g] = vs[e];
+    }
+  }
+}
+
+// Each workgroup walks its tiles (blockIdx.x, + gridDim.x, ...).  Tiles
+// described by a descriptor are software-pipelined: while tile i is merged
+// in LDS, the descriptor of tile i+2 and the input slices of tile i+1 are
+// already being fetched into registers, so global latency overlaps the LDS
+// work.  Tiles spanning many small nodes take the general path (tables built
+// from the node records, no overlap).
+template <int KT, int K, int TILE, int THREADS, bool HV>
 __global__ __launch_bounds__(THREADS) void k_merge(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
@@ -349,14 +539,17 @@ __global__ __launch_bounds__(THREADS) void k_merge(
   using O = typename Kt::U;
   using SM = MergeSmem<O, K, TILE>;
   constexpr int E = TILE / THREADS;
-  constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
+  constexpr int NW = SM::kDescWords;
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
   uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
   O *kB = reinterpret_cast<O *>(sm.bufB);
   uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
   uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufB);
-  const bool has_vals = in_vals != nullptr;
+  constexpr bool has_vals = HV;
+  constexpr int MAXS = 2 * K;
+  const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
+  uint64_t ga[E];
 
   const uint64_t tiles = plan->lvl_tiles[level];
   if (tiles == 0) return;
@@ -367,215 +560,156 @@ __global__ __launch_bounds__(THREADS) void k_merge(
   const uint64_t L = np[le] - np0;
   const uint32_t *tjl = tj + tile_base[level];
   const int t = threadIdx.x;
+  const uint64_t G = gridDim.x;
 
-  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    // ---- setup: piece and slice tables in LDS
-    if (t == 0) {
-      const TileDesc<K> &D = desc[tile];
-      uint32_t np_ = D.npieces;
-      sm.misc[0] = np_ == kBadTile ? 1 : 0;
-      sm.misc[1] = (int)D.total;
-      sm.misc[2] = np_ == kBadTile ? 0 : (int)np_;   // pieces (0: general setup below)
-      if (np_ == 1 || np_ == 2) {
-        int s = 0, off = 0;
-        for (int p = 0; p < (int)np_; p++) {
-          sm.pc_loff[p] = (uint16_t)off;
-          sm.pc_sl[p] = (uint16_t)s;
-          sm.pc_out[p] = D.out[p];
-          for (int j = 0; j < (int)D.d[p]; j++) {
-            sm.sl_off[s] = (uint16_t)off;
-            sl_g[s] = D.src[p][j];
-            off += (int)D.len[p][j];
-            s++;
-          }
-        }
-        sm.pc_loff[np_] = (uint16_t)off;
-        sm.pc_sl[np_] = (uint16_t)s;
-        sm.sl_off[s] = (uint16_t)off;
-        sm.misc[3] = s;
+  O kreg[E];
+  uint32_t vreg[E];
+  uint32_t dreg = 0;   // one word of a prefetched descriptor (lanes 0..NW-1)
+
+  // prologue: tables of the first tile, descriptor of the second, loads of the first
+  uint64_t tile = blockIdx.x;
+  if (tile >= tiles) return;
+  if (t < NW) sm.raw[t] = descw[tile * (sizeof(TileDesc<K>) / 4) + t];
+  lds_barrier();
+  if (t == 0) build_small<K>(sm.tab[0], *reinterpret_cast<const TileDesc<K> *>(sm.raw), true);
+  lds_barrier();
+  if (t < NW && tile + G < tiles) dreg = descw[(tile + G) * (sizeof(TileDesc<K>) / 4) + t];
+  bool loaded = false;
+  if (sm.tab[0].kind == kTabFast) {
+    addr_select<E, THREADS, MAXS>(ga, sm.tab[0].sl_off, sm.tab[0].sl_g, sm.tab[0].S,
+                                  sm.tab[0].Tt, t);
+    issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
+    loaded = true;
+  }
+  int cur = 0;
+
+  while (tile < tiles) {
+    const uint64_t nxt = tile + G;
+    SmallTab<K> &T = sm.tab[cur];
+    SmallTab<K> &N = sm.tab[cur ^ 1];
+    const int kind = T.kind;
+    if (kind == kTabFast) {
+      if (!loaded) {
+        addr_select<E, THREADS, MAXS>(ga, T.sl_off, T.sl_g, T.S, T.Tt, t);
+        issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
       }
+      commit_loads<Kt, O, E, THREADS>(kreg, vreg, kA, vA, has_vals, T.Tt, t);
     }
-    __syncthreads();
-    if (sm.misc[0]) {
-      if (t == 0) atomicOr(&plan->error, 32u);
-      __syncthreads();
-      continue;
+    // next tile's tables from its prefetched descriptor; then fetch ahead
+    if (t < NW) sm.raw[t] = dreg;
+    lds_barrier();
+    if (t == 0) build_small<K>(N, *reinterpret_cast<const TileDesc<K> *>(sm.raw), nxt < tiles);
+    lds_barrier();
+    if (t < NW && nxt + G < tiles) dreg = descw[(nxt + G) * (sizeof(TileDesc<K>) / 4) + t];
+    loaded = false;
+    if (N.kind == kTabFast) {
+      addr_select<E, THREADS, MAXS>(ga, N.sl_off, N.sl_g, N.S, N.Tt, t);
+      issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
+      loaded = true;
     }
-    const int Tt = sm.misc[1];
-    int P = sm.misc[2];
-    int S = sm.misc[3];
-    if (P == 0) {
+
+    if (kind == kTabFast) {
+      int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, has_vals, T.sl_off, T.S,
+                                                  T.pc_sl, T.P, T.Tt, t);
+      store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, has_vals,
+                                    T.pc_loff, T.pc_out, T.P, T.Tt, t);
+    } else if (kind == kTabGeneral) {
       // general setup: the tile spans many small nodes
+      const int Tt = T.Tt;
       TileGeom g = tile_geom(tile, TILE, L, nlev, np, lb, np0, tjl);
-      P = (int)(g.j1 - g.j0 + 1);
-      if (!g.ok || P + 1 > SM::kMaxPieces) {
-        if (t == 0) atomicOr(&plan->error, 16u);
-        __syncthreads();
-        continue;
-      }
-      const uint64_t Q0 = g.Q0, Q1 = g.Q1, j0 = g.j0;
-      uint64_t carry_len = 0, carry_sl = 0;
-      if (t == 0) sm.misc[4] = 0;
-      __syncthreads();
-      for (int pbase = 0; pbase < P; pbase += THREADS) {
-        int p = pbase + t;
-        NodeIn nd;
-        uint32_t c0[K], c1[K];
-        uint64_t plen = 0;
-        int pd = 0;
-        if (p < P) {
-          uint64_t j = j0 + p;
-          if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
-            sm.misc[4] = 1;
-            nd.d = 2;
-            nd.c[0] = nd.c[1] = nd.c[2] = 0;
-          }
-          pd = nd.d;
-          bool first = p == 0, last = p == P - 1;
-          bool cut_end = last && Q1 < np[lb + j + 1] - np0;
-          for (int jj = 0; jj < K; jj++) {
-            if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
-            uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
-            c0[jj] = first ? cr[tile * K + jj] : 0;
-            c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
-            if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
+      const int P = (int)(g.j1 - g.j0 + 1);
+      bool bad = !g.ok || P + 1 > SM::kMaxPieces;
+      if (t == 0) sm.misc[4] = bad ? 1 : 0;
+      lds_barrier();
+      if (!bad) {
+        const uint64_t Q0 = g.Q0, Q1 = g.Q1, j0 = g.j0;
+        uint64_t carry_len = 0, carry_sl = 0;
+        for (int pbase = 0; pbase < P; pbase += THREADS) {
+          int p = pbase + t;
+          NodeIn nd;
+          uint32_t c0[K], c1[K];
+          uint64_t plen = 0;
+          int pd = 0;
+          if (p < P) {
+            uint64_t j = j0 + p;
+            if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
               sm.misc[4] = 1;
-              c0[jj] = c1[jj] = 0;
+              nd.d = 2;
+              nd.c[0] = nd.c[1] = nd.c[2] = 0;
             }
-            plen += c1[jj] - c0[jj];
+            pd = nd.d;
+            bool first = p == 0, last = p == P - 1;
+            bool cut_end = last && Q1 < np[lb + j + 1] - np0;
+            for (int jj = 0; jj < K; jj++) {
+              if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
+              uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
+              c0[jj] = first ? cr[tile * K + jj] : 0;
+              c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
+              if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
+                sm.misc[4] = 1;
+                c0[jj] = c1[jj] = 0;
+              }
+              plen += c1[jj] - c0[jj];
+            }
           }
-        }
-        uint64_t packed = ((uint64_t)pd << 32) | plen;
-        sm.scan[t] = packed;
-        __syncthreads();
-        for (int o = 1; o < THREADS; o <<= 1) {
-          uint64_t y = t >= o ? sm.scan[t - o] : 0;
-          __syncthreads();
-          sm.scan[t] += y;
-          __syncthreads();
-        }
-        uint64_t ex = sm.scan[t] - packed;
-        uint64_t tot = sm.scan[THREADS - 1];
-        __syncthreads();
-        if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
-            carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
-          uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
-          uint64_t sl0 = carry_sl + (ex >> 32);
-          sm.pc_loff[p] = (uint16_t)loff;
-          sm.pc_sl[p] = (uint16_t)sl0;
-          sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
-          uint64_t acc = loff;
-          for (int jj = 0; jj < pd; jj++) {
-            sm.sl_off[sl0 + jj] = (uint16_t)acc;
-            sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
-            acc += c1[jj] - c0[jj];
+          uint64_t packed = ((uint64_t)pd << 32) | plen;
+          sm.scan[t] = packed;
+          lds_barrier();
+          for (int o = 1; o < THREADS; o <<= 1) {
+            uint64_t y = t >= o ? sm.scan[t - o] : 0;
+            lds_barrier();
+            sm.scan[t] += y;
+            lds_barrier();
           }
+          uint64_t ex = sm.scan[t] - packed;
+          uint64_t tot = sm.scan[THREADS - 1];
+          lds_barrier();
+          if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
+              carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
+            uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
+            uint64_t sl0 = carry_sl + (ex >> 32);
+            sm.pc_loff[p] = (uint16_t)loff;
+            sm.pc_sl[p] = (uint16_t)sl0;
+            sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
+            uint64_t acc = loff;
+            for (int jj = 0; jj < pd; jj++) {
+              sm.sl_off[sl0 + jj] = (uint16_t)acc;
+              sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
+              acc += c1[jj] - c0[jj];
+            }
+          }
+          carry_len += tot & 0xFFFFFFFFull;
+          carry_sl += tot >> 32;
         }
-        carry_len += tot & 0xFFFFFFFFull;
-        carry_sl += tot >> 32;
+        const int S = (int)carry_sl;
+        if (carry_len != (uint64_t)Tt || S + 1 > SM::kMaxSlices) sm.misc[4] = 1;
+        lds_barrier();
+        if (t == 0 && !sm.misc[4]) {
+          sm.pc_loff[P] = (uint16_t)Tt;
+          sm.pc_sl[P] = (uint16_t)S;
+          sm.sl_off[S] = (uint16_t)Tt;
+        }
+        lds_barrier();
+        if (!sm.misc[4]) {
+          O k2[E];
+          uint32_t v2[E];
+          addr_search<E, THREADS>(ga, sm.sl_off, sl_g, S, Tt, t);
+          issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
+          commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, has_vals, Tt, t);
+          lds_barrier();
+          int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, has_vals, sm.sl_off, S,
+                                                      sm.pc_sl, P, Tt, t);
+          store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals,
+                                        has_vals, sm.pc_loff, sm.pc_out, P, Tt, t);
+        }
       }
-      S = (int)carry_sl;
-      if (carry_len != (uint64_t)Tt || S + 1 > SM::kMaxSlices) sm.misc[4] = 1;
-      __syncthreads();
-      if (sm.misc[4]) {  // the tile's co-ranks do not add up: flag it and leave it alone
-        if (t == 0) atomicOr(&plan->error, 32u);
-        __syncthreads();
-        continue;
-      }
-      if (t == 0) {
-        sm.pc_loff[P] = (uint16_t)Tt;
-        sm.pc_sl[P] = (uint16_t)S;
-        sm.sl_off[S] = (uint16_t)Tt;
-      }
-      __syncthreads();
+      if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
+    } else if (kind == kTabBad) {
+      if (t == 0) atomicOr(&plan->error, 32u);
     }
-
-    // ---- stage the tile's inputs in LDS (key order-mapped).  Every thread
-    // first issues all of its E global loads, then writes LDS, so the load
-    // latency is paid once per tile rather than once per element.
-    {
-      O kreg[E];
-      uint32_t vreg[E];
-#pragma unroll
-      for (int i = 0; i < E; i++) {
-        int e = t + i * THREADS;
-        if (e < Tt) {
-          int s = ub16(sm.sl_off, S + 1, e) - 1;
-          uint64_t g = sl_g[s] + (uint64_t)(e - sm.sl_off[s]);
-          kreg[i] = in_keys[g];
-          vreg[i] = has_vals ? in_vals[g] : 0u;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < E; i++) {
-        int e = t + i * THREADS;
-        if (e < Tt) {
-          kA[e] = Kt::ord(kreg[i]);
-          if (has_vals) vA[e] = vreg[i];
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- log2(K) stages of pairwise merge-path merges
-    O *ks = kA, *kd = kB;
-    uint32_t *vs = vA, *vd = vB;
-    for (int st = 1; st <= LOGK; st++) {
-      int e = t * E;
-      const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
-      while (e < e_end) {
-        int s = ub16(sm.sl_off, S + 1, e) - 1;
-        int p = ub16(sm.pc_sl, P + 1, s) - 1;
-        int s0 = sm.pc_sl[p];
-        int pd = sm.pc_sl[p + 1] - s0;
-        int jj = s - s0;
-        int h = 1 << (st - 1);
-        int g0 = (jj >> st) << st;
-        int iM = g0 + h < pd ? g0 + h : pd;
-        int iR = g0 + 2 * h < pd ? g0 + 2 * h : pd;
-        int u0 = sm.sl_off[s0 + g0], u1 = sm.sl_off[s0 + iM], u2 = sm.sl_off[s0 + iR];
-        int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
-        int lo = diag - nR > 0 ? diag - nR : 0;
-        int hi = diag < nL ? diag : nL;
-        while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (ks[u0 + mid] <= ks[u1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
-        }
-        int ia = u0 + lo, ib = u1 + diag - lo;
-        int stop = e_end < u2 ? e_end : u2;
-        if (stop <= e) break;  // cannot happen with valid tables (e < u2)
-        // heads kept in registers; one LDS key load per output
-        O ka = ks[ia < TILE ? ia : TILE - 1];
-        O kb = ks[ib < TILE ? ib : TILE - 1];
-        for (; e < stop; e++) {
-          bool takeL = ib >= u2 || (ia < u1 && ka <= kb);
-          int src = takeL ? ia : ib;
-          kd[e] = takeL ? ka : kb;
-          if (has_vals) vd[e] = vs[src];
-          ia += takeL ? 1 : 0;
-          ib += takeL ? 0 : 1;
-          int nx = takeL ? ia : ib;
-          O kn = ks[nx < TILE ? nx : TILE - 1];
-          if (takeL) ka = kn; else kb = kn;
-        }
-      }
-      __syncthreads();
-      O *tk = ks; ks = kd; kd = tk;
-      uint32_t *tv = vs; vs = vd; vd = tv;
-    }
-
-    // ---- write back (coalesced per piece)
-#pragma unroll
-    for (int i = 0; i < E; i++) {
-      int e = t + i * THREADS;
-      if (e < Tt) {
-        int p = P == 1 ? 0 : ub16(sm.pc_loff, P + 1, e) - 1;
-        uint64_t g = sm.pc_out[p] + (uint64_t)(e - sm.pc_loff[p]);
-        out_keys[g] = Kt::unord(ks[e]);
-        if (has_vals) out_vals[g] = vs[e];
-      }
-    }
-    __syncthreads();
+    lds_barrier();
+    cur ^= 1;
+    tile = nxt;
   }
 }
 
@@ -613,10 +747,16 @@ static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj
                      w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level,
                      kTile, w.corank, desc);
   if (e1) (void)hipEventRecord(e1, s);
-  hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads>), dim3(gm), dim3(kMergeThreads), 0, s,
-                     (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals, w.run_start,
-                     w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base,
-                     w.plan, level, w.corank, desc);
+  if (a.in_vals)
+    hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads, true>), dim3(gm), dim3(kMergeThreads),
+                       0, s, (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals,
+                       w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
+                       tile_base, w.plan, level, w.corank, desc);
+  else
+    hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads, false>), dim3(gm), dim3(kMergeThreads),
+                       0, s, (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals,
+                       w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
+                       tile_base, w.plan, level, w.corank, desc);
   if (e2) (void)hipEventRecord(e2, s);
 }
 
