@@ -52,6 +52,7 @@ struct Plan {
   uint64_t lvl_begin[kMaxLevels + 1];  // level-sorted node list offsets
   uint64_t lvl_total[kMaxLevels];    // sum of node sizes per level
   uint64_t lvl_tiles[kMaxLevels];    // merge tiles per level
+  uint32_t gen_cnt[kMaxLevels];      // tiles per level that need the general merge path
 };
 
 // Run-detection block aggregate (16384 positions per block).
@@ -88,6 +89,7 @@ struct Work {
   uint64_t *scan_tmp;                // [nbb + 1024]
   uint32_t *corank;                  // [(N/tile + 2) * k]
   void *tile_desc;                   // [(N/tile + 2)] per-tile merge descriptors
+  uint32_t *gen_list;                // [(N/tile + 2)] tiles of the current level on the general path
   Plan *plan;
 };
 

@@ -256,7 +256,8 @@ __global__ __launch_bounds__(256) void k_tile_desc(
     const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
     const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
     const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level, int tsize,
-    const uint32_t *__restrict__ cr, TileDesc<K> *__restrict__ desc) {
+    const uint32_t *__restrict__ cr, TileDesc<K> *__restrict__ desc,
+    uint32_t *__restrict__ gen_list) {
   const uint64_t tiles = plan->lvl_tiles[level];
   if (tiles == 0) return;
   const uint64_t r = plan->r;
@@ -301,6 +302,8 @@ __global__ __launch_bounds__(256) void k_tile_desc(
         }
       }
       D.npieces = (bad || sum != D.total) ? kBadTile : (uint32_t)P;
+    } else {
+      gen_list[atomicAdd(&plan->gen_cnt[level], 1u)] = (uint32_t)tile;
     }
     desc[tile] = D;
   }
@@ -320,25 +323,32 @@ struct SmallTab {
   int S, P, Tt, kind;
 };
 
+// LDS of the descriptor-tile kernel: two stage buffers and the small tables.
 template <typename O, int K, int TILE>
-struct MergeSmem {
+struct FastSmem {
+  static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
+  static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
+  alignas(16) unsigned char bufA[kBuf];
+  alignas(16) unsigned char bufB[kBuf];
+  SmallTab<K> tab[2];
+  alignas(16) uint32_t raw[kDescWords];
+};
+
+// LDS of the general kernel (tiles spanning many small nodes).
+template <typename O, int K, int TILE>
+struct GenSmem {
   static constexpr int kMaxSlices = TILE + 2 * K + 2;
   static constexpr int kMaxPieces = TILE / 2 + 4;
   static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
   static constexpr size_t kAux = kBuf > (size_t)kMaxSlices * 8 ? kBuf : (size_t)kMaxSlices * 8;
-  static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
   alignas(16) unsigned char bufA[kBuf];
   alignas(16) unsigned char bufB[kAux];       // also holds slice global starts during setup
-  // tables of the general (many small nodes) path
   uint64_t pc_out[kMaxPieces];
   uint16_t sl_off[kMaxSlices];
   uint16_t pc_loff[kMaxPieces];
   uint16_t pc_sl[kMaxPieces];
   uint64_t scan[256];
   int misc[8];
-  // descriptor path
-  SmallTab<K> tab[2];
-  alignas(16) uint32_t raw[kDescWords];
 };
 
 template <typename T>
@@ -519,67 +529,51 @@ __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
   }
 }
 
-// Each workgroup walks its tiles (blockIdx.x, + gridDim.x, ...).  Tiles
-// described by a descriptor are software-pipelined: while tile i is merged
-// in LDS, the descriptor of tile i+2 and the input slices of tile i+1 are
-// already being fetched into registers, so global latency overlaps the LDS
-// work.  Tiles spanning many small nodes take the general path (tables built
-// from the node records, no overlap).
+// Descriptor tiles.  Each workgroup walks tiles blockIdx.x, +gridDim.x, ...
+// (skipping those of the general path) software-pipelined: while tile i is
+// merged in LDS, the descriptor of tile i+2 and the input slices of tile i+1
+// are already being fetched into registers, so global latency overlaps the
+// LDS work.
 template <int KT, int K, int TILE, int THREADS, bool HV>
-__global__ __launch_bounds__(THREADS) void k_merge(
+__global__ __launch_bounds__(THREADS) void k_merge_fast(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
-    const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
-    const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
-    const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
-    const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
-    const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level,
-    const uint32_t *__restrict__ cr, const TileDesc<K> *__restrict__ desc) {
+    Plan *__restrict__ plan, int level, const TileDesc<K> *__restrict__ desc) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
-  using SM = MergeSmem<O, K, TILE>;
+  using SM = FastSmem<O, K, TILE>;
   constexpr int E = TILE / THREADS;
   constexpr int NW = SM::kDescWords;
+  constexpr int DW = (int)(sizeof(TileDesc<K>) / 4);
+  constexpr int MAXS = 2 * K;
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
   uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
   O *kB = reinterpret_cast<O *>(sm.bufB);
   uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
-  uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufB);
-  constexpr bool has_vals = HV;
-  constexpr int MAXS = 2 * K;
   const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
-  uint64_t ga[E];
 
   const uint64_t tiles = plan->lvl_tiles[level];
-  if (tiles == 0) return;
-  const uint64_t rr_total = plan->r;
-  const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
-  const uint64_t nlev = le - lb;
-  const uint64_t np0 = np[lb];
-  const uint64_t L = np[le] - np0;
-  const uint32_t *tjl = tj + tile_base[level];
   const int t = threadIdx.x;
   const uint64_t G = gridDim.x;
+  uint64_t tile = blockIdx.x;
+  if (tile >= tiles) return;
 
   O kreg[E];
   uint32_t vreg[E];
+  uint64_t ga[E];
   uint32_t dreg = 0;   // one word of a prefetched descriptor (lanes 0..NW-1)
 
   // prologue: tables of the first tile, descriptor of the second, loads of the first
-  uint64_t tile = blockIdx.x;
-  if (tile >= tiles) return;
-  if (t < NW) sm.raw[t] = descw[tile * (sizeof(TileDesc<K>) / 4) + t];
+  if (t < NW) sm.raw[t] = descw[tile * DW + t];
   lds_barrier();
   if (t == 0) build_small<K>(sm.tab[0], *reinterpret_cast<const TileDesc<K> *>(sm.raw), true);
   lds_barrier();
-  if (t < NW && tile + G < tiles) dreg = descw[(tile + G) * (sizeof(TileDesc<K>) / 4) + t];
-  bool loaded = false;
+  if (t < NW && tile + G < tiles) dreg = descw[(tile + G) * DW + t];
   if (sm.tab[0].kind == kTabFast) {
     addr_select<E, THREADS, MAXS>(ga, sm.tab[0].sl_off, sm.tab[0].sl_g, sm.tab[0].S,
                                   sm.tab[0].Tt, t);
     issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
-    loaded = true;
   }
   int cur = 0;
 
@@ -588,128 +582,158 @@ __global__ __launch_bounds__(THREADS) void k_merge(
     SmallTab<K> &T = sm.tab[cur];
     SmallTab<K> &N = sm.tab[cur ^ 1];
     const int kind = T.kind;
-    if (kind == kTabFast) {
-      if (!loaded) {
-        addr_select<E, THREADS, MAXS>(ga, T.sl_off, T.sl_g, T.S, T.Tt, t);
-        issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
-      }
-      commit_loads<Kt, O, E, THREADS>(kreg, vreg, kA, vA, has_vals, T.Tt, t);
-    }
+    if (kind == kTabFast) commit_loads<Kt, O, E, THREADS>(kreg, vreg, kA, vA, HV, T.Tt, t);
     // next tile's tables from its prefetched descriptor; then fetch ahead
     if (t < NW) sm.raw[t] = dreg;
     lds_barrier();
     if (t == 0) build_small<K>(N, *reinterpret_cast<const TileDesc<K> *>(sm.raw), nxt < tiles);
     lds_barrier();
-    if (t < NW && nxt + G < tiles) dreg = descw[(nxt + G) * (sizeof(TileDesc<K>) / 4) + t];
-    loaded = false;
+    if (t < NW && nxt + G < tiles) dreg = descw[(nxt + G) * DW + t];
     if (N.kind == kTabFast) {
       addr_select<E, THREADS, MAXS>(ga, N.sl_off, N.sl_g, N.S, N.Tt, t);
       issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
-      loaded = true;
     }
-
     if (kind == kTabFast) {
-      int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, has_vals, T.sl_off, T.S,
-                                                  T.pc_sl, T.P, T.Tt, t);
-      store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, has_vals,
+      int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, HV, T.sl_off, T.S, T.pc_sl,
+                                                  T.P, T.Tt, t);
+      store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
                                     T.pc_loff, T.pc_out, T.P, T.Tt, t);
-    } else if (kind == kTabGeneral) {
-      // general setup: the tile spans many small nodes
-      const int Tt = T.Tt;
-      TileGeom g = tile_geom(tile, TILE, L, nlev, np, lb, np0, tjl);
-      const int P = (int)(g.j1 - g.j0 + 1);
-      bool bad = !g.ok || P + 1 > SM::kMaxPieces;
-      if (t == 0) sm.misc[4] = bad ? 1 : 0;
-      lds_barrier();
-      if (!bad) {
-        const uint64_t Q0 = g.Q0, Q1 = g.Q1, j0 = g.j0;
-        uint64_t carry_len = 0, carry_sl = 0;
-        for (int pbase = 0; pbase < P; pbase += THREADS) {
-          int p = pbase + t;
-          NodeIn nd;
-          uint32_t c0[K], c1[K];
-          uint64_t plen = 0;
-          int pd = 0;
-          if (p < P) {
-            uint64_t j = j0 + p;
-            if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
-              sm.misc[4] = 1;
-              nd.d = 2;
-              nd.c[0] = nd.c[1] = nd.c[2] = 0;
-            }
-            pd = nd.d;
-            bool first = p == 0, last = p == P - 1;
-            bool cut_end = last && Q1 < np[lb + j + 1] - np0;
-            for (int jj = 0; jj < K; jj++) {
-              if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
-              uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
-              c0[jj] = first ? cr[tile * K + jj] : 0;
-              c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
-              if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
-                sm.misc[4] = 1;
-                c0[jj] = c1[jj] = 0;
-              }
-              plen += c1[jj] - c0[jj];
-            }
-          }
-          uint64_t packed = ((uint64_t)pd << 32) | plen;
-          sm.scan[t] = packed;
-          lds_barrier();
-          for (int o = 1; o < THREADS; o <<= 1) {
-            uint64_t y = t >= o ? sm.scan[t - o] : 0;
-            lds_barrier();
-            sm.scan[t] += y;
-            lds_barrier();
-          }
-          uint64_t ex = sm.scan[t] - packed;
-          uint64_t tot = sm.scan[THREADS - 1];
-          lds_barrier();
-          if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
-              carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
-            uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
-            uint64_t sl0 = carry_sl + (ex >> 32);
-            sm.pc_loff[p] = (uint16_t)loff;
-            sm.pc_sl[p] = (uint16_t)sl0;
-            sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
-            uint64_t acc = loff;
-            for (int jj = 0; jj < pd; jj++) {
-              sm.sl_off[sl0 + jj] = (uint16_t)acc;
-              sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
-              acc += c1[jj] - c0[jj];
-            }
-          }
-          carry_len += tot & 0xFFFFFFFFull;
-          carry_sl += tot >> 32;
-        }
-        const int S = (int)carry_sl;
-        if (carry_len != (uint64_t)Tt || S + 1 > SM::kMaxSlices) sm.misc[4] = 1;
-        lds_barrier();
-        if (t == 0 && !sm.misc[4]) {
-          sm.pc_loff[P] = (uint16_t)Tt;
-          sm.pc_sl[P] = (uint16_t)S;
-          sm.sl_off[S] = (uint16_t)Tt;
-        }
-        lds_barrier();
-        if (!sm.misc[4]) {
-          O k2[E];
-          uint32_t v2[E];
-          addr_search<E, THREADS>(ga, sm.sl_off, sl_g, S, Tt, t);
-          issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
-          commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, has_vals, Tt, t);
-          lds_barrier();
-          int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, has_vals, sm.sl_off, S,
-                                                      sm.pc_sl, P, Tt, t);
-          store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals,
-                                        has_vals, sm.pc_loff, sm.pc_out, P, Tt, t);
-        }
-      }
-      if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
     } else if (kind == kTabBad) {
       if (t == 0) atomicOr(&plan->error, 32u);
     }
     lds_barrier();
     cur ^= 1;
     tile = nxt;
+  }
+}
+
+// Tiles spanning many small nodes (listed by the descriptor kernel): piece
+// and slice tables are built from the node records, then the same staged
+// merge runs.  Not pipelined.
+template <int KT, int K, int TILE, int THREADS, bool HV>
+__global__ __launch_bounds__(THREADS) void k_merge_general(
+    const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
+    typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
+    const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
+    const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
+    const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
+    const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
+    const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level,
+    const uint32_t *__restrict__ cr, const uint32_t *__restrict__ gen_list) {
+  using Kt = Key<KT>;
+  using O = typename Kt::U;
+  using SM = GenSmem<O, K, TILE>;
+  constexpr int E = TILE / THREADS;
+  __shared__ SM sm;
+  O *kA = reinterpret_cast<O *>(sm.bufA);
+  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
+  O *kB = reinterpret_cast<O *>(sm.bufB);
+  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
+  uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufB);
+
+  const uint32_t ngen = plan->gen_cnt[level];
+  if (ngen == 0) return;
+  const uint64_t rr_total = plan->r;
+  const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
+  const uint64_t nlev = le - lb;
+  const uint64_t np0 = np[lb];
+  const uint64_t L = np[le] - np0;
+  const uint32_t *tjl = tj + tile_base[level];
+  const int t = threadIdx.x;
+  uint64_t ga[E];
+
+  for (uint32_t gi = blockIdx.x; gi < ngen; gi += gridDim.x) {
+    const uint64_t tile = gen_list[gi];
+    TileGeom g = tile_geom(tile, TILE, L, nlev, np, lb, np0, tjl);
+    const int Tt = (int)(g.Q1 - g.Q0);
+    const int P = (int)(g.j1 - g.j0 + 1);
+    bool bad = !g.ok || P + 1 > SM::kMaxPieces;
+    if (t == 0) sm.misc[4] = bad ? 1 : 0;
+    __syncthreads();
+    if (!bad) {
+      const uint64_t Q0 = g.Q0, Q1 = g.Q1, j0 = g.j0;
+      uint64_t carry_len = 0, carry_sl = 0;
+      for (int pbase = 0; pbase < P; pbase += THREADS) {
+        int p = pbase + t;
+        NodeIn nd;
+        uint32_t c0[K], c1[K];
+        uint64_t plen = 0;
+        int pd = 0;
+        if (p < P) {
+          uint64_t j = j0 + p;
+          if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
+            sm.misc[4] = 1;
+            nd.d = 2;
+            nd.c[0] = nd.c[1] = nd.c[2] = 0;
+          }
+          pd = nd.d;
+          bool first = p == 0, last = p == P - 1;
+          bool cut_end = last && Q1 < np[lb + j + 1] - np0;
+          for (int jj = 0; jj < K; jj++) {
+            if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
+            uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
+            c0[jj] = first ? cr[tile * K + jj] : 0;
+            c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
+            if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
+              sm.misc[4] = 1;
+              c0[jj] = c1[jj] = 0;
+            }
+            plen += c1[jj] - c0[jj];
+          }
+        }
+        uint64_t packed = ((uint64_t)pd << 32) | plen;
+        sm.scan[t] = packed;
+        __syncthreads();
+        for (int o = 1; o < THREADS; o <<= 1) {
+          uint64_t y = t >= o ? sm.scan[t - o] : 0;
+          __syncthreads();
+          sm.scan[t] += y;
+          __syncthreads();
+        }
+        uint64_t ex = sm.scan[t] - packed;
+        uint64_t tot = sm.scan[THREADS - 1];
+        __syncthreads();
+        if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
+            carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
+          uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
+          uint64_t sl0 = carry_sl + (ex >> 32);
+          sm.pc_loff[p] = (uint16_t)loff;
+          sm.pc_sl[p] = (uint16_t)sl0;
+          sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
+          uint64_t acc = loff;
+          for (int jj = 0; jj < pd; jj++) {
+            sm.sl_off[sl0 + jj] = (uint16_t)acc;
+            sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
+            acc += c1[jj] - c0[jj];
+          }
+        }
+        carry_len += tot & 0xFFFFFFFFull;
+        carry_sl += tot >> 32;
+      }
+      const int S = (int)carry_sl;
+      if (carry_len != (uint64_t)Tt || S + 1 > SM::kMaxSlices) sm.misc[4] = 1;
+      __syncthreads();
+      if (t == 0 && !sm.misc[4]) {
+        sm.pc_loff[P] = (uint16_t)Tt;
+        sm.pc_sl[P] = (uint16_t)S;
+        sm.sl_off[S] = (uint16_t)Tt;
+      }
+      __syncthreads();
+      if (!sm.misc[4]) {
+        O k2[E];
+        uint32_t v2[E];
+        addr_search<E, THREADS>(ga, sm.sl_off, sl_g, S, Tt, t);
+        issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
+        commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, HV, Tt, t);
+        __syncthreads();
+        int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, HV, sm.sl_off, S, sm.pc_sl,
+                                                    P, Tt, t);
+        store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
+                                      sm.pc_loff, sm.pc_out, P, Tt, t);
+      }
+    }
+    if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
+    __syncthreads();
   }
 }
 
@@ -732,12 +756,28 @@ hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipSt
 constexpr int kMergeThreads = 256;
 constexpr int kTile = kTileSize;
 
+// Workgroups that fill the device exactly once (CUs x resident blocks per
+// CU) for a grid-stride kernel; computed once per kernel.
+template <typename F>
+static unsigned fill_grid(F kernel, int threads, unsigned fallback) {
+  static unsigned cached = 0;
+  if (cached) return cached;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      cus <= 0 || per_cu <= 0)
+    return fallback;
+  cached = (unsigned)(cus * per_cu);
+  return cached;
+}
+
 template <int KT, int K>
 static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
                            const uint64_t *tile_base, int level, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1, hipEvent_t e2) {
   using U = typename Key<KT>::U;
-  unsigned gc = 512, gm = 4096;
+  unsigned gc = 512, gm = 1024, gg = 2048;
   if (e0) (void)hipEventRecord(e0, s);
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
@@ -745,18 +785,29 @@ static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj
   TileDesc<K> *desc = reinterpret_cast<TileDesc<K> *>(w.tile_desc);
   hipLaunchKernelGGL((k_tile_desc<K>), dim3(gc), dim3(256), 0, s, w.run_start, w.Ls, w.Rs,
                      w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level,
-                     kTile, w.corank, desc);
+                     kTile, w.corank, desc, w.gen_list);
   if (e1) (void)hipEventRecord(e1, s);
-  if (a.in_vals)
-    hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads, true>), dim3(gm), dim3(kMergeThreads),
-                       0, s, (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals,
-                       w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
-                       tile_base, w.plan, level, w.corank, desc);
-  else
-    hipLaunchKernelGGL((k_merge<KT, K, kTile, kMergeThreads, false>), dim3(gm), dim3(kMergeThreads),
-                       0, s, (const U *)a.in_keys, a.in_vals, (U *)a.out_keys, a.out_vals,
-                       w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
-                       tile_base, w.plan, level, w.corank, desc);
+  if (a.in_vals) {
+    gm = fill_grid(k_merge_fast<KT, K, kTile, kMergeThreads, true>, kMergeThreads, gm);
+    hipLaunchKernelGGL((k_merge_fast<KT, K, kTile, kMergeThreads, true>), dim3(gm),
+                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
+                       (U *)a.out_keys, a.out_vals, w.plan, level, desc);
+    hipLaunchKernelGGL((k_merge_general<KT, K, kTile, kMergeThreads, true>), dim3(gg),
+                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
+                       (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
+                       w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
+                       w.gen_list);
+  } else {
+    gm = fill_grid(k_merge_fast<KT, K, kTile, kMergeThreads, false>, kMergeThreads, gm);
+    hipLaunchKernelGGL((k_merge_fast<KT, K, kTile, kMergeThreads, false>), dim3(gm),
+                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
+                       (U *)a.out_keys, a.out_vals, w.plan, level, desc);
+    hipLaunchKernelGGL((k_merge_general<KT, K, kTile, kMergeThreads, false>), dim3(gg),
+                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
+                       (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
+                       w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
+                       w.gen_list);
+  }
   if (e2) (void)hipEventRecord(e2, s);
 }
 
