@@ -315,6 +315,7 @@ enum { kTabNone = 0, kTabFast = 1, kTabGeneral = 2, kTabBad = 3 };
 
 template <int K>
 struct SmallTab {
+  uint64_t delta[2 * K];   // sl_g[s] - sl_off[s]: global index of LDS position e is delta[s] + e
   uint64_t sl_g[2 * K];
   uint64_t pc_out[2];
   uint16_t sl_off[2 * K + 2];
@@ -326,7 +327,7 @@ struct SmallTab {
 // LDS of the descriptor-tile kernel: two stage buffers and the small tables.
 template <typename O, int K, int TILE>
 struct FastSmem {
-  static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
+  static constexpr size_t kBuf = (size_t)(TILE + 2) * sizeof(O) + (size_t)TILE * 4;
   static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
   alignas(16) unsigned char bufA[kBuf];
   alignas(16) unsigned char bufB[kBuf];
@@ -380,6 +381,7 @@ __device__ inline void build_small(SmallTab<K> &T, const TileDesc<K> &D, bool ex
     for (int j = 0; j < d; j++) {
       T.sl_off[s] = (uint16_t)off;
       T.sl_g[s] = D.src[p][j];
+      T.delta[s] = D.src[p][j] - (uint64_t)off;
       off += (int)D.len[p][j];
       s++;
     }
@@ -408,29 +410,22 @@ __device__ inline void addr_search(uint64_t (&g)[E], const uint16_t *sl_off,
   }
 }
 
-// Same for a descriptor tile (at most MAXS slices): branch-free selects over
-// the slice starts instead of a search.
+// Same for a descriptor tile: the slice of position e is the number of slice
+// starts (after the first) at or below e; its global index is delta[s] + e.
 template <int E, int THREADS, int MAXS>
-__device__ inline void addr_select(uint64_t (&g)[E], const uint16_t *sl_off,
-                                   const uint64_t *sl_g, int S, int Tt, int t) {
+__device__ inline void addr_desc(uint64_t (&g)[E], const uint16_t *sl_off, const uint64_t *delta,
+                                 int S, int Tt, int t) {
   int so[MAXS];
-  uint64_t sg[MAXS];
 #pragma unroll
-  for (int j = 0; j < MAXS; j++) {
-    so[j] = sl_off[j];
-    sg[j] = sl_g[j];
-  }
+  for (int j = 1; j < MAXS; j++) so[j] = j < S ? (int)sl_off[j] : 0x7FFFFFFF;
 #pragma unroll
   for (int i = 0; i < E; i++) {
     int e = t + i * THREADS;
     int ec = e < Tt ? e : Tt - 1;
-    uint64_t a = sg[0] + (uint64_t)(ec - so[0]);
+    int s = 0;
 #pragma unroll
-    for (int j = 1; j < MAXS; j++) {
-      bool in = j < S && so[j] <= ec;
-      a = in ? sg[j] + (uint64_t)(ec - so[j]) : a;
-    }
-    g[i] = a;
+    for (int j = 1; j < MAXS; j++) s += so[j] <= ec ? 1 : 0;
+    g[i] = delta[s] + (uint64_t)ec;
   }
 }
 
@@ -513,6 +508,84 @@ __device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, boo
   return (LOGK & 1) ? 1 : 0;
 }
 
+// The same stages for a descriptor tile (at most two pieces, MAXS slices).
+// Slice offsets are uniform and held in registers; the lane's merge unit is
+// found with compares instead of searches; the merge-path search is a
+// lower_bound; the sequential merge walks LDS byte offsets (the key buffers
+// carry one element of padding, so reading one past a unit is harmless).
+template <typename O, int K, int TILE, int THREADS, bool HV>
+__device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB,
+                                        const uint16_t *sl_off_l, int S, const uint16_t *pc_sl_l,
+                                        int P, int Tt, int t) {
+  constexpr int E = TILE / THREADS;
+  constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
+  constexpr int MAXS = 2 * K;
+  constexpr int KS = (int)sizeof(O);
+  int so[MAXS + 1];
+#pragma unroll
+  for (int j = 0; j <= MAXS; j++) so[j] = j <= S ? (int)sl_off_l[j] : Tt;
+  const int s1 = P == 2 ? (int)pc_sl_l[1] : S;   // first slice of the second piece
+  O *ks = kA, *kd = kB;
+  uint32_t *vs = vA, *vd = vB;
+#pragma unroll
+  for (int st = 1; st <= LOGK; st++) {
+    int e = t * E;
+    const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
+    while (e < e_end) {
+      int s = 0;
+#pragma unroll
+      for (int j = 1; j < MAXS; j++) s += (j < S && so[j] <= e) ? 1 : 0;
+      const int s0 = s >= s1 ? s1 : 0;
+      const int pend = s >= s1 ? S : s1;
+      const int h = 1 << (st - 1);
+      const int g0 = s0 + (((s - s0) >> st) << st);
+      const int iM = g0 + h < pend ? g0 + h : pend;
+      const int iR = g0 + 2 * h < pend ? g0 + 2 * h : pend;
+      int u0 = so[0], u1 = so[0], u2 = so[0];
+#pragma unroll
+      for (int j = 1; j <= MAXS; j++) {
+        u0 = j == g0 ? so[j] : u0;
+        u1 = j == iM ? so[j] : u1;
+        u2 = j == iR ? so[j] : u2;
+      }
+      const int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
+      int lo = diag - nR > 0 ? diag - nR : 0;
+      int cnt = (diag < nL ? diag : nL) - lo;
+      // smallest i in [lo, lo+cnt] with ks[u0+i] > ks[u1+diag-1-i]
+      while (cnt > 0) {
+        const int half = cnt >> 1;
+        const int mid = lo + half;
+        const bool p = ks[u0 + mid] <= ks[u1 + diag - 1 - mid];
+        lo = p ? mid + 1 : lo;
+        cnt = p ? cnt - half - 1 : half;
+      }
+      const int stop = e_end < u2 ? e_end : u2;
+      if (stop <= e) break;  // cannot happen with valid tables (e < u2)
+      // byte offsets into the key buffer; payload offsets are key offsets * 4 / KS
+      const char *kb8 = reinterpret_cast<const char *>(ks);
+      uint32_t pa = (uint32_t)(u0 + lo) * KS, pb = (uint32_t)(u1 + diag - lo) * KS;
+      const uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
+      O ka = *reinterpret_cast<const O *>(kb8 + pa);
+      O kb = *reinterpret_cast<const O *>(kb8 + pb);
+      for (; e < stop; e++) {
+        const bool takeL = pa < ea && (pb >= eb || ka <= kb);
+        const uint32_t src = takeL ? pa : pb;
+        kd[e] = takeL ? ka : kb;
+        if (HV) vd[e] = vs[src / KS];
+        pa += takeL ? KS : 0;
+        pb += takeL ? 0 : KS;
+        const O kn = *reinterpret_cast<const O *>(kb8 + (takeL ? pa : pb));
+        ka = takeL ? kn : ka;
+        kb = takeL ? kb : kn;
+      }
+    }
+    lds_barrier();
+    O *tk = ks; ks = kd; kd = tk;
+    uint32_t *tv = vs; vs = vd; vd = tv;
+  }
+  return (LOGK & 1) ? 1 : 0;
+}
+
 template <typename Kt, typename O, int E, int THREADS>
 __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
                                   uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
@@ -548,9 +621,9 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
   constexpr int MAXS = 2 * K;
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
-  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
+  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)(TILE + 2) * sizeof(O));
   O *kB = reinterpret_cast<O *>(sm.bufB);
-  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
+  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)(TILE + 2) * sizeof(O));
   const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
 
   const uint64_t tiles = plan->lvl_tiles[level];
@@ -571,8 +644,8 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
   lds_barrier();
   if (t < NW && tile + G < tiles) dreg = descw[(tile + G) * DW + t];
   if (sm.tab[0].kind == kTabFast) {
-    addr_select<E, THREADS, MAXS>(ga, sm.tab[0].sl_off, sm.tab[0].sl_g, sm.tab[0].S,
-                                  sm.tab[0].Tt, t);
+    addr_desc<E, THREADS, MAXS>(ga, sm.tab[0].sl_off, sm.tab[0].delta, sm.tab[0].S,
+                                sm.tab[0].Tt, t);
     issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
   }
   int cur = 0;
@@ -590,12 +663,12 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
     lds_barrier();
     if (t < NW && nxt + G < tiles) dreg = descw[(nxt + G) * DW + t];
     if (N.kind == kTabFast) {
-      addr_select<E, THREADS, MAXS>(ga, N.sl_off, N.sl_g, N.S, N.Tt, t);
+      addr_desc<E, THREADS, MAXS>(ga, N.sl_off, N.delta, N.S, N.Tt, t);
       issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
     }
     if (kind == kTabFast) {
-      int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, HV, T.sl_off, T.S, T.pc_sl,
-                                                  T.P, T.Tt, t);
+      int res = merge_stages_fast<O, K, TILE, THREADS, HV>(kA, vA, kB, vB, T.sl_off, T.S,
+                                                           T.pc_sl, T.P, T.Tt, t);
       store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
                                     T.pc_loff, T.pc_out, T.P, T.Tt, t);
     } else if (kind == kTabBad) {
