@@ -38,25 +38,30 @@ def log(*a):
 
 
 def source_hash() -> str:
+    """Hash of the level-merge kernel sources; traffic figures measured on other
+    sources are not reported."""
     h = hashlib.sha256()
-    for name in ("mps_merge.hip", "mps_internal.h"):
+    for name in ("mps_merge.h", "mps_internal.h"):
         with open(os.path.join(ROOT, "paper_2209_06909_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """Measured HBM bytes per merged element (rocprofv3 FETCH_SIZE/WRITE_SIZE),
-    valid only while the merge kernel source is unchanged."""
-    p = os.path.join(ROOT, "profiles", "merge_traffic_runs_i64.json")
+def committed_traffic(tag: str):
+    """HBM bytes per merged element of the level merges, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary kept in profiles/ (calibrated against a copy
+    of known size); None if the merge kernel changed since it was measured."""
+    p = os.path.join(ROOT, "profiles", f"merge_traffic_{tag}.txt")
     try:
         with open(p) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line
+                      and not line.startswith(("|", "#", " ")))
+    except OSError:
         return None
-    if d.get("source_hash") != source_hash():
+    if kv.get("source_hash", "").strip() != source_hash():
         return None
-    return d
+    return {"bytes_per_merged_element": float(kv["bytes_per_merged_element"]),
+            "ratio_to_algorithmic": float(kv["ratio_to_algorithmic"])}
 
 
 def cpu_baseline(keys: np.ndarray, pay: np.ndarray, sample_n: int, k: int):
@@ -76,6 +81,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=2048, help="merge tile (outputs)")
+    ap.add_argument("--lane-slice", type=int, default=4, help="outputs per thread per LDS stage")
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-sample-log2n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,7 +111,8 @@ def main():
     # one untimed traced sort: runs, merge cost and placement volume
     keys.copy_(keys0)
     pay.copy_(pay0)
-    tr = mps.sort(keys, pay, k=args.k, trace=True)
+    tcfg = dict(tile=args.tile, lane_slice=args.lane_slice)
+    tr = mps.sort(keys, pay, k=args.k, trace=True, **tcfg)
     rs = tr.run_start.astype(np.int64)
     lens = np.diff(rs)
     moved = (tr.leaf_depth & 1).astype(bool) | tr.run_desc.astype(bool)
@@ -115,7 +123,7 @@ def main():
     for _ in range(args.warmup):
         keys.copy_(keys0)
         pay.copy_(pay0)
-        mps.sort(keys, pay, k=args.k)
+        mps.sort(keys, pay, k=args.k, **tcfg)
     torch.cuda.synchronize()
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -131,7 +139,7 @@ def main():
         keys.copy_(keys0)
         pay.copy_(pay0)
         ev[i][0].record()
-        mps.sort(keys, pay, k=args.k, time_levels=True)
+        mps.sort(keys, pay, k=args.k, time_levels=True, **tcfg)
         ev[i][1].record()
         elems, cms, mms = mps.level_stats()
         live = elems > 0
@@ -158,11 +166,15 @@ def main():
             "bytes_per_unit": 2 * KV, "unit_of_work": "merged element (key+payload read and written)",
             "avg_launch_ms": round(merge_ms / merge_launches, 4),
             "launches": merge_launches}
-    tr_d = committed_traffic()
+    tr_d = committed_traffic(f"runs_i64_2p{args.log2n}") if args.k == 4 and args.tile == 2048 \
+        and args.lane_slice == 4 else None
     if tr_d is not None:
-        per_launch = tr.merge_cost / max(1, tr.n_levels)
+        # per launch like `achieved`: the measured bytes per merged element times the
+        # merged elements of an average launch
+        per_launch = merge_bytes / merge_launches / (2 * KV)
         roof["traffic"] = round(tr_d["bytes_per_merged_element"] * per_launch)
         roof["traffic_per_merged_element"] = tr_d["bytes_per_merged_element"]
+        roof["traffic_ratio_to_algorithmic"] = tr_d["ratio_to_algorithmic"]
     levels_all = merge_bytes / ((merge_ms + corank_ms) * 1e-3) / 1e9
     sort_bytes = n * 8 + 2 * KV * placed + 2 * KV * tr.merge_cost
     sort_gbs = sort_bytes / (ms * 1e-3) / 1e9
@@ -175,7 +187,8 @@ def main():
         "config": {"workload": "runs_i64: n=2^%d int64 keys uniform over the full range, uint32 "
                                "index payload, random runs of length U{1..2*sqrt(n)} each sorted "
                                "ascending (seed 2)" % args.log2n,
-                   "n": n, "k": args.k, "key": "int64", "payload": "uint32"},
+                   "n": n, "k": args.k, "key": "int64", "payload": "uint32",
+                   "tile": args.tile, "lane_slice": args.lane_slice},
         "roofline": roof,
         "merge_levels_incl_corank": {"achieved_GBs": round(levels_all, 1),
                                      "frac": round(levels_all / HBM_PEAK_GBS, 4),

@@ -50,6 +50,12 @@ typedef enum { MPS_I32 = 0, MPS_I64 = 1, MPS_F32 = 2 } mps_key_type;
 /* Option flags (mps_opts.flags). */
 #define MPS_OPT_TIME_LEVELS 1u  /* record HIP events around every level's co-rank and merge
                                    launches (read them with mps_last_level_stats) */
+#define MPS_OPT_GRAPH 2u        /* capture the call's launch sequence in a HIP graph the first
+                                   time these exact arguments (pointers, sizes, options) are
+                                   seen and replay the graph on later calls; the graph reads
+                                   every data-dependent quantity on the device, so new
+                                   contents of keys / payload / offsets are fine.  Not with
+                                   MPS_OPT_TIME_LEVELS. */
 
 /* Options.  All fields may be zero for defaults. */
 typedef struct {
@@ -58,6 +64,11 @@ typedef struct {
     void *workspace;            /* device memory of >= mps_workspace_bytes(); NULL: the
                                    library allocates and caches one per device */
     uint64_t workspace_bytes;
+    uint32_t tile;              /* merge tile, outputs per workgroup task: 1024, 2048
+                                   (default) or 4096 */
+    uint32_t lane_slice;        /* outputs each thread merges per LDS stage (tile divided by
+                                   the workgroup size): 4 or 8; 0 = 8 for 4096-tiles, 4
+                                   otherwise.  Valid pairs: 1024/4, 2048/8, 2048/4, 4096/8 */
 } mps_opts;
 
 /* What the sort did (filled when a trace pointer is passed; forces a stream
@@ -114,6 +125,25 @@ int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
 int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload, const uint64_t *offsets,
                      const uint64_t *h_offsets, uint64_t m, uint64_t total_n,
                      const mps_opts *opts, mps_trace *trace, void *stream);
+
+/* Autotuner for batched sorts (a systems layer; the paper has no such step).
+ * Times every candidate configuration -- arity k in {4, 2, 8} times the tile
+ * configurations (tile, lane_slice) in {2048/8, 1024/4, 2048/4, 4096/8}, in
+ * that order -- on a sample of the batch (whole arrays from the start, up to
+ * sample_cap keys; 0 = 2^24) and writes the fastest into best->k, best->tile
+ * and best->lane_slice (other fields untouched).  keys / payload are the
+ * batch's device arrays (read only; the sample is copied), h_offsets its host
+ * offsets [m+1].  flags: 0 or MPS_OPT_GRAPH (time graph replays, as a caller
+ * using MPS_OPT_GRAPH will run).  cand_ms (nullable, 12 floats) receives every
+ * candidate's mean time in ms.  The choice is cached per device, key type,
+ * payload presence, log2(total keys) and log2(mean array size); a cached
+ * choice is returned without timing unless cand_ms is requested.  Allocates
+ * tuner memory (about twice the sample plus a workspace) for the duration of
+ * the call and synchronises `stream`.  Note that k changes the merge tree
+ * (powers are base-k), never the sorted result. */
+int mps_autotune(const void *keys, mps_key_type kt, const uint32_t *payload,
+                 const uint64_t *h_offsets, uint64_t m, uint64_t sample_cap, uint32_t flags,
+                 mps_opts *best, float *cand_ms, void *stream);
 
 /* Fills trace (counters and every array the caller supplies) from the most
  * recent sort that used `workspace` (the opts->workspace pointer of that

@@ -135,8 +135,10 @@ def _take_trace(t: _Trace) -> Trace:
 
     nodes = np.zeros(nn, dtype=NODE_DTYPE)
     if nn:
-        raw = ctypes.string_at(ctypes.cast(t.nodes, ctypes.c_void_p), nn * NODE_DTYPE.itemsize)
-        nodes = np.frombuffer(raw, dtype=NODE_DTYPE).copy()
+        # a byte view (ctypes.string_at takes a C int size, too small past 2 GiB)
+        raw = np.ctypeslib.as_array(ctypes.cast(t.nodes, ctypes.POINTER(ctypes.c_uint8)),
+                                    shape=(nn * NODE_DTYPE.itemsize,))
+        nodes = raw.copy().view(NODE_DTYPE)
     tr = Trace(n=int(t.n), r=r, k=int(t.k),
                run_start=arr(t.run_start, r + 1, np.uint64),
                run_desc=arr(t.run_desc, r, np.uint8),

@@ -29,8 +29,8 @@ _STATUS = {-1: "MPS_E_INVALID", -2: "MPS_E_NOMEM", -3: "MPS_E_HIP", -4: "MPS_E_U
 KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
 
 EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
-            "mps_sort_ex", "mps_sort_batched", "mps_trace_fetch", "mps_last_level_stats",
-            "mps_last_error"]
+            "mps_sort_ex", "mps_sort_batched", "mps_autotune", "mps_trace_fetch",
+            "mps_last_level_stats", "mps_last_error"]
 
 
 class MpsError(RuntimeError):
@@ -40,11 +40,21 @@ class MpsError(RuntimeError):
 
 
 OPT_TIME_LEVELS = 1
+OPT_GRAPH = 2
+# merge tile configurations: (outputs per tile, outputs per thread per LDS stage)
+TILE_CONFIGS = [(1024, 4), (2048, 8), (2048, 4), (4096, 8)]
 
 
 class _Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("tile", ctypes.c_uint32), ("lane_slice", ctypes.c_uint32)]
+
+
+def _opts(k, ws, *, time_levels=False, graph=False, tile=None, lane_slice=None) -> _Opts:
+    flags = (OPT_TIME_LEVELS if time_levels else 0) | (OPT_GRAPH if graph else 0)
+    return _Opts(k=k, flags=flags, workspace=ws.data_ptr(), workspace_bytes=ws.numel(),
+                 tile=int(tile or 0), lane_slice=int(lane_slice or 0))
 
 
 class _Trace(ctypes.Structure):
@@ -90,6 +100,8 @@ def lib() -> ctypes.CDLL:
             l.mps_sort_batched.argtypes = [P, i32, P, P, P, u64, u64, ctypes.POINTER(_Opts),
                                            ctypes.POINTER(_Trace), P]
             l.mps_sort_batched.restype = i32
+            l.mps_autotune.argtypes = [P, i32, P, P, u64, u64, u32, ctypes.POINTER(_Opts), P, P]
+            l.mps_autotune.restype = i32
             l.mps_trace_fetch.argtypes = [P, ctypes.POINTER(_Trace)]
             l.mps_trace_fetch.restype = i32
             l.mps_last_level_stats.argtypes = [u32, P, P, P, P]
@@ -209,12 +221,15 @@ def _stream_ptr(device, stream):
 
 
 def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
-         stream=None, time_levels: bool = False):
+         stream=None, time_levels: bool = False, graph: bool = False, tile: int | None = None,
+         lane_slice: int | None = None):
     """Stable multiway Powersort of a 1-D GPU tensor, in place.
 
     keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
     payload: optional int32/uint32 tensor of the same length, permuted with the keys.
     trace: if True, synchronise and return a Trace (runs, powers, nodes, merge cost).
+    graph: capture the launch sequence in a HIP graph (replayed on identical calls).
+    tile, lane_slice: merge tile configuration, one of TILE_CONFIGS (default 2048, 4).
     """
     _check_tensors(keys, payload)
     kt = key_type_of(keys)
@@ -224,8 +239,7 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
-    opts = _Opts(k=k, flags=OPT_TIME_LEVELS if time_levels else 0, workspace=ws.data_ptr(),
-                 workspace_bytes=ws.numel())
+    opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice)
     t = _Trace() if trace else None
     _check(lib().mps_sort_ex(ctypes.c_void_p(keys.data_ptr()), kt,
                              ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
@@ -250,11 +264,14 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
 
 
 def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
-                 trace_arrays: bool = True, stream=None, host_offsets=None):
+                 trace_arrays: bool = True, stream=None, host_offsets=None,
+                 time_levels: bool = False, graph: bool = False, tile: int | None = None,
+                 lane_slice: int | None = None):
     """Sort m independent arrays packed back to back in `keys` (and `payload`).
 
     offsets: GPU int64/uint64 tensor of m+1 entries (offsets[0] = 0, offsets[m] = len(keys)).
-    Every array is sorted exactly as sort() would sort it alone.
+    Every array is sorted exactly as sort() would sort it alone.  graph / tile /
+    lane_slice as for sort().
     """
     torch = _torch()
     _check_tensors(keys, payload)
@@ -273,7 +290,7 @@ def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
-    opts = _Opts(k=k, flags=0, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
+    opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice)
     t = _Trace() if trace else None
     _check(lib().mps_sort_batched(
         ctypes.c_void_p(keys.data_ptr()), kt,
@@ -285,6 +302,33 @@ def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
     if t is None:
         return None
     return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)
+
+
+TUNE_CANDIDATES = [(k, t, e) for k in (4, 2, 8) for (t, e) in TILE_CONFIGS]
+
+
+def autotune(keys, payload, host_offsets, *, sample_keys: int = 1 << 24, graph: bool = True,
+             stream=None, with_times: bool = False):
+    """Pick arity and merge tile configuration for batched sorts of this shape by
+    timing every candidate on a sample of the batch (see mps_autotune).  Returns
+    dict(k=, tile=, lane_slice=) and, with with_times, the per-candidate times."""
+    _check_tensors(keys, payload)
+    kt = key_type_of(keys)
+    hoff = np.ascontiguousarray(host_offsets, dtype=np.uint64)
+    m = hoff.size - 1
+    best = _Opts()
+    times = np.zeros(len(TUNE_CANDIDATES), np.float32) if with_times else None
+    _check(lib().mps_autotune(
+        ctypes.c_void_p(keys.data_ptr()), kt,
+        ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
+        hoff.ctypes.data_as(ctypes.c_void_p), m, int(sample_keys), OPT_GRAPH if graph else 0,
+        ctypes.byref(best), times.ctypes.data_as(ctypes.c_void_p) if times is not None else None,
+        _stream_ptr(keys.device, stream)))
+    out = dict(k=int(best.k), tile=int(best.tile), lane_slice=int(best.lane_slice))
+    if with_times:
+        out["candidates"] = [dict(k=k, tile=t, lane_slice=e, ms=float(x))
+                             for (k, t, e), x in zip(TUNE_CANDIDATES, times)]
+    return out
 
 
 def level_stats(cap: int = 64):

@@ -8,6 +8,7 @@
 // deeper than the actual tree find zero tiles and return at once.
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 #include <map>
 #include <cstring>
@@ -66,6 +67,8 @@ static int fail(int code, const std::string &msg) {
 
 extern "C" const char *mps_last_error(void) { return g_err.c_str(); }
 
+int mps::fail_msg(int code, const char *msg) { return fail(code, msg); }
+
 // ---------------------------------------------------------------- layout
 namespace {
 
@@ -104,7 +107,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   uint64_t nwords = (N + 63) / 64;
   uint64_t nblk = (N + 16383) / 16384;
   uint64_t nbb = (rmax + 1 + 1023) / 1024 + 1;
-  uint64_t tiles_max = N / kTileSize + 2;
+  uint64_t tiles_max = N / kTileMin + 2;   // enough for every tile configuration
   int levels = levels_for(N, k);
   if (levels >= kMaxLevels) return false;
   size_t c = 0;
@@ -256,11 +259,113 @@ struct LevelTiming {
 std::mutex g_time_mu;
 LevelTiming g_time[64];
 
+// The launch sequence of one sort on stream s (also what a graph captures).
+int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, const Work &w,
+                 const Layout &L, uint64_t *lvl_tot, uint64_t *tile_base, uint32_t *tj,
+                 int want_cost, LevelTiming *tm, hipStream_t s) {
+  const unsigned gtree = (unsigned)(L.nbb < 4096 ? L.nbb : 4096);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.plan, w.seg_off_local, w.N, w.m,
+                     (uint32_t)kt, payload ? 1u : 0u, (uint32_t)w.k, d_off ? 0 : 1);
+  if (d_off)
+    hipLaunchKernelGGL(k_check_offsets, dim3(64), dim3(256), 0, s, d_off, w.m, w.N, w.plan);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_detect(kt, keys, w, s));
+  HIP_TRY(launch_tree(w, want_cost, lvl_tot, tile_base, tj, gtree, s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_place(kt, keys, payload, w, s));
+  for (int d = L.levels - 1; d >= 0; d--) {
+    LevelArgs a;
+    bool out_user = (d & 1) == 0;
+    a.in_keys = out_user ? w.alt_keys : keys;
+    a.in_vals = payload ? (out_user ? w.alt_vals : payload) : nullptr;
+    a.out_keys = out_user ? keys : w.alt_keys;
+    a.out_vals = payload ? (out_user ? payload : w.alt_vals) : nullptr;
+    if (tm) {
+      HIP_TRY(launch_level_timed(kt, a, w, tj, tile_base, d, s, tm->ev[3 * d], tm->ev[3 * d + 1],
+                                 tm->ev[3 * d + 2]));
+    } else {
+      HIP_TRY(launch_level(kt, a, w, tj, tile_base, d, s));
+    }
+  }
+  return MPS_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+// Instantiated graphs of whole sorts, keyed by every argument that shapes the
+// launch sequence.  Captured on a library stream (capture only records), then
+// launched on the caller's stream.
+struct GraphKey {
+  int dev, kt, k, tile, threads, want_cost;
+  const void *keys, *payload, *off, *base;
+  uint64_t m, N;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(dev, kt, k, tile, threads, want_cost, keys, payload, off, base, m, N) <
+           std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.keys, o.payload, o.off,
+                    o.base, o.m, o.N);
+  }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+hipStream_t g_capture_stream[64];
+constexpr size_t kMaxGraphs = 256;
+
+int graph_launch(const GraphKey &key, void *keys, int kt, uint32_t *payload,
+                 const uint64_t *d_off, const Work &w, const Layout &L, uint64_t *lvl_tot,
+                 uint64_t *tile_base, uint32_t *tj, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    if (key.dev < 0 || key.dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");
+    hipStream_t &cs = g_capture_stream[key.dev];
+    if (!cs) HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    if (g_graphs.size() >= kMaxGraphs) {
+      for (auto &e : g_graphs) (void)hipGraphExecDestroy(e.second);
+      g_graphs.clear();
+    }
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    int rc = enqueue_sort(keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, key.want_cost,
+                          nullptr, cs);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (rc != MPS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(MPS_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipGraphExec_t ge = nullptr;
+    hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(MPS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    it = g_graphs.emplace(key, ge).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, s));
+  return MPS_OK;
+}
+
+int resolve_tile(const mps_opts *opts, int &tile, int &threads) {
+  uint32_t t = opts && opts->tile ? opts->tile : (uint32_t)kTileDefault;
+  uint32_t e = opts ? opts->lane_slice : 0;
+  if (e == 0) e = t == 4096 ? 8 : 4;   // measured fastest per tile size
+  if (t != 1024 && t != 2048 && t != 4096) return fail(MPS_E_UNSUPPORTED, "tile must be 1024, 2048 or 4096");
+  if (e != 4 && e != 8) return fail(MPS_E_UNSUPPORTED, "lane_slice must be 4 or 8");
+  if (!tile_config_ok((int)t, (int)(t / e)))
+    return fail(MPS_E_UNSUPPORTED, "unsupported tile / lane_slice pair (1024/4, 2048/8, 2048/4, 4096/8)");
+  tile = (int)t;
+  threads = (int)(t / e);
+  return MPS_OK;
+}
+
 int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint64_t m,
              uint64_t N, const mps_opts *opts, mps_trace *trace, hipStream_t s) {
   uint32_t k = opts ? opts->k : 0;
   int rc = check_k(k);
   if (rc) return rc;
+  int tile = 0, threads = 0;
+  rc = resolve_tile(opts, tile, threads);
+  if (rc) return rc;
+  const uint32_t flags = opts ? opts->flags : 0;
+  if ((flags & MPS_OPT_GRAPH) && (flags & MPS_OPT_TIME_LEVELS))
+    return fail(MPS_E_INVALID, "MPS_OPT_GRAPH cannot be combined with MPS_OPT_TIME_LEVELS");
   Layout L;
   if (!make_layout(N, m, kt, payload != nullptr, k, L)) return fail(MPS_E_INVALID, "bad sizes");
   void *base = nullptr;
@@ -280,7 +385,8 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   w.rmax = L.rmax;
   w.k = (int)k;
   w.logk = k == 2 ? 1 : (k == 4 ? 2 : 3);
-  w.tile = kTileSize;
+  w.tile = tile;
+  w.threads = threads;
   w.alt_keys = at<void>(base, L.alt_keys);
   w.alt_vals = payload ? at<uint32_t>(base, L.alt_vals) : nullptr;
   w.seg_off_local = at<uint64_t>(base, L.seg_off);
@@ -318,51 +424,33 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   uint64_t *lvl_tot = at<uint64_t>(base, L.lvl_tot);
   uint64_t *tile_base = at<uint64_t>(base, L.tile_base);
   uint32_t *tj = at<uint32_t>(base, L.tj);
+  const int want_cost = trace ? 1 : 0;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
 
-  const unsigned gtree = (unsigned)(L.nbb < 4096 ? L.nbb : 4096);
-
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.plan, w.seg_off_local, N, m, (uint32_t)kt,
-                     payload ? 1u : 0u, k, d_off ? 0 : 1);
-  if (d_off)
-    hipLaunchKernelGGL(k_check_offsets, dim3(64), dim3(256), 0, s, d_off, m, N, w.plan);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(launch_detect(kt, keys, w, s));
-  HIP_TRY(launch_tree(w, trace ? 1 : 0, lvl_tot, tile_base, tj, gtree, s));
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(launch_place(kt, keys, payload, w, s));
-  LevelTiming *tm = nullptr;
-  if (opts && (opts->flags & MPS_OPT_TIME_LEVELS)) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");
-    std::lock_guard<std::mutex> lk(g_time_mu);
-    tm = &g_time[dev];
-    while (tm->ev.size() < (size_t)L.levels * 3) {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
-      tm->ev.push_back(e);
+  if (flags & MPS_OPT_GRAPH) {
+    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, keys, payload, d_off, base, m, N};
+    rc = graph_launch(key, keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, s);
+    if (rc) return rc;
+  } else {
+    LevelTiming *tm = nullptr;
+    std::unique_lock<std::mutex> tlk(g_time_mu, std::defer_lock);
+    if (flags & MPS_OPT_TIME_LEVELS) {
+      if (dev < 0 || dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");
+      tlk.lock();
+      tm = &g_time[dev];
+      while (tm->ev.size() < (size_t)L.levels * 3) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        tm->ev.push_back(e);
+      }
+      tm->levels = L.levels;
+      tm->base = base;
     }
-    tm->levels = L.levels;
-    tm->base = base;
+    rc = enqueue_sort(keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, want_cost, tm, s);
+    if (rc) return rc;
   }
-  for (int d = L.levels - 1; d >= 0; d--) {
-    LevelArgs a;
-    bool out_user = (d & 1) == 0;
-    a.in_keys = out_user ? w.alt_keys : keys;
-    a.in_vals = payload ? (out_user ? w.alt_vals : payload) : nullptr;
-    a.out_keys = out_user ? keys : w.alt_keys;
-    a.out_vals = payload ? (out_user ? payload : w.alt_vals) : nullptr;
-    if (tm) {
-      HIP_TRY(launch_level_timed(kt, a, w, tj, tile_base, d, s, tm->ev[3 * d], tm->ev[3 * d + 1],
-                                 tm->ev[3 * d + 2]));
-    } else {
-      HIP_TRY(launch_level(kt, a, w, tj, tile_base, d, s));
-    }
-  }
-  if (!(opts && opts->workspace)) {
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) g_last_base[dev] = base;
-  }
+  if (!(opts && opts->workspace) && dev >= 0 && dev < 64) g_last_base[dev] = base;
   if (trace) return fill_trace(base, trace);
   return MPS_OK;
 }

@@ -53,6 +53,8 @@ struct Plan {
   uint64_t lvl_total[kMaxLevels];    // sum of node sizes per level
   uint64_t lvl_tiles[kMaxLevels];    // merge tiles per level
   uint32_t gen_cnt[kMaxLevels];      // tiles per level that need the general merge path
+  uint32_t q_fast[kMaxLevels];       // work-queue heads of the two merge kernels, per level
+  uint32_t q_gen[kMaxLevels];
 };
 
 // Run-detection block aggregate (16384 positions per block).
@@ -65,7 +67,7 @@ struct DetAgg {
 // Device views of the workspace.
 struct Work {
   uint64_t N, m, rmax;
-  int k, logk, tile;
+  int k, logk, tile, threads;         // arity; merge tile (outputs) and workgroup size
   void *alt_keys;
   uint32_t *alt_vals;
   const uint64_t *off;               // segment offsets [m+1]
@@ -155,8 +157,19 @@ struct LevelArgs {
   uint32_t *out_vals;
 };
 
-constexpr int kTileSize = 2048;   // outputs per merge tile
+// Merge tile configurations (outputs per tile x threads per workgroup):
+// 1024x256, 2048x256, 2048x512 (default) and 4096x512.
+constexpr int kTileMin = 1024;
+constexpr int kTileDefault = 2048;
 constexpr int kTileDescBytes = 256;  // >= sizeof(TileDesc<8>)
+
+inline bool tile_config_ok(int tile, int threads) {
+  return (tile == 1024 && threads == 256) || (tile == 2048 && threads == 256) ||
+         (tile == 2048 && threads == 512) || (tile == 4096 && threads == 512);
+}
+
+// Records the calling thread's error message (read by mps_last_error) and returns code.
+int fail_msg(int code, const char *msg);
 
 hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s);
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
@@ -164,7 +177,17 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                         const uint64_t *tile_base, int level, hipStream_t s);
-// Same, with events recorded before the co-rank, between co-rank and merge,
+// The merge launches of one level for one tile configuration (each defined in
+// its own translation unit).
+#define MPS_DECLARE_MERGES(NAME)                                                          \
+  hipError_t NAME(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,         \
+                  const uint64_t *tile_base, int level, hipStream_t s);
+MPS_DECLARE_MERGES(launch_merges_1024x256)
+MPS_DECLARE_MERGES(launch_merges_2048x256)
+MPS_DECLARE_MERGES(launch_merges_2048x512)
+MPS_DECLARE_MERGES(launch_merges_4096x512)
+#undef MPS_DECLARE_MERGES
+// Same as launch_level, with events recorded before the co-rank, between co-rank and merge,
 // and after the merge launch (all on stream s).
 hipError_t launch_level_timed(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                               const uint64_t *tile_base, int level, hipStream_t s,

@@ -10,16 +10,8 @@
 // strictly decreasing run is reversed on the way (paper, Section 2: such runs
 // hold no equal keys, so reversing keeps the sort stable).
 //
-// Each level is cut into tiles of exactly `tile` outputs over the
-// concatenation of its nodes (a tile may cover the tail of one node, whole
-// small nodes and the head of another).  For every tile boundary a co-rank
-// step finds how many elements of each child precede it in the stable merged
-// order (key, then child index: equal keys keep their input order, as in the
-// paper's merges where the left run wins ties).  A workgroup then stages the
-// tile's input slices in LDS and merges them by a binary tree of 2-way
-// merge-path merges (log2 k stages), all in LDS, and writes the tile back
-// with coalesced stores.
-#include "mps_internal.h"
+// The level merges themselves are in mps_merge.h.
+#include "mps_merge.h"
 
 namespace mps {
 
@@ -80,736 +72,6 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
   }
 }
 
-// ---------------------------------------------------------------- node access
-struct NodeIn {
-  uint64_t c[9];   // child boundaries: c[0] = span start, c[d] = span end
-  int d;
-};
-
-// Child boundaries of node v; false (and nothing read through a bad index)
-// if the node record is inconsistent.
-template <int K>
-__device__ inline bool load_node(uint32_t v, uint64_t r, const uint64_t *rs, const uint32_t *Ls,
-                                 const uint32_t *Rs, const uint32_t *mem,
-                                 const uint8_t *arity, NodeIn &nd) {
-  if (v >= r) return false;
-  int d = arity[v];
-  if (d < 2 || d > K) return false;
-  nd.d = d;
-  uint32_t l = Ls[v], rr = Rs[v];
-  if (l >= v || rr > r || rr <= v) return false;
-  nd.c[0] = rs[l];
-  uint32_t prev = l;
-  for (int j = 1; j < d; j++) {
-    uint32_t b = mem[(uint64_t)v * (K - 1) + (j - 1)];
-    if (b <= prev || b >= rr) return false;
-    nd.c[j] = rs[b];
-    prev = b;
-  }
-  nd.c[d] = rs[rr];
-  return true;
-}
-
-// Stable order across children: (key, child index).
-template <typename O>
-__device__ inline bool st_less(O x, int a, O y, int b) {
-  return x < y || (x == y && a < b);
-}
-
-// ---------------------------------------------------------------- co-rank
-// Cut of a node at output rank q: c_j = number of elements of child j among
-// the first q outputs.  Windows [lo_j, hi_j] always contain c_j.  Each round
-// splits the remaining rank over the windows proportionally, checks whether
-// the split is a consistent cut (largest taken < smallest untaken in the
-// stable order) and otherwise shrinks the window of the largest taken element
-// from above and that of the smallest untaken element from below.
-template <int KT, int K>
-__global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__restrict__ in_keys,
-                                                const uint64_t *__restrict__ rs,
-                                                const uint32_t *__restrict__ Ls,
-                                                const uint32_t *__restrict__ Rs,
-                                                const uint32_t *__restrict__ mem,
-                                                const uint8_t *__restrict__ arity,
-                                                const uint32_t *__restrict__ list,
-                                                const uint64_t *__restrict__ np,
-                                                const uint32_t *__restrict__ tj,
-                                                const uint64_t *__restrict__ tile_base,
-                                                Plan *__restrict__ plan, int level,
-                                                int tile, uint32_t *__restrict__ cr) {
-  using O = typename Key<KT>::U;
-  const uint64_t tiles = plan->lvl_tiles[level];
-  if (tiles == 0) return;
-  const uint64_t r = plan->r;
-  const uint64_t lb = plan->lvl_begin[level];
-  const uint64_t nlev = plan->lvl_begin[level + 1] - lb;
-  const uint64_t np0 = np[lb];
-  const uint32_t *tjl = tj + tile_base[level];
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tiles;
-       t += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t out[K];
-    for (int j = 0; j < K; j++) out[j] = 0;
-    if (t > 0) {
-      uint64_t Q = t * (uint64_t)tile;
-      uint32_t jn = tjl[t];
-      uint64_t q = jn < nlev ? Q - (np[lb + jn] - np0) : 0;
-      NodeIn nd;
-      if (jn >= nlev || !load_node<K>(list[lb + jn], r, rs, Ls, Rs, mem, arity, nd) ||
-          q >= nd.c[nd.d] - nd.c[0]) {
-        atomicOr(&plan->error, 128u);
-        q = 0;
-      }
-      if (q > 0) {
-        const int d = nd.d;
-        uint64_t lo[K], hi[K], mm[K];
-        for (int j = 0; j < K; j++) {
-          uint64_t len = j < d ? nd.c[j + 1] - nd.c[j] : 0;
-          lo[j] = 0;
-          hi[j] = len < q ? len : q;
-        }
-        for (int it = 0; it < 4096; it++) {
-          uint64_t slo = 0, W = 0;
-          for (int j = 0; j < d; j++) { slo += lo[j]; W += hi[j] - lo[j]; }
-          uint64_t rem = q - slo;
-          if (rem == 0) { for (int j = 0; j < d; j++) mm[j] = 0; break; }
-          if (rem == W) { for (int j = 0; j < d; j++) mm[j] = hi[j] - lo[j]; break; }
-          uint64_t sm = 0;
-          for (int j = 0; j < d; j++) {
-            uint64_t w = hi[j] - lo[j];
-            mm[j] = (w * rem) / W;  // w < 2^31, rem < 2^32
-            sm += mm[j];
-          }
-          for (int j = 0; j < d && sm < rem; j++)
-            if (mm[j] < hi[j] - lo[j]) { mm[j]++; sm++; }
-          int a = -1, b = -1;
-          O xa = 0, yb = 0;
-          for (int j = 0; j < d; j++) {
-            uint64_t w = hi[j] - lo[j];
-            uint64_t base = nd.c[j] + lo[j];
-            if (mm[j] > 0) {
-              O x = Key<KT>::ord(in_keys[base + mm[j] - 1]);
-              if (a < 0 || !st_less(x, j, xa, a)) { xa = x; a = j; }
-            }
-            if (mm[j] < w) {
-              O y = Key<KT>::ord(in_keys[base + mm[j]]);
-              if (b < 0 || st_less(y, j, yb, b)) { yb = y; b = j; }
-            }
-          }
-          // Consistent cut: the largest taken element precedes the smallest
-          // untaken one.  Within one child positions decide, so a == b is
-          // always consistent; across children (key, child) decides.
-          if (a < 0 || b < 0 || a == b || st_less(xa, a, yb, b)) break;
-          hi[a] = lo[a] + mm[a] - 1;
-          lo[b] = lo[b] + mm[b] + 1;
-        }
-        for (int j = 0; j < d; j++) out[j] = (uint32_t)(lo[j] + mm[j]);
-      }
-    }
-    for (int j = 0; j < K; j++) cr[t * K + j] = out[j];
-  }
-}
-
-// ---------------------------------------------------------------- tile merge
-// A tile covers output positions [Q0, Q1) of the level's node concatenation;
-// j0/j1 are the first and last node it touches.
-struct TileGeom {
-  uint64_t Q0, Q1, j0, j1;
-  bool ok;
-};
-
-__device__ inline TileGeom tile_geom(uint64_t tile, int tsize, uint64_t L, uint64_t nlev,
-                                     const uint64_t *np, uint64_t lb, uint64_t np0,
-                                     const uint32_t *tjl) {
-  TileGeom g;
-  g.Q0 = tile * (uint64_t)tsize;
-  g.Q1 = g.Q0 + tsize < L ? g.Q0 + tsize : L;
-  g.j0 = tjl[tile];
-  if (g.Q1 == L) {
-    g.j1 = nlev - 1;
-  } else {
-    uint64_t jn = tjl[tile + 1];
-    g.j1 = (jn < nlev && np[lb + jn] - np0 == g.Q1) ? jn - 1 : jn;
-  }
-  g.ok = g.j0 <= g.j1 && g.j1 < nlev;
-  return g;
-}
-
-// Per-tile descriptor for tiles that touch at most two nodes (the common case
-// once nodes are larger than a tile): global start and length of every input
-// slice and the output start of every piece, so that the merge kernel does not
-// chase node records through dependent global loads.
-template <int K>
-struct TileDesc {
-  uint64_t out[2];
-  uint64_t src[2][K];
-  uint32_t len[2][K];
-  uint32_t d[2];
-  uint32_t npieces;   // 1 or 2: use this descriptor; 0: general setup; kBadTile: inconsistent
-  uint32_t total;
-};
-constexpr uint32_t kBadTile = 0xFFFFFFFFu;
-static_assert(sizeof(TileDesc<8>) <= kTileDescBytes, "tile descriptor slot too small");
-
-template <int K>
-__global__ __launch_bounds__(256) void k_tile_desc(
-    const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
-    const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
-    const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
-    const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
-    const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level, int tsize,
-    const uint32_t *__restrict__ cr, TileDesc<K> *__restrict__ desc,
-    uint32_t *__restrict__ gen_list) {
-  const uint64_t tiles = plan->lvl_tiles[level];
-  if (tiles == 0) return;
-  const uint64_t r = plan->r;
-  const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
-  const uint64_t nlev = le - lb;
-  const uint64_t np0 = np[lb];
-  const uint64_t L = np[le] - np0;
-  const uint32_t *tjl = tj + tile_base[level];
-  for (uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; tile < tiles;
-       tile += (uint64_t)gridDim.x * blockDim.x) {
-    TileDesc<K> D;
-    TileGeom g = tile_geom(tile, tsize, L, nlev, np, lb, np0, tjl);
-    D.total = (uint32_t)(g.Q1 - g.Q0);
-    D.npieces = 0;
-    for (int p = 0; p < 2; p++) {
-      D.out[p] = 0;
-      D.d[p] = 0;
-      for (int j = 0; j < K; j++) { D.src[p][j] = 0; D.len[p][j] = 0; }
-    }
-    if (!g.ok) {
-      D.npieces = kBadTile;
-    } else if (g.j1 - g.j0 + 1 <= 2) {
-      const int P = (int)(g.j1 - g.j0 + 1);
-      uint64_t sum = 0;
-      bool bad = false;
-      for (int p = 0; p < P && !bad; p++) {
-        uint64_t j = g.j0 + p;
-        NodeIn nd;
-        if (!load_node<K>(list[lb + j], r, rs, Ls, Rs, mem, arity, nd)) { bad = true; break; }
-        bool first = p == 0;
-        bool cut_end = p == P - 1 && g.Q1 < np[lb + j + 1] - np0;
-        D.d[p] = (uint32_t)nd.d;
-        D.out[p] = nd.c[0] + (first ? g.Q0 - (np[lb + j] - np0) : 0);
-        for (int jj = 0; jj < nd.d; jj++) {
-          uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
-          uint32_t c0 = first ? cr[tile * K + jj] : 0;
-          uint32_t c1 = cut_end ? cr[(tile + 1) * K + jj] : len;
-          if (c1 > len || c0 > c1) { bad = true; break; }
-          D.src[p][jj] = nd.c[jj] + c0;
-          D.len[p][jj] = c1 - c0;
-          sum += c1 - c0;
-        }
-      }
-      D.npieces = (bad || sum != D.total) ? kBadTile : (uint32_t)P;
-    } else {
-      gen_list[atomicAdd(&plan->gen_cnt[level], 1u)] = (uint32_t)tile;
-    }
-    desc[tile] = D;
-  }
-}
-
-// Small tables of one descriptor-described tile (double-buffered: the next
-// tile's tables are built while the current tile is merged).
-enum { kTabNone = 0, kTabFast = 1, kTabGeneral = 2, kTabBad = 3 };
-
-template <int K>
-struct SmallTab {
-  uint64_t delta[2 * K];   // sl_g[s] - sl_off[s]: global index of LDS position e is delta[s] + e
-  uint64_t sl_g[2 * K];
-  uint64_t pc_out[2];
-  uint16_t sl_off[2 * K + 2];
-  uint16_t pc_loff[3];
-  uint16_t pc_sl[3];
-  int S, P, Tt, kind;
-};
-
-// LDS of the descriptor-tile kernel: two stage buffers and the small tables.
-template <typename O, int K, int TILE>
-struct FastSmem {
-  static constexpr size_t kBuf = (size_t)(TILE + 2) * sizeof(O) + (size_t)TILE * 4;
-  static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
-  alignas(16) unsigned char bufA[kBuf];
-  alignas(16) unsigned char bufB[kBuf];
-  SmallTab<K> tab[2];
-  alignas(16) uint32_t raw[kDescWords];
-};
-
-// LDS of the general kernel (tiles spanning many small nodes).
-template <typename O, int K, int TILE>
-struct GenSmem {
-  static constexpr int kMaxSlices = TILE + 2 * K + 2;
-  static constexpr int kMaxPieces = TILE / 2 + 4;
-  static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
-  static constexpr size_t kAux = kBuf > (size_t)kMaxSlices * 8 ? kBuf : (size_t)kMaxSlices * 8;
-  alignas(16) unsigned char bufA[kBuf];
-  alignas(16) unsigned char bufB[kAux];       // also holds slice global starts during setup
-  uint64_t pc_out[kMaxPieces];
-  uint16_t sl_off[kMaxSlices];
-  uint16_t pc_loff[kMaxPieces];
-  uint16_t pc_sl[kMaxPieces];
-  uint64_t scan[256];
-  int misc[8];
-};
-
-template <typename T>
-__device__ inline int ub16(const uint16_t *a, int n, T x) {
-  // first index in [0, n) with a[i] > x
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if ((T)a[mid] <= x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// Thread 0: build a small table from the raw descriptor words in LDS.
-template <int K>
-__device__ inline void build_small(SmallTab<K> &T, const TileDesc<K> &D, bool exists) {
-  if (!exists) { T.kind = kTabNone; return; }
-  uint32_t np = D.npieces;
-  T.Tt = (int)D.total;
-  if (np == kBadTile || np > 2) { T.kind = kTabBad; return; }
-  if (np == 0) { T.kind = kTabGeneral; return; }
-  int s = 0, off = 0;
-  for (int p = 0; p < (int)np; p++) {
-    T.pc_loff[p] = (uint16_t)off;
-    T.pc_sl[p] = (uint16_t)s;
-    T.pc_out[p] = D.out[p];
-    int d = (int)D.d[p];
-    if (d > K) d = K;
-    for (int j = 0; j < d; j++) {
-      T.sl_off[s] = (uint16_t)off;
-      T.sl_g[s] = D.src[p][j];
-      T.delta[s] = D.src[p][j] - (uint64_t)off;
-      off += (int)D.len[p][j];
-      s++;
-    }
-  }
-  T.pc_loff[np] = (uint16_t)off;
-  T.pc_sl[np] = (uint16_t)s;
-  T.sl_off[s] = (uint16_t)off;
-  T.S = s;
-  T.P = (int)np;
-  T.kind = off == T.Tt ? kTabFast : kTabBad;
-}
-
-// Global addresses of a thread's E positions (t + i*THREADS).  Positions past
-// the tile end are clamped to its last element (loaded, never used), so the
-// loads that follow form one straight-line block: the compiler then issues
-// all of them before the first wait instead of waiting between them.
-template <int E, int THREADS>
-__device__ inline void addr_search(uint64_t (&g)[E], const uint16_t *sl_off,
-                                   const uint64_t *sl_g, int S, int Tt, int t) {
-#pragma unroll
-  for (int i = 0; i < E; i++) {
-    int e = t + i * THREADS;
-    int ec = e < Tt ? e : Tt - 1;
-    int s = ub16(sl_off, S + 1, ec) - 1;
-    g[i] = sl_g[s] + (uint64_t)(ec - sl_off[s]);
-  }
-}
-
-// Same for a descriptor tile: the slice of position e is the number of slice
-// starts (after the first) at or below e; its global index is delta[s] + e.
-template <int E, int THREADS, int MAXS>
-__device__ inline void addr_desc(uint64_t (&g)[E], const uint16_t *sl_off, const uint64_t *delta,
-                                 int S, int Tt, int t) {
-  int so[MAXS];
-#pragma unroll
-  for (int j = 1; j < MAXS; j++) so[j] = j < S ? (int)sl_off[j] : 0x7FFFFFFF;
-#pragma unroll
-  for (int i = 0; i < E; i++) {
-    int e = t + i * THREADS;
-    int ec = e < Tt ? e : Tt - 1;
-    int s = 0;
-#pragma unroll
-    for (int j = 1; j < MAXS; j++) s += so[j] <= ec ? 1 : 0;
-    g[i] = delta[s] + (uint64_t)ec;
-  }
-}
-
-template <typename O, int E, bool HV>
-__device__ inline void issue_at(O (&kreg)[E], uint32_t (&vreg)[E], const O *in_keys,
-                                const uint32_t *in_vals, const uint64_t (&g)[E]) {
-#pragma unroll
-  for (int i = 0; i < E; i++) {
-    kreg[i] = in_keys[g[i]];
-    if (HV) vreg[i] = in_vals[g[i]];
-  }
-}
-
-template <typename Kt, typename O, int E, int THREADS>
-__device__ inline void commit_loads(const O (&kreg)[E], const uint32_t (&vreg)[E], O *kA,
-                                    uint32_t *vA, bool has_vals, int Tt, int t) {
-#pragma unroll
-  for (int i = 0; i < E; i++) {
-    int e = t + i * THREADS;
-    if (e < Tt) {
-      kA[e] = Kt::ord(kreg[i]);
-      if (has_vals) vA[e] = vreg[i];
-    }
-  }
-}
-
-// log2(K) stages of pairwise merge-path merges in LDS; returns which buffer
-// holds the result (0: A, 1: B).
-template <typename O, int K, int TILE, int THREADS>
-__device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, bool has_vals,
-                                   const uint16_t *sl_off, int S, const uint16_t *pc_sl, int P,
-                                   int Tt, int t) {
-  constexpr int E = TILE / THREADS;
-  constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
-  O *ks = kA, *kd = kB;
-  uint32_t *vs = vA, *vd = vB;
-  for (int st = 1; st <= LOGK; st++) {
-    int e = t * E;
-    const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
-    while (e < e_end) {
-      int s = ub16(sl_off, S + 1, e) - 1;
-      int p = P == 1 ? 0 : ub16(pc_sl, P + 1, s) - 1;
-      int s0 = pc_sl[p];
-      int pd = pc_sl[p + 1] - s0;
-      int jj = s - s0;
-      int h = 1 << (st - 1);
-      int g0 = (jj >> st) << st;
-      int iM = g0 + h < pd ? g0 + h : pd;
-      int iR = g0 + 2 * h < pd ? g0 + 2 * h : pd;
-      int u0 = sl_off[s0 + g0], u1 = sl_off[s0 + iM], u2 = sl_off[s0 + iR];
-      int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
-      int lo = diag - nR > 0 ? diag - nR : 0;
-      int hi = diag < nL ? diag : nL;
-      while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (ks[u0 + mid] <= ks[u1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
-      }
-      int ia = u0 + lo, ib = u1 + diag - lo;
-      int stop = e_end < u2 ? e_end : u2;
-      if (stop <= e) break;  // cannot happen with valid tables (e < u2)
-      // heads kept in registers; one LDS key load per output
-      O ka = ks[ia < TILE ? ia : TILE - 1];
-      O kb = ks[ib < TILE ? ib : TILE - 1];
-      for (; e < stop; e++) {
-        bool takeL = ib >= u2 || (ia < u1 && ka <= kb);
-        int src = takeL ? ia : ib;
-        kd[e] = takeL ? ka : kb;
-        if (has_vals) vd[e] = vs[src];
-        ia += takeL ? 1 : 0;
-        ib += takeL ? 0 : 1;
-        int nx = takeL ? ia : ib;
-        O kn = ks[nx < TILE ? nx : TILE - 1];
-        if (takeL) ka = kn; else kb = kn;
-      }
-    }
-    lds_barrier();
-    O *tk = ks; ks = kd; kd = tk;
-    uint32_t *tv = vs; vs = vd; vd = tv;
-  }
-  return (LOGK & 1) ? 1 : 0;
-}
-
-// The same stages for a descriptor tile (at most two pieces, MAXS slices).
-// Slice offsets are uniform and held in registers; the lane's merge unit is
-// found with compares instead of searches; the merge-path search is a
-// lower_bound; the sequential merge walks LDS byte offsets (the key buffers
-// carry one element of padding, so reading one past a unit is harmless).
-template <typename O, int K, int TILE, int THREADS, bool HV>
-__device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB,
-                                        const uint16_t *sl_off_l, int S, const uint16_t *pc_sl_l,
-                                        int P, int Tt, int t) {
-  constexpr int E = TILE / THREADS;
-  constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
-  constexpr int MAXS = 2 * K;
-  constexpr int KS = (int)sizeof(O);
-  int so[MAXS + 1];
-#pragma unroll
-  for (int j = 0; j <= MAXS; j++) so[j] = j <= S ? (int)sl_off_l[j] : Tt;
-  const int s1 = P == 2 ? (int)pc_sl_l[1] : S;   // first slice of the second piece
-  O *ks = kA, *kd = kB;
-  uint32_t *vs = vA, *vd = vB;
-#pragma unroll
-  for (int st = 1; st <= LOGK; st++) {
-    int e = t * E;
-    const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
-    while (e < e_end) {
-      int s = 0;
-#pragma unroll
-      for (int j = 1; j < MAXS; j++) s += (j < S && so[j] <= e) ? 1 : 0;
-      const int s0 = s >= s1 ? s1 : 0;
-      const int pend = s >= s1 ? S : s1;
-      const int h = 1 << (st - 1);
-      const int g0 = s0 + (((s - s0) >> st) << st);
-      const int iM = g0 + h < pend ? g0 + h : pend;
-      const int iR = g0 + 2 * h < pend ? g0 + 2 * h : pend;
-      int u0 = so[0], u1 = so[0], u2 = so[0];
-#pragma unroll
-      for (int j = 1; j <= MAXS; j++) {
-        u0 = j == g0 ? so[j] : u0;
-        u1 = j == iM ? so[j] : u1;
-        u2 = j == iR ? so[j] : u2;
-      }
-      const int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
-      int lo = diag - nR > 0 ? diag - nR : 0;
-      int cnt = (diag < nL ? diag : nL) - lo;
-      // smallest i in [lo, lo+cnt] with ks[u0+i] > ks[u1+diag-1-i]
-      while (cnt > 0) {
-        const int half = cnt >> 1;
-        const int mid = lo + half;
-        const bool p = ks[u0 + mid] <= ks[u1 + diag - 1 - mid];
-        lo = p ? mid + 1 : lo;
-        cnt = p ? cnt - half - 1 : half;
-      }
-      const int stop = e_end < u2 ? e_end : u2;
-      if (stop <= e) break;  // cannot happen with valid tables (e < u2)
-      // byte offsets into the key buffer; payload offsets are key offsets * 4 / KS
-      const char *kb8 = reinterpret_cast<const char *>(ks);
-      uint32_t pa = (uint32_t)(u0 + lo) * KS, pb = (uint32_t)(u1 + diag - lo) * KS;
-      const uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
-      O ka = *reinterpret_cast<const O *>(kb8 + pa);
-      O kb = *reinterpret_cast<const O *>(kb8 + pb);
-      for (; e < stop; e++) {
-        const bool takeL = pa < ea && (pb >= eb || ka <= kb);
-        const uint32_t src = takeL ? pa : pb;
-        kd[e] = takeL ? ka : kb;
-        if (HV) vd[e] = vs[src / KS];
-        pa += takeL ? KS : 0;
-        pb += takeL ? 0 : KS;
-        const O kn = *reinterpret_cast<const O *>(kb8 + (takeL ? pa : pb));
-        ka = takeL ? kn : ka;
-        kb = takeL ? kb : kn;
-      }
-    }
-    lds_barrier();
-    O *tk = ks; ks = kd; kd = tk;
-    uint32_t *tv = vs; vs = vd; vd = tv;
-  }
-  return (LOGK & 1) ? 1 : 0;
-}
-
-template <typename Kt, typename O, int E, int THREADS>
-__device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
-                                  uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
-                                  const uint64_t *pc_out, int P, int Tt, int t) {
-#pragma unroll
-  for (int i = 0; i < E; i++) {
-    int e = t + i * THREADS;
-    if (e < Tt) {
-      int p = P == 1 ? 0 : ub16(pc_loff, P + 1, e) - 1;
-      uint64_t g = pc_out[p] + (uint64_t)(e - pc_loff[p]);
-      out_keys[g] = Kt::unord(ks[e]);
-      if (has_vals) out_vals[g] = vs[e];
-    }
-  }
-}
-
-// Descriptor tiles.  Each workgroup walks tiles blockIdx.x, +gridDim.x, ...
-// (skipping those of the general path) software-pipelined: while tile i is
-// merged in LDS, the descriptor of tile i+2 and the input slices of tile i+1
-// are already being fetched into registers, so global latency overlaps the
-// LDS work.
-template <int KT, int K, int TILE, int THREADS, bool HV>
-__global__ __launch_bounds__(THREADS) void k_merge_fast(
-    const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
-    typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
-    Plan *__restrict__ plan, int level, const TileDesc<K> *__restrict__ desc) {
-  using Kt = Key<KT>;
-  using O = typename Kt::U;
-  using SM = FastSmem<O, K, TILE>;
-  constexpr int E = TILE / THREADS;
-  constexpr int NW = SM::kDescWords;
-  constexpr int DW = (int)(sizeof(TileDesc<K>) / 4);
-  constexpr int MAXS = 2 * K;
-  __shared__ SM sm;
-  O *kA = reinterpret_cast<O *>(sm.bufA);
-  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)(TILE + 2) * sizeof(O));
-  O *kB = reinterpret_cast<O *>(sm.bufB);
-  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)(TILE + 2) * sizeof(O));
-  const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
-
-  const uint64_t tiles = plan->lvl_tiles[level];
-  const int t = threadIdx.x;
-  const uint64_t G = gridDim.x;
-  uint64_t tile = blockIdx.x;
-  if (tile >= tiles) return;
-
-  O kreg[E];
-  uint32_t vreg[E];
-  uint64_t ga[E];
-  uint32_t dreg = 0;   // one word of a prefetched descriptor (lanes 0..NW-1)
-
-  // prologue: tables of the first tile, descriptor of the second, loads of the first
-  if (t < NW) sm.raw[t] = descw[tile * DW + t];
-  lds_barrier();
-  if (t == 0) build_small<K>(sm.tab[0], *reinterpret_cast<const TileDesc<K> *>(sm.raw), true);
-  lds_barrier();
-  if (t < NW && tile + G < tiles) dreg = descw[(tile + G) * DW + t];
-  if (sm.tab[0].kind == kTabFast) {
-    addr_desc<E, THREADS, MAXS>(ga, sm.tab[0].sl_off, sm.tab[0].delta, sm.tab[0].S,
-                                sm.tab[0].Tt, t);
-    issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
-  }
-  int cur = 0;
-
-  while (tile < tiles) {
-    const uint64_t nxt = tile + G;
-    SmallTab<K> &T = sm.tab[cur];
-    SmallTab<K> &N = sm.tab[cur ^ 1];
-    const int kind = T.kind;
-    if (kind == kTabFast) commit_loads<Kt, O, E, THREADS>(kreg, vreg, kA, vA, HV, T.Tt, t);
-    // next tile's tables from its prefetched descriptor; then fetch ahead
-    if (t < NW) sm.raw[t] = dreg;
-    lds_barrier();
-    if (t == 0) build_small<K>(N, *reinterpret_cast<const TileDesc<K> *>(sm.raw), nxt < tiles);
-    lds_barrier();
-    if (t < NW && nxt + G < tiles) dreg = descw[(nxt + G) * DW + t];
-    if (N.kind == kTabFast) {
-      addr_desc<E, THREADS, MAXS>(ga, N.sl_off, N.delta, N.S, N.Tt, t);
-      issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
-    }
-    if (kind == kTabFast) {
-      int res = merge_stages_fast<O, K, TILE, THREADS, HV>(kA, vA, kB, vB, T.sl_off, T.S,
-                                                           T.pc_sl, T.P, T.Tt, t);
-      store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
-                                    T.pc_loff, T.pc_out, T.P, T.Tt, t);
-    } else if (kind == kTabBad) {
-      if (t == 0) atomicOr(&plan->error, 32u);
-    }
-    lds_barrier();
-    cur ^= 1;
-    tile = nxt;
-  }
-}
-
-// Tiles spanning many small nodes (listed by the descriptor kernel): piece
-// and slice tables are built from the node records, then the same staged
-// merge runs.  Not pipelined.
-template <int KT, int K, int TILE, int THREADS, bool HV>
-__global__ __launch_bounds__(THREADS) void k_merge_general(
-    const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
-    typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
-    const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
-    const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
-    const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
-    const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
-    const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level,
-    const uint32_t *__restrict__ cr, const uint32_t *__restrict__ gen_list) {
-  using Kt = Key<KT>;
-  using O = typename Kt::U;
-  using SM = GenSmem<O, K, TILE>;
-  constexpr int E = TILE / THREADS;
-  __shared__ SM sm;
-  O *kA = reinterpret_cast<O *>(sm.bufA);
-  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
-  O *kB = reinterpret_cast<O *>(sm.bufB);
-  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
-  uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufB);
-
-  const uint32_t ngen = plan->gen_cnt[level];
-  if (ngen == 0) return;
-  const uint64_t rr_total = plan->r;
-  const uint64_t lb = plan->lvl_begin[level], le = plan->lvl_begin[level + 1];
-  const uint64_t nlev = le - lb;
-  const uint64_t np0 = np[lb];
-  const uint64_t L = np[le] - np0;
-  const uint32_t *tjl = tj + tile_base[level];
-  const int t = threadIdx.x;
-  uint64_t ga[E];
-
-  for (uint32_t gi = blockIdx.x; gi < ngen; gi += gridDim.x) {
-    const uint64_t tile = gen_list[gi];
-    TileGeom g = tile_geom(tile, TILE, L, nlev, np, lb, np0, tjl);
-    const int Tt = (int)(g.Q1 - g.Q0);
-    const int P = (int)(g.j1 - g.j0 + 1);
-    bool bad = !g.ok || P + 1 > SM::kMaxPieces;
-    if (t == 0) sm.misc[4] = bad ? 1 : 0;
-    __syncthreads();
-    if (!bad) {
-      const uint64_t Q0 = g.Q0, Q1 = g.Q1, j0 = g.j0;
-      uint64_t carry_len = 0, carry_sl = 0;
-      for (int pbase = 0; pbase < P; pbase += THREADS) {
-        int p = pbase + t;
-        NodeIn nd;
-        uint32_t c0[K], c1[K];
-        uint64_t plen = 0;
-        int pd = 0;
-        if (p < P) {
-          uint64_t j = j0 + p;
-          if (!load_node<K>(list[lb + j], rr_total, rs, Ls, Rs, mem, arity, nd)) {
-            sm.misc[4] = 1;
-            nd.d = 2;
-            nd.c[0] = nd.c[1] = nd.c[2] = 0;
-          }
-          pd = nd.d;
-          bool first = p == 0, last = p == P - 1;
-          bool cut_end = last && Q1 < np[lb + j + 1] - np0;
-          for (int jj = 0; jj < K; jj++) {
-            if (jj >= pd) { c0[jj] = c1[jj] = 0; continue; }
-            uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
-            c0[jj] = first ? cr[tile * K + jj] : 0;
-            c1[jj] = cut_end ? cr[(tile + 1) * K + jj] : len;
-            if (c1[jj] > len || c0[jj] > c1[jj]) {  // inconsistent cut: never index with it
-              sm.misc[4] = 1;
-              c0[jj] = c1[jj] = 0;
-            }
-            plen += c1[jj] - c0[jj];
-          }
-        }
-        uint64_t packed = ((uint64_t)pd << 32) | plen;
-        sm.scan[t] = packed;
-        __syncthreads();
-        for (int o = 1; o < THREADS; o <<= 1) {
-          uint64_t y = t >= o ? sm.scan[t - o] : 0;
-          __syncthreads();
-          sm.scan[t] += y;
-          __syncthreads();
-        }
-        uint64_t ex = sm.scan[t] - packed;
-        uint64_t tot = sm.scan[THREADS - 1];
-        __syncthreads();
-        if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
-            carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
-          uint64_t loff = carry_len + (ex & 0xFFFFFFFFull);
-          uint64_t sl0 = carry_sl + (ex >> 32);
-          sm.pc_loff[p] = (uint16_t)loff;
-          sm.pc_sl[p] = (uint16_t)sl0;
-          sm.pc_out[p] = nd.c[0] + (p == 0 ? Q0 - (np[lb + j0] - np0) : 0);
-          uint64_t acc = loff;
-          for (int jj = 0; jj < pd; jj++) {
-            sm.sl_off[sl0 + jj] = (uint16_t)acc;
-            sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
-            acc += c1[jj] - c0[jj];
-          }
-        }
-        carry_len += tot & 0xFFFFFFFFull;
-        carry_sl += tot >> 32;
-      }
-      const int S = (int)carry_sl;
-      if (carry_len != (uint64_t)Tt || S + 1 > SM::kMaxSlices) sm.misc[4] = 1;
-      __syncthreads();
-      if (t == 0 && !sm.misc[4]) {
-        sm.pc_loff[P] = (uint16_t)Tt;
-        sm.pc_sl[P] = (uint16_t)S;
-        sm.sl_off[S] = (uint16_t)Tt;
-      }
-      __syncthreads();
-      if (!sm.misc[4]) {
-        O k2[E];
-        uint32_t v2[E];
-        addr_search<E, THREADS>(ga, sm.sl_off, sl_g, S, Tt, t);
-        issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
-        commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, HV, Tt, t);
-        __syncthreads();
-        int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, HV, sm.sl_off, S, sm.pc_sl,
-                                                    P, Tt, t);
-        store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
-                                      sm.pc_loff, sm.pc_out, P, Tt, t);
-      }
-    }
-    if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------- host side
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s) {
   uint64_t nblk = (w.N + kPlaceBlock - 1) / kPlaceBlock;
@@ -826,91 +88,63 @@ hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipSt
   return hipGetLastError();
 }
 
-constexpr int kMergeThreads = 256;
-constexpr int kTile = kTileSize;
-
-// Workgroups that fill the device exactly once (CUs x resident blocks per
-// CU) for a grid-stride kernel; computed once per kernel.
-template <typename F>
-static unsigned fill_grid(F kernel, int threads, unsigned fallback) {
-  static unsigned cached = 0;
-  if (cached) return cached;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-      cus <= 0 || per_cu <= 0)
-    return fallback;
-  cached = (unsigned)(cus * per_cu);
-  return cached;
-}
-
+// Co-rank and descriptor launches of one level (tile size is a run-time value).
 template <int KT, int K>
-static void launch_level_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
-                           const uint64_t *tile_base, int level, hipStream_t s, hipEvent_t e0,
-                           hipEvent_t e1, hipEvent_t e2) {
+static void launch_cuts_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
+                          const uint64_t *tile_base, int level, hipStream_t s) {
   using U = typename Key<KT>::U;
-  unsigned gc = 512, gm = 1024, gg = 2048;
-  if (e0) (void)hipEventRecord(e0, s);
+  const unsigned gc = 512;
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
-                     tile_base, w.plan, level, kTile, w.corank);
+                     tile_base, w.plan, level, w.tile, w.corank);
   TileDesc<K> *desc = reinterpret_cast<TileDesc<K> *>(w.tile_desc);
   hipLaunchKernelGGL((k_tile_desc<K>), dim3(gc), dim3(256), 0, s, w.run_start, w.Ls, w.Rs,
                      w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level,
-                     kTile, w.corank, desc, w.gen_list);
-  if (e1) (void)hipEventRecord(e1, s);
-  if (a.in_vals) {
-    gm = fill_grid(k_merge_fast<KT, K, kTile, kMergeThreads, true>, kMergeThreads, gm);
-    hipLaunchKernelGGL((k_merge_fast<KT, K, kTile, kMergeThreads, true>), dim3(gm),
-                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.plan, level, desc);
-    hipLaunchKernelGGL((k_merge_general<KT, K, kTile, kMergeThreads, true>), dim3(gg),
-                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
-                       w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
-                       w.gen_list);
-  } else {
-    gm = fill_grid(k_merge_fast<KT, K, kTile, kMergeThreads, false>, kMergeThreads, gm);
-    hipLaunchKernelGGL((k_merge_fast<KT, K, kTile, kMergeThreads, false>), dim3(gm),
-                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.plan, level, desc);
-    hipLaunchKernelGGL((k_merge_general<KT, K, kTile, kMergeThreads, false>), dim3(gg),
-                       dim3(kMergeThreads), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
-                       w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
-                       w.gen_list);
-  }
-  if (e2) (void)hipEventRecord(e2, s);
+                     w.tile, w.corank, desc, w.gen_list);
 }
 
-static hipError_t dispatch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
-                                 const uint64_t *tile_base, int level, hipStream_t s,
-                                 hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+static hipError_t launch_cuts(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                              const uint64_t *tile_base, int level, hipStream_t s) {
   switch (w.k * 4 + kt) {
-    case 2 * 4 + 0: launch_level_t<0, 2>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 2 * 4 + 1: launch_level_t<1, 2>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 2 * 4 + 2: launch_level_t<2, 2>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 4 * 4 + 0: launch_level_t<0, 4>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 4 * 4 + 1: launch_level_t<1, 4>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 4 * 4 + 2: launch_level_t<2, 4>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 8 * 4 + 0: launch_level_t<0, 8>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 8 * 4 + 1: launch_level_t<1, 8>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
-    case 8 * 4 + 2: launch_level_t<2, 8>(a, w, tj, tile_base, level, s, e0, e1, e2); break;
+    case 2 * 4 + 0: launch_cuts_t<0, 2>(a, w, tj, tile_base, level, s); break;
+    case 2 * 4 + 1: launch_cuts_t<1, 2>(a, w, tj, tile_base, level, s); break;
+    case 2 * 4 + 2: launch_cuts_t<2, 2>(a, w, tj, tile_base, level, s); break;
+    case 4 * 4 + 0: launch_cuts_t<0, 4>(a, w, tj, tile_base, level, s); break;
+    case 4 * 4 + 1: launch_cuts_t<1, 4>(a, w, tj, tile_base, level, s); break;
+    case 4 * 4 + 2: launch_cuts_t<2, 4>(a, w, tj, tile_base, level, s); break;
+    case 8 * 4 + 0: launch_cuts_t<0, 8>(a, w, tj, tile_base, level, s); break;
+    case 8 * 4 + 1: launch_cuts_t<1, 8>(a, w, tj, tile_base, level, s); break;
+    case 8 * 4 + 2: launch_cuts_t<2, 8>(a, w, tj, tile_base, level, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+static hipError_t launch_merges(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                                const uint64_t *tile_base, int level, hipStream_t s) {
+  if (w.tile == 1024 && w.threads == 256) return launch_merges_1024x256(kt, a, w, tj, tile_base, level, s);
+  if (w.tile == 2048 && w.threads == 256) return launch_merges_2048x256(kt, a, w, tj, tile_base, level, s);
+  if (w.tile == 2048 && w.threads == 512) return launch_merges_2048x512(kt, a, w, tj, tile_base, level, s);
+  if (w.tile == 4096 && w.threads == 512) return launch_merges_4096x512(kt, a, w, tj, tile_base, level, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_level_timed(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                               const uint64_t *tile_base, int level, hipStream_t s,
                               hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
-  return dispatch_level(kt, a, w, tj, tile_base, level, s, e0, e1, e2);
+  if (e0) (void)hipEventRecord(e0, s);
+  hipError_t e = launch_cuts(kt, a, w, tj, tile_base, level, s);
+  if (e != hipSuccess) return e;
+  if (e1) (void)hipEventRecord(e1, s);
+  e = launch_merges(kt, a, w, tj, tile_base, level, s);
+  if (e != hipSuccess) return e;
+  if (e2) (void)hipEventRecord(e2, s);
+  return hipSuccess;
 }
 
 hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                         const uint64_t *tile_base, int level, hipStream_t s) {
-  return dispatch_level(kt, a, w, tj, tile_base, level, s, nullptr, nullptr, nullptr);
+  return launch_level_timed(kt, a, w, tj, tile_base, level, s, nullptr, nullptr, nullptr);
 }
 
 }  // namespace mps

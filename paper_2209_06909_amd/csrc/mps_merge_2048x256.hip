@@ -1,0 +1,11 @@
+// mps_merge_2048x256.hip -- level merges with 2048-output tiles and 256-thread workgroups.
+#include "mps_merge.h"
+
+namespace mps {
+
+hipError_t launch_merges_2048x256(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
+                                  const uint64_t *tile_base, int level, hipStream_t s) {
+  return launch_merges_cfg<2048, 256>(kt, a, w, tj, tile_base, level, s);
+}
+
+}  // namespace mps

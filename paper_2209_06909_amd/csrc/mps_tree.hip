@@ -575,8 +575,8 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   hipLaunchKernelGGL(k_scan_sums, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
   hipLaunchKernelGGL(k_scan_apply, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
-  hipLaunchKernelGGL(k_lvl_tiles, dim3(1), dim3(64), 0, s, w.plan, w.lvl_np, kTileSize, tile_base);
-  hipLaunchKernelGGL(k_tile_map, dim3(2048), b256, 0, s, w.lvl_np, w.plan, kTileSize, tile_base, tj);
+  hipLaunchKernelGGL(k_lvl_tiles, dim3(1), dim3(64), 0, s, w.plan, w.lvl_np, w.tile, tile_base);
+  hipLaunchKernelGGL(k_tile_map, dim3(2048), b256, 0, s, w.lvl_np, w.plan, w.tile, tile_base, tj);
   return hipGetLastError();
 }
 

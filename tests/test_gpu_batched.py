@@ -1,0 +1,162 @@
+"""GPU parity of the batching layer: merge tile configurations, the work-queue
+merge kernels, HIP-graph replay and batched sorts of many uneven arrays, all
+against the CPU oracle (bit-exact keys, payload permutation, runs, powers and
+merge cost) or against the eager single-array path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+import paper_2209_06909_amd as mps  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def pay_dev(p):
+    return torch.from_numpy(np.ascontiguousarray(p).view(np.int32)).to(DEV)
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint8)
+
+
+def batch_truth(keys, pay, off, k):
+    """Oracle outputs and the per-array runs / powers concatenated as the batched trace
+    reports them (array edges carry power 0)."""
+    ok, op, omc = oracle.sort_many(keys, pay, off, k=k)
+    rs_all, pw_all = [], []
+    for i in range(len(off) - 1):
+        s, e = int(off[i]), int(off[i + 1])
+        if e == s:
+            continue
+        rs, _ = oracle.runs(keys[s:e])
+        if rs_all:
+            pw_all.append(np.zeros(1, np.uint8))
+        pw_all.append(oracle.powers(rs, k))
+        rs_all.append(rs[:-1] + s)
+    rs_all.append(np.array([off[-1]], np.uint64))
+    return ok, op, int(omc.sum()), np.concatenate(rs_all), np.concatenate(pw_all)
+
+
+@pytest.mark.parametrize("tile,lane_slice", mps.TILE_CONFIGS)
+@pytest.mark.parametrize("k", [4, 2, 8])
+def test_tile_configs_vs_oracle(tile, lane_slice, k):
+    """Every merge tile configuration on a run-structured int64 input (many tiles,
+    ragged tail) and on a ties-heavy int32 input (stability)."""
+    for name, n, seed in (("runs_i64", (1 << 17) + 4321, 31), ("ties_i32", (1 << 17) + 99, 32)):
+        say(f"[gpu] tile {tile}/{lane_slice} k={k} {name} n={n}")
+        keys, pay = workloads.WORKLOADS[name](n=n, seed=seed)
+        ok, op, ot = oracle.sort(keys, pay, k=k)
+        kd, pd = to_dev(keys), pay_dev(pay)
+        tr = mps.sort(kd, pd, k=k, trace=True, tile=tile, lane_slice=lane_slice)
+        assert np.array_equal(bits(kd.cpu().numpy()), bits(ok))
+        assert np.array_equal(pd.cpu().numpy().view(np.uint32), op)
+        assert np.array_equal(tr.run_start, ot.run_start)
+        assert np.array_equal(tr.power, ot.power)
+        assert tr.merge_cost == ot.merge_cost
+
+
+def test_bad_tile_config_rejected():
+    kd = to_dev(np.arange(100, dtype=np.int32)[::-1].copy())
+    with pytest.raises(mps.MpsError):
+        mps.sort(kd, tile=1024, lane_slice=8)
+    with pytest.raises(mps.MpsError):
+        mps.sort(kd, tile=3000)
+
+
+def uneven_batch(m, seed, lo, hi):
+    keys, pay, off = workloads.batch_i32(m=m, seed=seed, lo_exp=lo, hi_exp=hi)
+    return keys, pay, off
+
+
+@pytest.mark.parametrize("tile,lane_slice", [(2048, 8), (1024, 4), (4096, 8)])
+def test_batched_uneven_vs_oracle(tile, lane_slice):
+    """Many arrays with log-uniform sizes (the batched workload's shape, scaled
+    down), a few of them empty, through one batched call."""
+    say(f"[gpu] batched uneven tile {tile}/{lane_slice}")
+    keys, pay, off = uneven_batch(400, 41, 4.0, 16.0)
+    sizes = np.diff(off.astype(np.int64))
+    sizes[[3, 4, 200]] = 0
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys, pay = keys[: int(off[-1])], pay[: int(off[-1])]
+    ok, op, M, rs, pw = batch_truth(keys, pay, off, 4)
+    kd, pd = to_dev(keys), pay_dev(pay)
+    od = torch.from_numpy(off.view(np.int64)).to(DEV)
+    tr = mps.sort_batched(kd, pd, od, k=4, trace=True, host_offsets=off, tile=tile,
+                          lane_slice=lane_slice)
+    assert np.array_equal(kd.cpu().numpy(), ok)
+    assert np.array_equal(pd.cpu().numpy().view(np.uint32), op)
+    assert tr.merge_cost == M
+    assert np.array_equal(tr.run_start, rs)
+    assert np.array_equal(tr.power, pw)
+
+
+def test_graph_replay_matches_eager():
+    """A graph-captured batched sort replayed on fresh copies of the input, with
+    eager work and synchronisations between the replays: every replay equals the
+    eager result, and so does a replay after the offsets' contents change."""
+    say("[gpu] graph replay")
+    keys, pay, off = uneven_batch(300, 43, 6.0, 15.0)
+    kd0, pd0 = to_dev(keys), pay_dev(pay)
+    od = torch.from_numpy(off.view(np.int64)).to(DEV)
+    ek, ep = kd0.clone(), pd0.clone()
+    mps.sort_batched(ek, ep, od, k=4)
+    torch.cuda.synchronize()
+    ek, ep = ek.cpu().numpy(), ep.cpu().numpy()
+    kd, pd = torch.empty_like(kd0), torch.empty_like(pd0)
+    for rep in range(4):
+        kd.copy_(kd0)
+        pd.copy_(pd0)
+        mps.sort_batched(kd, pd, od, k=4, graph=True)
+        junk = torch.randn(1 << 16, device=DEV).sum()       # eager work between replays
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert np.array_equal(kd.cpu().numpy(), ek), f"replay {rep}"
+        assert np.array_equal(pd.cpu().numpy(), ep), f"replay {rep}"
+    # same pointers and sizes, different array boundaries: the graph reads them on the device
+    sizes = np.diff(off.astype(np.int64))
+    perm = np.random.default_rng(5).permutation(sizes.size)
+    off2 = np.concatenate([[0], np.cumsum(sizes[perm])]).astype(np.uint64)
+    od.copy_(torch.from_numpy(off2.view(np.int64)))
+    ok2, op2, _ = oracle.sort_many(keys, pay, off2, k=4)
+    kd.copy_(kd0)
+    pd.copy_(pd0)
+    mps.sort_batched(kd, pd, od, k=4, graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(kd.cpu().numpy(), ok2)
+    assert np.array_equal(pd.cpu().numpy().view(np.uint32), op2)
+
+
+def test_graph_single_array_and_trace():
+    say("[gpu] graph single")
+    keys, pay = workloads.runs_i32(n=(1 << 16) + 5, seed=8)
+    ok, op, ot = oracle.sort(keys, pay, k=4)
+    for rep in range(3):
+        kd, pd = to_dev(keys), pay_dev(pay)
+        tr = mps.sort(kd, pd, k=4, graph=True, trace=(rep == 2))
+        torch.cuda.synchronize()
+        assert np.array_equal(kd.cpu().numpy(), ok)
+        assert np.array_equal(pd.cpu().numpy().view(np.uint32), op)
+        if tr is not None:
+            assert np.array_equal(tr.run_start, ot.run_start)
+            assert tr.merge_cost == ot.merge_cost
+
+
+def test_graph_rejects_level_timing():
+    kd = to_dev(np.arange(1000, dtype=np.int32))
+    with pytest.raises(mps.MpsError):
+        mps.sort(kd, graph=True, time_levels=True)
