@@ -75,6 +75,210 @@ def cpu_baseline(keys: np.ndarray, pay: np.ndarray, sample_n: int, k: int):
                       f"single-threaded C oracle, {dt:.2f} s"}
 
 
+def _time_reps(torch, reps, restore, run):
+    """Median and all times (ms) of `run` over reps, each after `restore` (untimed)."""
+    ts = []
+    for _ in range(reps):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), ts
+
+
+def bench_batched(args, torch, mps, workloads):
+    """Batched workload: m int32 arrays with log-uniform sizes in [2^8, 2^22] and random
+    runs, index payload.  One batched call (autotuned configuration, graph replay)
+    against one mps_sort call per array through the C ABI on the same stream."""
+    import ctypes
+    dev = torch.device("cuda:0")
+    m = args.batched_m
+    log(f"batched: generating m={m} arrays on the GPU")
+    keys0, pay0, off_h = workloads.batch_i32_device(m=m, device="cuda:0")
+    total = int(off_h[-1])
+    off_d = torch.from_numpy(off_h.view(np.int64)).to(dev)
+    keys, pay = torch.empty_like(keys0), torch.empty_like(pay0)
+
+    def restore():
+        keys.copy_(keys0)
+        pay.copy_(pay0)
+
+    log(f"batched: total {total} keys; autotuning")
+    t0 = time.perf_counter()
+    tuned = mps.autotune(keys0, pay0, off_h, sample_keys=1 << 25, graph=True, with_times=True)
+    tune_s = time.perf_counter() - t0
+    cfg = dict(k=tuned["k"], tile=tuned["tile"], lane_slice=tuned["lane_slice"])
+    log(f"batched: tuned {cfg} in {tune_s:.1f} s")
+    reps = args.batched_reps
+
+    def batched(**c):
+        return lambda: mps.sort_batched(keys, pay, off_d, graph=True, **c)
+
+    restore()
+    mps.sort_batched(keys, pay, off_d, graph=True, **cfg)          # warm-up + capture
+    t_tuned, all_tuned = _time_reps(torch, reps, restore, batched(**cfg))
+    restore()
+    mps.sort_batched(keys, pay, off_d, graph=True, k=4)
+    t_def, _ = _time_reps(torch, reps, restore, batched(k=4))
+    # merge cost and placement of the batch (for the HBM fraction)
+    restore()
+    tr = mps.sort_batched(keys, pay, off_d, trace=True, **cfg)
+    rs = tr.run_start.astype(np.int64)
+    moved = (tr.leaf_depth & 1).astype(bool) | tr.run_desc.astype(bool)
+    placed = int(np.diff(rs)[moved].sum())
+    KV = 4 + 4
+    sort_bytes = total * 4 + 2 * KV * placed + 2 * KV * tr.merge_cost
+
+    # one launch sequence per array through the C ABI (library-managed workspace)
+    lib = mps.lib()
+    kp, pp = keys.data_ptr(), pay.data_ptr()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    offs = off_h.astype(np.int64).tolist()
+
+    def per_array():
+        for i in range(m):
+            a, b = offs[i], offs[i + 1]
+            rc = lib.mps_sort(ctypes.c_void_p(kp + 4 * a), mps.KEY_I32, ctypes.c_void_p(pp + 4 * a),
+                              b - a, stream)
+            if rc < 0:
+                raise RuntimeError(lib.mps_last_error().decode())
+    log("batched: per-array loop")
+    restore()
+    per_array()                                                       # warm-up
+    t_loop, _ = _time_reps(torch, max(1, reps - 1), restore, per_array)
+    gk = lambda ms: round(total / (ms * 1e-3) / 1e9, 4)
+    return {
+        "workload": f"batch_i32: m={m} int32 arrays, sizes floor(2^U) U~U[8,22], random runs "
+                    f"U{{1..2*sqrt(size)}} ascending, index payload (sizes/runs seed 5, keys drawn "
+                    f"on the GPU)",
+        "total_keys": total, "bytes": total * KV,
+        "batched_value": gk(t_tuned), "batched_ms": round(t_tuned, 3),
+        "batched_ms_all": [round(x, 3) for x in all_tuned],
+        "batched_default_value": gk(t_def), "batched_default_ms": round(t_def, 3),
+        "per_array_value": gk(t_loop), "per_array_ms": round(t_loop, 3),
+        "speedup_vs_per_array": round(t_loop / t_tuned, 3),
+        "unit": "GKeys/s",
+        "tuned": cfg, "tune_seconds": round(tune_s, 2), "tune_sample_keys": 1 << 25,
+        "tune_candidates": tuned["candidates"],
+        "merge_cost": int(tr.merge_cost), "runs": int(tr.r),
+        "sort_hbm": {"algorithmic_bytes": int(sort_bytes),
+                     "achieved_GBs": round(sort_bytes / (t_tuned * 1e-3) / 1e9, 1),
+                     "frac": round(sort_bytes / (t_tuned * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "per_array_launch": "one mps_sort call per array via the C ABI, same stream, default "
+                            "configuration, library-managed workspace",
+    }
+
+
+def bench_serving(args, torch, mps, workloads):
+    """Serving: a pool of float32 requests (sizes log-uniform in [2^10, 2^26], random runs,
+    ~1% duplicate keys, index payload) resident on the GPU.  (1) Closed loop: every pool
+    entry submitted at once -> the server's capacity, against one mps_sort per request on
+    one stream.  (2) Open loop: Poisson arrivals at 0.7 x capacity for --serve-seconds,
+    each request drawing a pool entry that the server copies into its admitted slot; the
+    latency of a request runs from submit to the scheduler seeing its batch complete."""
+    import ctypes
+    dev = torch.device("cuda:0")
+    log(f"serving: generating a pool of {args.serve_pool} requests on the GPU")
+    pool = workloads.serve_pool_device(count=args.serve_pool, device="cuda:0")
+    sizes = np.array([x.numel() for x, _ in pool], np.int64)
+    mean_size = float(sizes.mean())
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = mps.Server(hbm_budget_bytes=budget, n_streams=args.serve_streams,
+                     max_batch=args.serve_max_batch)
+    try:
+        # closed loop (also warms up the server and the allocator)
+        outs = [(torch.empty_like(x), torch.empty_like(p)) for x, p in pool]
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids = [srv.submit(x, p, ko, po) for (x, p), (ko, po) in zip(pool, outs)]
+            infos = [srv.wait(i, timeout=120) for i in ids]
+            closed_s = time.perf_counter() - t0
+            for i in ids:
+                srv.release(i)
+        capacity = float(sizes.sum()) / closed_s
+        # one mps_sort per request (copy into the output, sort it there), same stream
+        lib = mps.lib()
+        stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+        def per_request():
+            for (x, p), (ko, po) in zip(pool, outs):
+                ko.copy_(x)
+                po.copy_(p)
+                rc = lib.mps_sort(ctypes.c_void_p(ko.data_ptr()), mps.KEY_F32,
+                                  ctypes.c_void_p(po.data_ptr()), ko.numel(), stream)
+                if rc < 0:
+                    raise RuntimeError(lib.mps_last_error().decode())
+        per_request()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per_request()
+        torch.cuda.synchronize()
+        loop_s = time.perf_counter() - t0
+        del outs
+        # open loop: Poisson arrivals
+        rate = 0.7 * capacity / mean_size
+        arrivals = workloads.poisson_arrivals(rate, args.serve_seconds, seed=7)
+        pick = np.random.default_rng(8).integers(0, len(pool), size=arrivals.size)
+        log(f"serving: capacity {capacity / 1e9:.2f} GKeys/s closed loop; offered "
+            f"{rate:.1f} req/s for {args.serve_seconds} s ({arrivals.size} requests)")
+        lat, keys_done, batch_sizes = [], 0, []
+        outstanding = {}
+        t0 = time.perf_counter()
+        i = 0
+        next_note = 10.0
+        while i < arrivals.size or outstanding:
+            now = time.perf_counter() - t0
+            while i < arrivals.size and arrivals[i] <= now:
+                x, p = pool[int(pick[i])]
+                ko, po = torch.empty_like(x), torch.empty_like(p)
+                outstanding[srv.submit(x, p, ko, po)] = (ko, po)
+                i += 1
+            for rid in list(outstanding):
+                rc, info = srv.poll(rid)
+                if rc == 0:
+                    lat.append((info["t_done_ns"] - info["t_submit_ns"]) * 1e-6)
+                    batch_sizes.append(info["batch_requests"])
+                    keys_done += outstanding[rid][0].numel()
+                    srv.release(rid)
+                    del outstanding[rid]
+            if now > next_note:
+                log(f"serving: t={now:.0f} s, submitted {i}, in flight {len(outstanding)}")
+                next_note += 10.0
+            if i < arrivals.size:
+                time.sleep(max(0.0, min(1e-4, arrivals[i] - (time.perf_counter() - t0))))
+            else:
+                time.sleep(5e-5)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array(lat)
+    return {
+        "workload": "serve_f32: pool of %d float32 requests, sizes floor(2^U) U~U[10,26] (seed 6), "
+                    "N(0,1) keys in random runs U{1..2*sqrt(size)} ascending, ~1%% duplicates, int32 "
+                    "index payload, drawn on the GPU; Poisson arrivals (seed 7), pool entry per "
+                    "arrival (seed 8)" % len(pool),
+        "pool_keys": int(sizes.sum()), "mean_request_keys": round(mean_size, 1),
+        "server": {"hbm_budget_bytes": budget, "n_streams": args.serve_streams,
+                   "max_batch": args.serve_max_batch},
+        "closed_loop_value": round(capacity / 1e9, 4),
+        "per_request_loop_value": round(float(sizes.sum()) / loop_s / 1e9, 4),
+        "speedup_vs_per_request": round(loop_s / closed_s, 3),
+        "offered_rate_rps": round(rate, 2), "offered_load": "0.7 x closed-loop capacity",
+        "seconds": args.serve_seconds, "requests": int(arrivals.size), "completed": int(lat.size),
+        "served_value": round(keys_done / wall / 1e9, 4), "unit": "GKeys/s",
+        "latency_ms_p50": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
+        "latency_ms_p99": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
+        "latency_ms_mean": round(float(lat.mean()), 3) if lat.size else None,
+        "mean_batch_requests": round(float(np.mean(batch_sizes)), 2) if batch_sizes else None,
+        "batches": int(st["batches"]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +290,15 @@ def main():
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-sample-log2n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-m", type=int, default=8192, help="arrays in the batched workload")
+    ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="Poisson run length")
+    ap.add_argument("--serve-pool", type=int, default=512, help="request pool size")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -205,6 +418,17 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(keys_h, pay_h, 1 << args.cpu_sample_log2n, args.k)
+    del keys_h, pay_h, keys0, pay0, keys, pay
+    mps.release_workspaces()
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = bench_batched(args, torch, mps, workloads)
+        mps.release_workspaces()
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = bench_serving(args, torch, mps, workloads)
+        mps.release_workspaces()
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -162,6 +162,81 @@ int mps_trace_fetch(const void *workspace, mps_trace *trace);
 int mps_last_level_stats(uint32_t cap, uint32_t *n_levels, uint64_t *level_elems,
                          float *corank_ms, float *merge_ms);
 
+/* ------------------------------------------------------------ serving
+ * A continuous-batching server (a systems layer around the sort; the paper has
+ * none).  Requests are device-resident and caller-owned; submit never blocks
+ * on the GPU.  A scheduler thread admits queued requests in arrival order
+ * into batches whose device memory -- packed copies of the requests plus the
+ * batched sort's workspace -- fits in the free part of an arena of
+ * hbm_budget_bytes reserved at creation.  Each batch runs on one of n_streams
+ * streams (gather, one mps_sort_batched, scatter), so batches formed from
+ * requests that arrived meanwhile overlap on the device.  Each result is
+ * exactly what mps_sort gives for that request alone.  The server uses the
+ * device that is current when it is created. */
+typedef struct mps_server mps_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* device arena for admitted requests (allocated once) */
+    uint32_t n_streams;         /* batches in flight at once (0: 2; at most 16) */
+    uint32_t max_batch;         /* requests per batch (0: 256) */
+    uint32_t k;                 /* merge arity (0: 4) */
+    uint32_t tile, lane_slice;  /* merge tile configuration (0: defaults, as mps_opts) */
+    uint32_t poll_us;           /* scheduler wake-up period while batches run (0: 20 us) */
+    uint32_t fail_every;        /* testing: every fail_every-th batch is failed on the host
+                                   before anything is enqueued (0: never) */
+} mps_serve_cfg;
+
+typedef struct {
+    const void *keys;           /* device, n keys (read only) */
+    const uint32_t *payload;    /* device, n payloads, or NULL */
+    void *keys_out;             /* device, n keys: the sorted keys (may equal keys) */
+    uint32_t *payload_out;      /* device, NULL iff payload is NULL (may equal payload) */
+    uint64_t n;                 /* <= 2^31 */
+    mps_key_type kt;
+    void *ready_event;          /* hipEvent_t or NULL: the batch's stream waits for it before
+                                   reading the inputs (e.g. recorded after the work that
+                                   produced them); must stay valid until completion */
+} mps_request;
+
+typedef struct {
+    uint64_t t_submit_ns;       /* host steady clock at submit */
+    uint64_t t_admit_ns;        /* when its batch was formed and enqueued */
+    uint64_t t_done_ns;         /* when the scheduler saw the batch complete */
+    uint64_t batch;             /* batch number (from 1) */
+    uint32_t batch_requests;    /* requests in that batch */
+    int status;                 /* MPS_PENDING, MPS_OK or an error */
+} mps_req_info;
+
+typedef struct {
+    uint64_t queued;            /* submitted, not yet admitted */
+    uint64_t batches;           /* batches launched so far */
+    uint64_t arena_bytes, arena_used;
+    uint32_t busy_streams;
+} mps_serve_stats_t;
+
+/* MPS_E_INVALID (bad cfg), MPS_E_UNSUPPORTED, MPS_E_NOMEM (budget above the
+ * free device memory, or allocation failure), MPS_E_HIP. */
+int mps_serve_create(const mps_serve_cfg *cfg, mps_server **out);
+/* Queues a request; *req_id identifies it.  The caller keeps every buffer valid
+ * until poll reports completion.  MPS_E_INVALID for NULL pointers or a payload
+ * without payload_out, MPS_E_NOMEM if the request alone needs more than the
+ * whole budget, MPS_E_UNSUPPORTED for n > 2^31. */
+int mps_serve_submit(mps_server *s, const mps_request *req, uint64_t *req_id);
+/* Status of a request (MPS_PENDING, MPS_OK, or the error that ended it --
+ * MPS_E_HIP for a failed launch, MPS_E_DEVICE for a failed device-side
+ * check); info (nullable) receives its timestamps.  MPS_E_NOTFOUND for an
+ * unknown or released id. */
+int mps_serve_poll(mps_server *s, uint64_t req_id, mps_req_info *info);
+/* Forgets a finished request (MPS_E_INVALID if it is still pending). */
+int mps_serve_release(mps_server *s, uint64_t req_id);
+int mps_serve_stats(mps_server *s, mps_serve_stats_t *stats);
+/* Stops accepting requests, finishes every queued and running one, and frees
+ * the server. */
+int mps_serve_destroy(mps_server *s);
+/* Host-only self-test of the server's arena allocator and batching policy
+ * (needs no GPU): 0, or the number of the first failed check. */
+int mps_serve_selftest(void);
+
 /* Message describing the last error of the calling thread ("" if none). */
 const char *mps_last_error(void);
 

@@ -30,7 +30,9 @@ KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
 
 EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
             "mps_sort_ex", "mps_sort_batched", "mps_autotune", "mps_trace_fetch",
-            "mps_last_level_stats", "mps_last_error"]
+            "mps_last_level_stats", "mps_serve_create", "mps_serve_submit", "mps_serve_poll",
+            "mps_serve_release", "mps_serve_stats", "mps_serve_destroy", "mps_serve_selftest",
+            "mps_last_error"]
 
 
 class MpsError(RuntimeError):
@@ -66,6 +68,31 @@ class _Trace(ctypes.Structure):
                 ("node_begin", ctypes.c_void_p), ("node_end", ctypes.c_void_p),
                 ("node_first", ctypes.c_void_p), ("node_arity", ctypes.c_void_p),
                 ("node_power", ctypes.c_void_p), ("node_depth", ctypes.c_void_p)]
+
+
+class _ServeCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("k", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("lane_slice", ctypes.c_uint32), ("poll_us", ctypes.c_uint32),
+                ("fail_every", ctypes.c_uint32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("payload", ctypes.c_void_p),
+                ("keys_out", ctypes.c_void_p), ("payload_out", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("kt", ctypes.c_int), ("ready_event", ctypes.c_void_p)]
+
+
+class _ReqInfo(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("batch", ctypes.c_uint64),
+                ("batch_requests", ctypes.c_uint32), ("status", ctypes.c_int)]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("arena_used", ctypes.c_uint64),
+                ("busy_streams", ctypes.c_uint32)]
 
 
 _lib = None
@@ -106,6 +133,20 @@ def lib() -> ctypes.CDLL:
             l.mps_trace_fetch.restype = i32
             l.mps_last_level_stats.argtypes = [u32, P, P, P, P]
             l.mps_last_level_stats.restype = i32
+            l.mps_serve_create.argtypes = [ctypes.POINTER(_ServeCfg), ctypes.POINTER(P)]
+            l.mps_serve_create.restype = i32
+            l.mps_serve_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(u64)]
+            l.mps_serve_submit.restype = i32
+            l.mps_serve_poll.argtypes = [P, u64, ctypes.POINTER(_ReqInfo)]
+            l.mps_serve_poll.restype = i32
+            l.mps_serve_release.argtypes = [P, u64]
+            l.mps_serve_release.restype = i32
+            l.mps_serve_stats.argtypes = [P, ctypes.POINTER(_ServeStats)]
+            l.mps_serve_stats.restype = i32
+            l.mps_serve_destroy.argtypes = [P]
+            l.mps_serve_destroy.restype = i32
+            l.mps_serve_selftest.argtypes = []
+            l.mps_serve_selftest.restype = i32
             l.mps_last_error.argtypes = []
             l.mps_last_error.restype = ctypes.c_char_p
             _lib = l
@@ -147,10 +188,19 @@ def _workspace(device, nbytes: int):
     with _ws_lock:
         buf = _ws.get(key)
         if buf is None or buf.numel() < nbytes:
+            # drop every reference to the old buffer first, so that its memory can be
+            # reused for the larger one
+            buf = None
             _ws.pop(key, None)
             buf = torch.empty(int(nbytes * 1.05) + 4096, dtype=torch.uint8, device=device)
             _ws[key] = buf
         return buf
+
+
+def release_workspaces():
+    """Drop the cached torch workspaces (they are reallocated on the next call)."""
+    with _ws_lock:
+        _ws.clear()
 
 
 def _check_tensors(keys, payload):
@@ -342,3 +392,97 @@ def level_stats(cap: int = 64):
                                       mms.ctypes.data))
     n = min(int(nl.value), cap)
     return elems[:n].copy(), cms[:n].copy(), mms[:n].copy()
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching sort server (mps_serve_*): submit device tensors at any
+    time, poll for completion.  Each result equals sort() of that request alone.
+
+        with mps.Server(hbm_budget_bytes=8 << 30) as srv:
+            rid = srv.submit(keys, payload, keys_out, payload_out)
+            srv.wait(rid)
+    """
+
+    def __init__(self, hbm_budget_bytes: int, *, n_streams: int = 2, max_batch: int = 256,
+                 k: int = 4, tile: int = 0, lane_slice: int = 0, poll_us: int = 0,
+                 fail_every: int = 0):
+        cfg = _ServeCfg(hbm_budget_bytes=int(hbm_budget_bytes), n_streams=n_streams,
+                        max_batch=max_batch, k=k, tile=tile, lane_slice=lane_slice,
+                        poll_us=poll_us, fail_every=fail_every)
+        h = ctypes.c_void_p()
+        _check(lib().mps_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit(self, keys, payload=None, keys_out=None, payload_out=None) -> int:
+        """Queue a sort of `keys` (and `payload`) into keys_out / payload_out (default:
+        in place).  The tensors are kept alive until release(); the request waits for
+        the work queued so far on the current stream."""
+        torch = _torch()
+        _check_tensors(keys, payload)
+        keys_out = keys if keys_out is None else keys_out
+        if payload is not None and payload_out is None:
+            payload_out = payload
+        if keys_out.dtype != keys.dtype or keys_out.numel() != keys.numel() or not keys_out.is_contiguous():
+            raise ValueError("keys_out must match keys")
+        if payload_out is not None and (payload is None or payload_out.numel() != keys.numel()):
+            raise ValueError("payload_out needs a payload of the same length")
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(keys.device))
+        req = _Request(keys=keys.data_ptr(), payload=payload.data_ptr() if payload is not None else None,
+                       keys_out=keys_out.data_ptr(),
+                       payload_out=payload_out.data_ptr() if payload_out is not None else None,
+                       n=keys.numel(), kt=key_type_of(keys), ready_event=ev.cuda_event)
+        rid = ctypes.c_uint64(0)
+        _check(lib().mps_serve_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._live[rid.value] = (keys, payload, keys_out, payload_out, ev)
+        return rid.value
+
+    def poll(self, rid: int):
+        """(status, info): status is MPS_PENDING (1), MPS_OK (0) or raises MpsError."""
+        info = _ReqInfo()
+        rc = lib().mps_serve_poll(self._h, rid, ctypes.byref(info))
+        if rc < 0:
+            raise MpsError(rc, lib().mps_last_error().decode())
+        return rc, dict(t_submit_ns=info.t_submit_ns, t_admit_ns=info.t_admit_ns,
+                        t_done_ns=info.t_done_ns, batch=info.batch,
+                        batch_requests=info.batch_requests)
+
+    def wait(self, rid: int, timeout: float | None = None, sleep: float = 50e-6):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            rc, info = self.poll(rid)
+            if rc == MPS_OK:
+                return info
+            if timeout is not None and time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"request {rid} still pending after {timeout} s")
+            time.sleep(sleep)
+
+    def release(self, rid: int):
+        _check(lib().mps_serve_release(self._h, rid))
+        self._live.pop(rid, None)
+
+    def stats(self) -> dict:
+        st = _ServeStats()
+        _check(lib().mps_serve_stats(self._h, ctypes.byref(st)))
+        return dict(queued=st.queued, batches=st.batches, arena_bytes=st.arena_bytes,
+                    arena_used=st.arena_used, busy_streams=st.busy_streams)
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().mps_serve_destroy(self._h))
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def serve_selftest() -> int:
+    """Host-only self-test of the server's allocator and batching policy (no GPU)."""
+    return int(lib().mps_serve_selftest())

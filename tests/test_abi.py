@@ -57,3 +57,10 @@ def test_argument_errors_need_no_gpu():
     off = (ctypes.c_uint64 * 2)(0, (1 << 31) + 5)
     assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 1, (1 << 31) + 5, None, None,
                                 None) == -4
+
+
+def test_serve_host_selftest():
+    """The request server's arena allocator and batch-formation policy (host code,
+    no GPU): first-fit allocation, coalescing, accounting under random churn, and
+    arrival-order batches split by key type, count and memory."""
+    assert mps.serve_selftest() == 0

@@ -160,3 +160,95 @@ def test_graph_rejects_level_timing():
     kd = to_dev(np.arange(1000, dtype=np.int32))
     with pytest.raises(mps.MpsError):
         mps.sort(kd, graph=True, time_levels=True)
+
+
+def test_autotune_picks_a_candidate_and_sorts():
+    say("[gpu] autotune small")
+    keys, pay, off = uneven_batch(200, 47, 6.0, 14.0)
+    kd, pd = to_dev(keys), pay_dev(pay)
+    od = torch.from_numpy(off.view(np.int64)).to(DEV)
+    best = mps.autotune(kd, pd, off, sample_keys=1 << 18, graph=True, with_times=True)
+    cands = best["candidates"]
+    assert len(cands) == 12 and all(np.isfinite(c["ms"]) and c["ms"] > 0 for c in cands)
+    fastest = min(cands, key=lambda c: c["ms"])
+    assert (best["k"], best["tile"], best["lane_slice"]) == (fastest["k"], fastest["tile"],
+                                                             fastest["lane_slice"])
+    # the input was only sampled, never modified
+    assert np.array_equal(kd.cpu().numpy(), keys)
+    again = mps.autotune(kd, pd, off, sample_keys=1 << 18, graph=True)   # cached
+    assert (again["k"], again["tile"], again["lane_slice"]) == (best["k"], best["tile"],
+                                                                best["lane_slice"])
+    k = best["k"]
+    ok, op, M, rs, pw = batch_truth(keys, pay, off, k)
+    tr = mps.sort_batched(kd, pd, od, k=k, tile=best["tile"], lane_slice=best["lane_slice"],
+                          trace=True)
+    assert np.array_equal(kd.cpu().numpy(), ok)
+    assert np.array_equal(pd.cpu().numpy().view(np.uint32), op)
+    assert tr.merge_cost == M and np.array_equal(tr.power, pw)
+
+
+def device_check_sorted_batch(k_in, k_out, p_out, off, chunk=1 << 27):
+    """Properties that single out the stable sort of every array, checked with torch
+    on the device chunk by chunk: non-decreasing keys, payload a permutation of the
+    array's indices, every output key equal to the input key its payload names, and
+    equal keys in increasing payload order."""
+    m = off.size - 1
+    i = 0
+    while i < m:
+        j, n = i, 0
+        while j < m and (j == i or n + int(off[j + 1] - off[j]) <= chunk):
+            n += int(off[j + 1] - off[j])
+            j += 1
+        s0 = int(off[i])
+        if n:
+            sz = torch.as_tensor((off[i + 1:j + 1] - off[i:j]).astype(np.int64), device=DEV)
+            starts = torch.cumsum(sz, 0) - sz
+            first = torch.zeros(n, dtype=torch.bool, device=DEV)
+            first[starts[sz > 0]] = True
+            ko = k_out[s0:s0 + n].to(torch.int64)
+            po = p_out[s0:s0 + n].to(torch.int64)
+            inner = ~first[1:]
+            assert bool(((ko[1:] >= ko[:-1]) | ~inner).all())
+            loc = torch.repeat_interleave(starts, sz)
+            assert bool(((po >= 0) & (po < torch.repeat_interleave(sz, sz))).all())
+            g = loc + po
+            seen = torch.zeros(n, dtype=torch.bool, device=DEV)
+            seen[g] = True
+            assert bool(seen.all())
+            assert bool((k_in[s0:s0 + n].to(torch.int64)[g] == ko).all())
+            eq = (ko[1:] == ko[:-1]) & inner
+            assert bool(((po[1:] > po[:-1]) | ~eq).all())
+        i = j
+
+
+def test_batched_full_size():
+    """The batched workload at full size (8192 arrays, ~3.5e9 keys) in the autotuned
+    graph configuration the benchmark times: every array checked by properties on the
+    device, and 12 sampled arrays (the smallest, the largest and 10 seeded picks)
+    bit-exact against the oracle."""
+    say("[gpu] batched full size: generating")
+    mps.release_workspaces()
+    torch.cuda.empty_cache()
+    kin, pin, off = workloads.batch_i32_device(m=8192, device=DEV)
+    od = torch.from_numpy(off.view(np.int64)).to(DEV)
+    best = mps.autotune(kin, pin, off, sample_keys=1 << 25, graph=True)
+    say(f"[gpu] batched full size: total {int(off[-1])}, tuned {best}")
+    kd, pd = kin.clone(), pin.clone()
+    mps.sort_batched(kd, pd, od, graph=True, **best)
+    torch.cuda.synchronize()
+    say("[gpu] batched full size: device property checks")
+    device_check_sorted_batch(kin, kd, pd, off)
+    sizes = np.diff(off.astype(np.int64))
+    pick = set(np.random.default_rng(3).choice(sizes.size, 10, replace=False).tolist())
+    pick |= {int(sizes.argmin()), int(sizes.argmax())}
+    say(f"[gpu] batched full size: oracle on arrays {sorted(pick)}")
+    for i in sorted(pick):
+        s, e = int(off[i]), int(off[i + 1])
+        keys = kin[s:e].cpu().numpy()
+        pay = pin[s:e].cpu().numpy().view(np.uint32)
+        ok, op, _ = oracle.sort(keys, pay, k=best["k"])
+        assert np.array_equal(kd[s:e].cpu().numpy(), ok), f"array {i}"
+        assert np.array_equal(pd[s:e].cpu().numpy().view(np.uint32), op), f"array {i}"
+    del kin, pin, kd, pd
+    mps.release_workspaces()
+    torch.cuda.empty_cache()

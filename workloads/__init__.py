@@ -7,7 +7,14 @@ oracle nor the GPU library, so both sides can be fed the same arrays.
 The paper measures on synthetic data only (Section 4.3: integers with random
 runs, 16-byte records, random permutations); its generator code is not
 published, so the recipes below are this project's stand-ins for those inputs.
-All draws use numpy's PCG64 ``default_rng(seed)``.
+All host draws use numpy's PCG64 ``default_rng(seed)``.  The two large pools
+(the batched workload at full size, about 3.5e9 keys, and the serving request
+pool) are drawn on the GPU with a seeded torch generator instead, so that the
+benchmark does not spend minutes on the host: sizes and run lengths still come
+from PCG64, and the keys of each run are drawn already in ascending order as
+order statistics (the ascending sample of L uniforms has the law of the
+normalised partial sums S_1/S_{L+1} < ... < S_L/S_{L+1} of L+1 standard
+exponential gaps), so no per-run sort is needed.
 
 Workloads (sizes can be scaled down for tests; the recipe stays the same):
   runs_i32      n=2^20 int32; run lengths U{1..2048} (last run truncated);
@@ -24,6 +31,7 @@ Workloads (sizes can be scaled down for tests; the recipe stays the same):
   batch_i32     m=8192 arrays, sizes floor(2^U), U~U[8,22]; int32 full range;
                 run lengths U{1..floor(2*sqrt(size))}, sorted ascending;
                 payload = index within the array.  Packed with uint64 offsets.
+  batch_i32_device  the same recipe at full size on the GPU (order statistics).
   serve_f32     request pool: sizes floor(2^U), U~U[10,26]; float32 ~ N(0,1)
                 redrawn while |x| < FLT_MIN (all normal numbers); about 1% of
                 positions overwritten by copies of other keys of the same
@@ -212,3 +220,94 @@ WORKLOADS = {
     "perm_i64": perm_i64,
     "ties_i32": ties_i32,
 }
+
+
+# ---------------------------------------------------------------- device pools
+def _batch_layout(m: int, seed: int, lo_exp: float, hi_exp: float):
+    """Array sizes, offsets and per-array run lengths (host, PCG64)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(2.0 ** rng.uniform(lo_exp, hi_exp, size=m)).astype(np.int64)
+    offsets = np.zeros(m + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(sizes)
+    lens = []
+    for sz in sizes.tolist():
+        mr = max(1, int(2 * math.isqrt(sz)))
+        lens.append(_run_lengths(rng, sz, lambda g, c, mr=mr: g.integers(1, mr + 1, size=c)))
+    return sizes, offsets, lens
+
+
+def _sorted_uniform_runs(torch, gen, run_lens, device):
+    """float64 tensor: for each run of length L, L ascending uniforms in (0,1) drawn
+    as order statistics (partial sums of L+1 exponential gaps over their total)."""
+    lens = torch.as_tensor(run_lens, dtype=torch.int64, device=device)
+    R = lens.numel()
+    T = int(lens.sum())
+    gaps = torch.empty(T + R, dtype=torch.float64, device=device).exponential_(generator=gen)
+    cs = gaps.cumsum_(0)
+    run_id = torch.repeat_interleave(torch.arange(R, device=device), lens)
+    slot = torch.arange(T, device=device) + run_id                  # run r owns L_r + 1 slots
+    first = torch.cumsum(lens, 0) - lens + torch.arange(R, device=device)   # first slot of run r
+    base = torch.where(first > 0, cs[(first - 1).clamp_min(0)], torch.zeros_like(cs[:1]))
+    total = cs[first + lens] - base
+    u = (cs[slot] - base[run_id]) / total[run_id]
+    return u
+
+
+def batch_i32_device(m: int = 8192, seed: int = 5, lo_exp: float = 8.0, hi_exp: float = 22.0,
+                     device: str = "cuda:0", chunk_keys: int = 1 << 27):
+    """The batched workload drawn on the GPU: (keys int32 tensor, payload int32 tensor =
+    index within the array, host offsets uint64[m+1]).  Same sizes and run-length
+    recipe as batch_i32; keys uniform over int32, ascending within runs."""
+    import torch
+    sizes, offsets, lens = _batch_layout(m, seed, lo_exp, hi_exp)
+    total = int(offsets[-1])
+    keys = torch.empty(total, dtype=torch.int32, device=device)
+    pay = torch.empty(total, dtype=torch.int32, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    i = 0
+    while i < m:
+        j, n = i, 0
+        while j < m and (j == i or n + sizes[j] <= chunk_keys):
+            n += int(sizes[j])
+            j += 1
+        s0 = int(offsets[i])
+        if n:
+            u = _sorted_uniform_runs(torch, gen, np.concatenate(lens[i:j]), device)
+            k = torch.floor(u * 4294967296.0) - 2147483648.0
+            keys[s0:s0 + n] = k.clamp_(-2147483648.0, 2147483647.0).to(torch.int32)
+            sz = torch.as_tensor(sizes[i:j], device=device)
+            starts = torch.cumsum(sz, 0) - sz
+            pay[s0:s0 + n] = (torch.arange(n, device=device)
+                              - torch.repeat_interleave(starts, sz)).to(torch.int32)
+        i = j
+    return keys, pay, offsets
+
+
+def serve_pool_device(count: int = 512, seed: int = 6, lo_exp: float = 10.0, hi_exp: float = 26.0,
+                      device: str = "cuda:0"):
+    """Serving request pool on the GPU: a list of (keys float32 tensor, payload int32 =
+    index) per request.  Sizes floor(2^U), U~U[lo,hi] (PCG64, seed); keys N(0,1) in random
+    runs U{1..floor(2*sqrt(size))}, ascending within a run (normal quantiles of sorted
+    uniforms, kept away from 0 so every key is a normal float32), and about 1% of the
+    positions repeat their left neighbour's key (duplicates)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(2.0 ** rng.uniform(lo_exp, hi_exp, size=count)).astype(np.int64)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    tiny = float(np.finfo(np.float32).tiny)
+    pool = []
+    for sz in sizes.tolist():
+        mr = max(1, int(2 * math.isqrt(sz)))
+        lens = _run_lengths(rng, sz, lambda g, c: g.integers(1, mr + 1, size=c))
+        u = _sorted_uniform_runs(torch, gen, lens, device)
+        x = torch.special.ndtri(u).to(torch.float32)
+        small = x.abs() < tiny
+        x = torch.where(small, torch.where(x < 0, -tiny, tiny), x)   # no zeros or subnormals
+        if sz > 1:
+            nd = max(1, sz // 100)
+            pos = torch.randint(1, sz, (nd,), generator=gen, device=device)
+            x[pos] = x[pos - 1]
+        pool.append((x, torch.arange(sz, dtype=torch.int32, device=device)))
+    return pool
