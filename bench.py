@@ -108,7 +108,7 @@ def bench_batched(args, torch, mps, workloads):
 
     log(f"batched: total {total} keys; autotuning")
     t0 = time.perf_counter()
-    tuned = mps.autotune(keys0, pay0, off_h, sample_keys=1 << 25, graph=True, with_times=True)
+    tuned = mps.autotune(keys0, pay0, off_h, sample_keys=1 << 28, graph=True, with_times=True)
     tune_s = time.perf_counter() - t0
     cfg = dict(k=tuned["k"], tile=tuned["tile"], lane_slice=tuned["lane_slice"])
     log(f"batched: tuned {cfg} in {tune_s:.1f} s")
@@ -161,7 +161,7 @@ def bench_batched(args, torch, mps, workloads):
         "per_array_value": gk(t_loop), "per_array_ms": round(t_loop, 3),
         "speedup_vs_per_array": round(t_loop / t_tuned, 3),
         "unit": "GKeys/s",
-        "tuned": cfg, "tune_seconds": round(tune_s, 2), "tune_sample_keys": 1 << 25,
+        "tuned": cfg, "tune_seconds": round(tune_s, 2), "tune_sample_keys": 1 << 28,
         "tune_candidates": tuned["candidates"],
         "merge_cost": int(tr.merge_cost), "runs": int(tr.r),
         "sort_hbm": {"algorithmic_bytes": int(sort_bytes),

@@ -67,8 +67,8 @@ typedef struct {
     uint32_t tile;              /* merge tile, outputs per workgroup task: 1024, 2048
                                    (default) or 4096 */
     uint32_t lane_slice;        /* outputs each thread merges per LDS stage (tile divided by
-                                   the workgroup size): 4 or 8; 0 = 8 for 4096-tiles, 4
-                                   otherwise.  Valid pairs: 1024/4, 2048/8, 2048/4, 4096/8 */
+                                   the workgroup size): 4 or 8; 0 = 4.  Valid pairs: 1024/4,
+                                   2048/8, 2048/4, 4096/8, 4096/4 */
 } mps_opts;
 
 /* What the sort did (filled when a trace pointer is passed; forces a stream
@@ -128,13 +128,13 @@ int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload, const uint6
 
 /* Autotuner for batched sorts (a systems layer; the paper has no such step).
  * Times every candidate configuration -- arity k in {4, 2, 8} times the tile
- * configurations (tile, lane_slice) in {2048/8, 1024/4, 2048/4, 4096/8}, in
- * that order -- on a sample of the batch (whole arrays from the start, up to
- * sample_cap keys; 0 = 2^24) and writes the fastest into best->k, best->tile
+ * configurations (tile, lane_slice) in {2048/8, 1024/4, 2048/4, 4096/8,
+ * 4096/4}, in that order -- on a sample of the batch (whole arrays from the start, up to
+ * sample_cap keys; 0 = 2^27) and writes the fastest into best->k, best->tile
  * and best->lane_slice (other fields untouched).  keys / payload are the
  * batch's device arrays (read only; the sample is copied), h_offsets its host
  * offsets [m+1].  flags: 0 or MPS_OPT_GRAPH (time graph replays, as a caller
- * using MPS_OPT_GRAPH will run).  cand_ms (nullable, 12 floats) receives every
+ * using MPS_OPT_GRAPH will run).  cand_ms (nullable, 15 floats) receives every
  * candidate's mean time in ms.  The choice is cached per device, key type,
  * payload presence, log2(total keys) and log2(mean array size); a cached
  * choice is returned without timing unless cand_ms is requested.  Allocates

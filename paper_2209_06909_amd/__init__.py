@@ -44,7 +44,7 @@ class MpsError(RuntimeError):
 OPT_TIME_LEVELS = 1
 OPT_GRAPH = 2
 # merge tile configurations: (outputs per tile, outputs per thread per LDS stage)
-TILE_CONFIGS = [(1024, 4), (2048, 8), (2048, 4), (4096, 8)]
+TILE_CONFIGS = [(1024, 4), (2048, 8), (2048, 4), (4096, 8), (4096, 4)]
 
 
 class _Opts(ctypes.Structure):
@@ -354,10 +354,12 @@ def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
     return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)
 
 
-TUNE_CANDIDATES = [(k, t, e) for k in (4, 2, 8) for (t, e) in TILE_CONFIGS]
+# candidate order of mps_autotune: arity outer, tile configuration inner
+TUNE_CANDIDATES = [(k, t, e) for k in (4, 2, 8)
+                   for (t, e) in ((2048, 8), (1024, 4), (2048, 4), (4096, 8), (4096, 4))]
 
 
-def autotune(keys, payload, host_offsets, *, sample_keys: int = 1 << 24, graph: bool = True,
+def autotune(keys, payload, host_offsets, *, sample_keys: int = 1 << 27, graph: bool = True,
              stream=None, with_times: bool = False):
     """Pick arity and merge tile configuration for batched sorts of this shape by
     timing every candidate on a sample of the batch (see mps_autotune).  Returns

@@ -345,11 +345,12 @@ int graph_launch(const GraphKey &key, void *keys, int kt, uint32_t *payload,
 int resolve_tile(const mps_opts *opts, int &tile, int &threads) {
   uint32_t t = opts && opts->tile ? opts->tile : (uint32_t)kTileDefault;
   uint32_t e = opts ? opts->lane_slice : 0;
-  if (e == 0) e = t == 4096 ? 8 : 4;   // measured fastest per tile size
+  if (e == 0) e = 4;
   if (t != 1024 && t != 2048 && t != 4096) return fail(MPS_E_UNSUPPORTED, "tile must be 1024, 2048 or 4096");
   if (e != 4 && e != 8) return fail(MPS_E_UNSUPPORTED, "lane_slice must be 4 or 8");
   if (!tile_config_ok((int)t, (int)(t / e)))
-    return fail(MPS_E_UNSUPPORTED, "unsupported tile / lane_slice pair (1024/4, 2048/8, 2048/4, 4096/8)");
+    return fail(MPS_E_UNSUPPORTED,
+                "unsupported tile / lane_slice pair (1024/4, 2048/8, 2048/4, 4096/8, 4096/4)");
   tile = (int)t;
   threads = (int)(t / e);
   return MPS_OK;

@@ -158,14 +158,15 @@ struct LevelArgs {
 };
 
 // Merge tile configurations (outputs per tile x threads per workgroup):
-// 1024x256, 2048x256, 2048x512 (default) and 4096x512.
+// 1024x256, 2048x256, 2048x512 (default), 4096x512 and 4096x1024.
 constexpr int kTileMin = 1024;
 constexpr int kTileDefault = 2048;
 constexpr int kTileDescBytes = 256;  // >= sizeof(TileDesc<8>)
 
 inline bool tile_config_ok(int tile, int threads) {
   return (tile == 1024 && threads == 256) || (tile == 2048 && threads == 256) ||
-         (tile == 2048 && threads == 512) || (tile == 4096 && threads == 512);
+         (tile == 2048 && threads == 512) || (tile == 4096 && threads == 512) ||
+         (tile == 4096 && threads == 1024);
 }
 
 // Records the calling thread's error message (read by mps_last_error) and returns code.
@@ -186,6 +187,7 @@ MPS_DECLARE_MERGES(launch_merges_1024x256)
 MPS_DECLARE_MERGES(launch_merges_2048x256)
 MPS_DECLARE_MERGES(launch_merges_2048x512)
 MPS_DECLARE_MERGES(launch_merges_4096x512)
+MPS_DECLARE_MERGES(launch_merges_4096x1024)
 #undef MPS_DECLARE_MERGES
 // Same as launch_level, with events recorded before the co-rank, between co-rank and merge,
 // and after the merge launch (all on stream s).

@@ -17,7 +17,9 @@ namespace mps {
 
 // ---------------------------------------------------------------- placement
 constexpr int kPlaceThreads = 256;
-constexpr uint64_t kPlaceBlock = 4096;
+constexpr int kPlaceE = 8;                                   // positions per thread
+constexpr uint64_t kPlaceBlock = (uint64_t)kPlaceThreads * kPlaceE;
+constexpr int kPlaceRuns = 512;                              // run table entries staged in LDS
 
 __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, uint64_t e) {
   // last j in [lo, hi] with rs[j] <= e
@@ -28,6 +30,13 @@ __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, 
   return lo;
 }
 
+// Each workgroup step covers kPlaceBlock positions.  The runs overlapping it
+// are staged in LDS (start and a flag byte: bit 0 odd depth, bit 1 descending)
+// unless there are too many; then every position finds its run and what to do
+// with it, all loads are issued, then all stores.  Odd-depth leaves are copied
+// to the other buffer (reversed if descending); even-depth descending runs are
+// reversed in place by the threads of their first half, each swapping with
+// its mirror position.
 template <typename U>
 __global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
                                                          uint32_t *__restrict__ vals,
@@ -37,34 +46,94 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
                                                          const uint8_t *__restrict__ desc,
                                                          const uint8_t *__restrict__ leaf_depth,
                                                          const Plan *__restrict__ plan) {
+  __shared__ uint64_t sRs[kPlaceRuns + 1];
+  __shared__ uint8_t sFl[kPlaceRuns];
   __shared__ uint64_t sJ[2];
   const uint64_t r = plan->r;
+  const int t = threadIdx.x;
   const uint64_t nblk = (N + kPlaceBlock - 1) / kPlaceBlock;
   for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-    uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
-    if (threadIdx.x == 0) {
+    const uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
+    if (t == 0) {
       sJ[0] = run_of(rs, 0, r - 1, bs);
       sJ[1] = run_of(rs, sJ[0], r - 1, be - 1);
     }
     __syncthreads();
-    uint64_t j0 = sJ[0], j1 = sJ[1];
-    for (uint64_t e = bs + threadIdx.x; e < be; e += kPlaceThreads) {
-      uint64_t j = run_of(rs, j0, j1, e);
-      uint64_t s = rs[j], f = rs[j + 1];
-      bool odd = leaf_depth[j] & 1, dsc = desc[j];
-      if (odd) {
-        uint64_t dst = dsc ? s + f - 1 - e : e;
-        akeys[dst] = keys[e];
-        if (vals) avals[dst] = vals[e];
-      } else if (dsc && e - s < (f - s) / 2) {
-        uint64_t m = s + f - 1 - e;
-        U a = keys[e], c = keys[m];
-        keys[e] = c;
-        keys[m] = a;
-        if (vals) {
-          uint32_t x = vals[e], y = vals[m];
-          vals[e] = y;
-          vals[m] = x;
+    const uint64_t j0 = sJ[0], j1 = sJ[1];
+    const int nr = (int)(j1 - j0 + 1);
+    const bool staged = nr <= kPlaceRuns;
+    int any = 0;
+    if (staged) {
+      for (int i = t; i <= nr; i += kPlaceThreads) sRs[i] = rs[j0 + i];
+      for (int i = t; i < nr; i += kPlaceThreads) {
+        uint8_t f = (uint8_t)((leaf_depth[j0 + i] & 1) | (desc[j0 + i] ? 2 : 0));
+        sFl[i] = f;
+        any |= f;
+      }
+    }
+    any = __syncthreads_or(any) || !staged;
+    if (any) {
+      uint64_t dst[kPlaceE];
+      int act[kPlaceE];
+#pragma unroll
+      for (int i = 0; i < kPlaceE; i++) {
+        const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
+        act[i] = 0;
+        dst[i] = e;
+        if (e < be) {
+          uint64_t s, f;
+          int fl;
+          if (staged) {
+            int lo = 0, hi = nr - 1;   // last run with start <= e
+            while (hi > lo) {
+              int mid = (lo + hi + 1) >> 1;
+              if (sRs[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            s = sRs[lo];
+            f = sRs[lo + 1];
+            fl = sFl[lo];
+          } else {
+            uint64_t j = run_of(rs, j0, j1, e);
+            s = rs[j];
+            f = rs[j + 1];
+            fl = (leaf_depth[j] & 1) | (desc[j] ? 2 : 0);
+          }
+          if (fl & 1) {
+            act[i] = 1;
+            dst[i] = (fl & 2) ? s + f - 1 - e : e;
+          } else if ((fl & 2) && e - s < (f - s) / 2) {
+            act[i] = 2;
+            dst[i] = s + f - 1 - e;
+          }
+        }
+      }
+      U ka[kPlaceE], kb[kPlaceE];
+      uint32_t va[kPlaceE], vb[kPlaceE];
+#pragma unroll
+      for (int i = 0; i < kPlaceE; i++) {
+        const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
+        if (act[i]) {
+          ka[i] = keys[e];
+          if (vals) va[i] = vals[e];
+        }
+        if (act[i] == 2) {
+          kb[i] = keys[dst[i]];
+          if (vals) vb[i] = vals[dst[i]];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kPlaceE; i++) {
+        const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
+        if (act[i] == 1) {
+          akeys[dst[i]] = ka[i];
+          if (vals) avals[dst[i]] = va[i];
+        } else if (act[i] == 2) {
+          keys[e] = kb[i];
+          keys[dst[i]] = ka[i];
+          if (vals) {
+            vals[e] = vb[i];
+            vals[dst[i]] = va[i];
+          }
         }
       }
     }
@@ -126,6 +195,7 @@ static hipError_t launch_merges(int kt, const LevelArgs &a, const Work &w, const
   if (w.tile == 2048 && w.threads == 256) return launch_merges_2048x256(kt, a, w, tj, tile_base, level, s);
   if (w.tile == 2048 && w.threads == 512) return launch_merges_2048x512(kt, a, w, tj, tile_base, level, s);
   if (w.tile == 4096 && w.threads == 512) return launch_merges_4096x512(kt, a, w, tj, tile_base, level, s);
+  if (w.tile == 4096 && w.threads == 1024) return launch_merges_4096x1024(kt, a, w, tj, tile_base, level, s);
   return hipErrorInvalidValue;
 }
 

@@ -34,7 +34,7 @@ std::map<TuneKey, TuneVal> g_tune_cache;
 
 // Candidates: arity x tile configuration.
 const uint32_t kArities[3] = {4, 2, 8};
-const uint32_t kTiles[4][2] = {{2048, 8}, {1024, 4}, {2048, 4}, {4096, 8}};
+const uint32_t kTiles[5][2] = {{2048, 8}, {1024, 4}, {2048, 4}, {4096, 8}, {4096, 4}};
 
 struct DevBuf {
   void *p = nullptr;
@@ -80,11 +80,11 @@ extern "C" int mps_autotune(const void *keys, mps_key_type kt, const uint32_t *p
     }
   }
   // sample: whole arrays from the start, up to sample_cap keys (at least one array)
-  if (sample_cap == 0) sample_cap = 1ull << 24;
+  if (sample_cap == 0) sample_cap = 1ull << 27;   // well beyond the last-level cache
   uint64_t ms = 0;
   while (ms < m && (ms == 0 || h_offsets[ms + 1] <= sample_cap)) ms++;
   const uint64_t sn = h_offsets[ms];
-  std::vector<float> times(12, INFINITY);
+  std::vector<float> times(15, INFINITY);
   hipStream_t s = (hipStream_t)stream;
   uint32_t bk = 4, bt = 2048, bl = 8;
   if (sn >= 2) {
@@ -160,7 +160,7 @@ extern "C" int mps_autotune(const void *keys, mps_key_type kt, const uint32_t *p
     if (rc != MPS_OK) return rc;
   }
   if (cand_ms)
-    for (int i = 0; i < 12; i++) cand_ms[i] = times[i];
+    for (int i = 0; i < 15; i++) cand_ms[i] = times[i];
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = TuneVal{bk, bt, bl};

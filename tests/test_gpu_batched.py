@@ -169,7 +169,7 @@ def test_autotune_picks_a_candidate_and_sorts():
     od = torch.from_numpy(off.view(np.int64)).to(DEV)
     best = mps.autotune(kd, pd, off, sample_keys=1 << 18, graph=True, with_times=True)
     cands = best["candidates"]
-    assert len(cands) == 12 and all(np.isfinite(c["ms"]) and c["ms"] > 0 for c in cands)
+    assert len(cands) == len(mps.TUNE_CANDIDATES) and all(np.isfinite(c["ms"]) and c["ms"] > 0 for c in cands)
     fastest = min(cands, key=lambda c: c["ms"])
     assert (best["k"], best["tile"], best["lane_slice"]) == (fastest["k"], fastest["tile"],
                                                              fastest["lane_slice"])
@@ -231,7 +231,7 @@ def test_batched_full_size():
     torch.cuda.empty_cache()
     kin, pin, off = workloads.batch_i32_device(m=8192, device=DEV)
     od = torch.from_numpy(off.view(np.int64)).to(DEV)
-    best = mps.autotune(kin, pin, off, sample_keys=1 << 25, graph=True)
+    best = mps.autotune(kin, pin, off, sample_keys=1 << 28, graph=True)
     say(f"[gpu] batched full size: total {int(off[-1])}, tuned {best}")
     kd, pd = kin.clone(), pin.clone()
     mps.sort_batched(kd, pd, od, graph=True, **best)
