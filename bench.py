@@ -290,6 +290,7 @@ def main():
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-sample-log2n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-k-sweep", action="store_true")
     ap.add_argument("--batched-m", type=int, default=8192, help="arrays in the batched workload")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
@@ -388,6 +389,20 @@ def main():
         roof["traffic"] = round(tr_d["bytes_per_merged_element"] * per_launch)
         roof["traffic_per_merged_element"] = tr_d["bytes_per_merged_element"]
         roof["traffic_ratio_to_algorithmic"] = tr_d["ratio_to_algorithmic"]
+    # measured copy ceiling: a device-to-device copy of the same key and payload
+    # arrays (every byte read once and written once), as context for the roofline
+    cp_ms = []
+    for _ in range(3):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        keys.copy_(keys0)
+        pay.copy_(pay0)
+        c1.record()
+        c1.synchronize()
+        cp_ms.append(c0.elapsed_time(c1))
+    copy_gbs = 2 * n * KV / (min(cp_ms) * 1e-3) / 1e9
+    roof["copy_ceiling_GBs"] = round(copy_gbs, 1)
+    roof["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 4)
     levels_all = merge_bytes / ((merge_ms + corank_ms) * 1e-3) / 1e9
     sort_bytes = n * 8 + 2 * KV * placed + 2 * KV * tr.merge_cost
     sort_gbs = sort_bytes / (ms * 1e-3) / 1e9
@@ -415,6 +430,23 @@ def main():
         "levels": [{"d": d, "elems": int(per_level[0][d]), "corank_ms": round(float(per_level[1][d]), 4),
                     "merge_ms": round(float(per_level[2][d]), 4)} for d in range(len(per_level[0]))],
     }
+    if not args.no_k_sweep:
+        # the paper's central comparison (Section 4, Table 1): the same input sorted with
+        # 2-way, 4-way and 8-way merging -- merge cost and time
+        sweep = []
+        for kk in (2, 4, 8):
+            keys.copy_(keys0)
+            pay.copy_(pay0)
+            trk = mps.sort(keys, pay, k=kk, trace=True, trace_arrays=False, **tcfg)
+            t_k, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
+                                lambda: mps.sort(keys, pay, k=kk, **tcfg))
+            sweep.append({"k": kk, "ms": round(t_k, 3), "gkeys_s": round(n / (t_k * 1e-3) / 1e9, 3),
+                          "merge_cost": int(trk.merge_cost),
+                          "merge_cost_per_key": round(trk.merge_cost / n, 4),
+                          "tree_levels": int(trk.n_levels)})
+        m4 = next(x["merge_cost"] for x in sweep if x["k"] == 4)
+        m2 = next(x["merge_cost"] for x in sweep if x["k"] == 2)
+        out["k_sweep"] = {"runs": sweep, "merge_cost_ratio_k4_over_k2": round(m4 / m2, 4)}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(keys_h, pay_h, 1 << args.cpu_sample_log2n, args.k)

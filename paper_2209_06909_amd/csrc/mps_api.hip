@@ -77,7 +77,7 @@ struct Layout {
   size_t alt_keys, alt_vals, seg_off, dbits, det_agg, det_zin, det_off, run_start, run_desc,
       power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
       dist0, dist1, leaf_depth, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
-      tj, plan;
+      tj, samples, plan;
   uint64_t rmax, nbb, tiles_max, tj_cap;
   int levels;
 };
@@ -145,6 +145,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.corank = take(c, tiles_max * k * 4);
   L.tile_desc = take(c, tiles_max * kTileDescBytes);
   L.gen_list = take(c, tiles_max * 4);
+  L.samples = take(c, (N / kSampleStride + 2) * 8);
   L.tile_base = take(c, (kMaxLevels + 1) * 8);
   L.tj_cap = (tiles_max + 1) * (uint64_t)levels + 64;
   L.tj = take(c, L.tj_cap * 4);
@@ -421,6 +422,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   w.corank = at<uint32_t>(base, L.corank);
   w.tile_desc = at<void>(base, L.tile_desc);
   w.gen_list = at<uint32_t>(base, L.gen_list);
+  w.samples = at<uint64_t>(base, L.samples);
   w.plan = at<Plan>(base, L.plan);
   uint64_t *lvl_tot = at<uint64_t>(base, L.lvl_tot);
   uint64_t *tile_base = at<uint64_t>(base, L.tile_base);

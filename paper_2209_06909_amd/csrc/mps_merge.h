@@ -62,7 +62,89 @@ __device__ inline bool st_less(O x, int a, O y, int b) {
 // splits the remaining rank over the windows proportionally, checks whether
 // the split is a consistent cut (largest taken < smallest untaken in the
 // stable order) and otherwise shrinks the window of the largest taken element
-// from above and that of the smallest untaken element from below.
+// from above and that of the smallest untaken element from below.  get(j, i)
+// is the order key of element i of list j.
+template <typename O, int K, typename Get>
+__device__ inline void corank_search(int d, uint64_t q, uint64_t (&lo)[K], uint64_t (&hi)[K],
+                                     uint64_t (&cut)[K], Get get) {
+  uint64_t mm[K];
+  for (int j = 0; j < K; j++) mm[j] = 0;
+  for (int it = 0; it < 4096; it++) {
+    uint64_t slo = 0, W = 0;
+    for (int j = 0; j < d; j++) { slo += lo[j]; W += hi[j] - lo[j]; }
+    uint64_t rem = q - slo;
+    if (rem == 0) { for (int j = 0; j < d; j++) mm[j] = 0; break; }
+    if (rem == W) { for (int j = 0; j < d; j++) mm[j] = hi[j] - lo[j]; break; }
+    // Proportional split of rem over the windows.  The split only steers the
+    // search (any split with 0 <= mm_j <= w_j summing to rem is a valid probe), so
+    // it is computed in double precision -- 64-bit integer division has no
+    // hardware instruction and would dominate the search -- and then corrected
+    // to sum exactly to rem.
+    const double f = (double)rem / (double)W;
+    uint64_t sm = 0;
+    for (int j = 0; j < d; j++) {
+      const uint64_t w = hi[j] - lo[j];
+      uint64_t v = (uint64_t)((double)w * f);
+      mm[j] = v < w ? v : w;
+      sm += mm[j];
+    }
+    for (int j = 0; j < d && sm > rem; j++) {
+      const uint64_t dec = mm[j] < sm - rem ? mm[j] : sm - rem;
+      mm[j] -= dec;
+      sm -= dec;
+    }
+    for (int j = 0; j < d && sm < rem; j++) {
+      const uint64_t w = hi[j] - lo[j];
+      const uint64_t inc = w - mm[j] < rem - sm ? w - mm[j] : rem - sm;
+      mm[j] += inc;
+      sm += inc;
+    }
+    int a = -1, b = -1;
+    O xa = 0, yb = 0;
+    for (int j = 0; j < d; j++) {
+      uint64_t w = hi[j] - lo[j];
+      if (mm[j] > 0) {
+        O x = get(j, lo[j] + mm[j] - 1);
+        if (a < 0 || !st_less(x, j, xa, a)) { xa = x; a = j; }
+      }
+      if (mm[j] < w) {
+        O y = get(j, lo[j] + mm[j]);
+        if (b < 0 || st_less(y, j, yb, b)) { yb = y; b = j; }
+      }
+    }
+    // Consistent cut: the largest taken element precedes the smallest
+    // untaken one.  Within one child positions decide, so a == b is
+    // always consistent; across children (key, child) decides.
+    if (a < 0 || b < 0 || a == b || st_less(xa, a, yb, b)) break;
+    hi[a] = lo[a] + mm[a] - 1;
+    lo[b] = lo[b] + mm[b] + 1;
+  }
+  for (int j = 0; j < d; j++) cut[j] = lo[j] + mm[j];
+}
+
+// Every kSampleStride-th key of a level's input (global positions 0, S, 2S, ...),
+// as order keys, so that co-ranking can narrow its windows on a sample that
+// stays in cache before it probes the full arrays.
+
+template <int KT>
+__global__ __launch_bounds__(256) void k_sample(const typename Key<KT>::U *__restrict__ in_keys,
+                                               uint64_t N, const Plan *__restrict__ plan,
+                                               int level, uint64_t *__restrict__ smp) {
+  if (plan->lvl_tiles[level] == 0) return;
+  const uint64_t ns = (N + kSampleStride - 1) / kSampleStride;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    smp[i] = (uint64_t)Key<KT>::ord(in_keys[i * kSampleStride]);
+}
+
+// Cuts of every tile boundary of a level.  For a large node the windows are
+// first narrowed on the sample: child j's samples are the level samples whose
+// positions fall in the child (local positions o_j + x*S).  If the true cut
+// takes c_j* samples of child j, then a_j*/S - 1 < c_j* < a_j*/S + 1, so the
+// sample rank Q* = sum c_j* lies strictly between q/S - d and q/S + d.  Sample
+// cuts are nested in the stable order, so the sample cut at rank
+// Qlo <= Q* takes only truly taken samples (a lower bound per child) and the
+// one at Qhi >= Q* leaves only truly untaken samples untaken (an upper bound).
 template <int KT, int K>
 __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__restrict__ in_keys,
                                                 const uint64_t *__restrict__ rs,
@@ -75,8 +157,10 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
                                                 const uint32_t *__restrict__ tj,
                                                 const uint64_t *__restrict__ tile_base,
                                                 Plan *__restrict__ plan, int level,
-                                                int tile, uint32_t *__restrict__ cr) {
+                                                int tile, uint32_t *__restrict__ cr,
+                                                const uint64_t *__restrict__ smp) {
   using O = typename Key<KT>::U;
+  constexpr uint64_t S = kSampleStride;
   const uint64_t tiles = plan->lvl_tiles[level];
   if (tiles == 0) return;
   const uint64_t r = plan->r;
@@ -100,48 +184,54 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
       }
       if (q > 0) {
         const int d = nd.d;
-        uint64_t lo[K], hi[K], mm[K];
+        uint64_t lo[K], hi[K], cut[K];
         for (int j = 0; j < K; j++) {
           uint64_t len = j < d ? nd.c[j + 1] - nd.c[j] : 0;
           lo[j] = 0;
           hi[j] = len < q ? len : q;
         }
-        for (int it = 0; it < 4096; it++) {
-          uint64_t slo = 0, W = 0;
-          for (int j = 0; j < d; j++) { slo += lo[j]; W += hi[j] - lo[j]; }
-          uint64_t rem = q - slo;
-          if (rem == 0) { for (int j = 0; j < d; j++) mm[j] = 0; break; }
-          if (rem == W) { for (int j = 0; j < d; j++) mm[j] = hi[j] - lo[j]; break; }
-          uint64_t sm = 0;
-          for (int j = 0; j < d; j++) {
-            uint64_t w = hi[j] - lo[j];
-            mm[j] = (w * rem) / W;  // w < 2^31, rem < 2^32
-            sm += mm[j];
+        if (nd.c[d] - nd.c[0] >= 16 * S * (uint64_t)d) {
+          uint64_t i0[K], m[K], off[K], slo[K], shi[K], clo[K], chi[K];
+          uint64_t ms = 0;
+          for (int j = 0; j < K; j++) {
+            i0[j] = m[j] = off[j] = 0;
+            if (j >= d) continue;
+            i0[j] = (nd.c[j] + S - 1) / S;
+            const uint64_t i1 = (nd.c[j + 1] + S - 1) / S;
+            m[j] = i1 - i0[j];
+            off[j] = i0[j] * S - nd.c[j];
+            ms += m[j];
           }
-          for (int j = 0; j < d && sm < rem; j++)
-            if (mm[j] < hi[j] - lo[j]) { mm[j]++; sm++; }
-          int a = -1, b = -1;
-          O xa = 0, yb = 0;
+          auto gs = [&](int j, uint64_t x) { return (O)smp[i0[j] + x]; };
+          const uint64_t qs = q / S;
+          uint64_t qlo = qs > (uint64_t)d ? qs - d : 0;
+          qlo = qlo < ms ? qlo : ms;
+          const uint64_t qhi = qs + d + 1 < ms ? qs + d + 1 : ms;
+          for (int j = 0; j < K; j++) { slo[j] = 0; shi[j] = j < d ? (m[j] < qlo ? m[j] : qlo) : 0; }
+          corank_search<O, K>(d, qlo, slo, shi, clo, gs);
+          for (int j = 0; j < K; j++) { slo[j] = 0; shi[j] = j < d ? (m[j] < qhi ? m[j] : qhi) : 0; }
+          corank_search<O, K>(d, qhi, slo, shi, chi, gs);
+          uint64_t sl = 0, sh = 0;
+          uint64_t nlo[K], nhi[K];
           for (int j = 0; j < d; j++) {
-            uint64_t w = hi[j] - lo[j];
-            uint64_t base = nd.c[j] + lo[j];
-            if (mm[j] > 0) {
-              O x = Key<KT>::ord(in_keys[base + mm[j] - 1]);
-              if (a < 0 || !st_less(x, j, xa, a)) { xa = x; a = j; }
-            }
-            if (mm[j] < w) {
-              O y = Key<KT>::ord(in_keys[base + mm[j]]);
-              if (b < 0 || st_less(y, j, yb, b)) { yb = y; b = j; }
-            }
+            const uint64_t len = nd.c[j + 1] - nd.c[j];
+            nlo[j] = clo[j] >= 1 ? off[j] + (clo[j] - 1) * S + 1 : 0;
+            nhi[j] = chi[j] < m[j] ? off[j] + chi[j] * S : len;
+            if (nhi[j] > hi[j]) nhi[j] = hi[j];
+            sl += nlo[j];
+            sh += nhi[j];
           }
-          // Consistent cut: the largest taken element precedes the smallest
-          // untaken one.  Within one child positions decide, so a == b is
-          // always consistent; across children (key, child) decides.
-          if (a < 0 || b < 0 || a == b || st_less(xa, a, yb, b)) break;
-          hi[a] = lo[a] + mm[a] - 1;
-          lo[b] = lo[b] + mm[b] + 1;
+          bool sane = sl <= q && sh >= q;
+          for (int j = 0; j < d; j++) sane = sane && nlo[j] <= nhi[j];
+          if (sane) {
+            for (int j = 0; j < d; j++) { lo[j] = nlo[j]; hi[j] = nhi[j]; }
+          } else {
+            atomicOr(&plan->error, 512u);   // never expected: fall back to whole windows
+          }
         }
-        for (int j = 0; j < d; j++) out[j] = (uint32_t)(lo[j] + mm[j]);
+        auto gk = [&](int j, uint64_t x) { return Key<KT>::ord(in_keys[nd.c[j] + x]); };
+        corank_search<O, K>(d, q, lo, hi, cut, gk);
+        for (int j = 0; j < d; j++) out[j] = (uint32_t)cut[j];
       }
     }
     for (int j = 0; j < K; j++) cr[t * K + j] = out[j];
@@ -543,11 +633,16 @@ __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
   }
 }
 
-// Descriptor tiles.  Each workgroup walks tiles blockIdx.x, +gridDim.x, ...
-// (skipping those of the general path) software-pipelined: while tile i is
-// merged in LDS, the descriptor of tile i+2 and the input slices of tile i+1
-// are already being fetched into registers, so global latency overlaps the
-// LDS work.
+// Tiles per work-queue claim of the descriptor-tile kernel: the claiming wave
+// waits for the claim's return, which also waits for all of its outstanding
+// memory operations, so claims should be rare.
+constexpr int kFastClaim = 8;
+
+// Descriptor tiles.  Each workgroup takes tiles from the level's work queue
+// (kFastClaim at a time, skipping those of the general path) and processes
+// them software-pipelined: while tile i is merged in LDS, the descriptor of
+// tile i+2 and the input slices of tile i+1 are already being fetched into
+// registers, so global latency overlaps the LDS work.
 template <int KT, int K, int TILE, int THREADS, bool HV>
 __global__ __launch_bounds__(THREADS) void k_merge_fast(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
@@ -572,11 +667,12 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
   uint32_t *queue = &plan->q_fast[level];
   const int t = threadIdx.x;
 
-  // the first two tiles in one claim
-  if (t == 0) sm.claim[0] = atomicAdd(queue, 2u);
+  if (t == 0) sm.claim[0] = atomicAdd(queue, (uint32_t)kFastClaim);
   __syncthreads();
-  uint64_t tile = sm.claim[0];
-  uint64_t nxt = tile + 1;
+  uint64_t cbase = sm.claim[0];
+  int cidx = 2;
+  uint64_t tile = cbase;
+  uint64_t nxt = cbase + 1;
   if (tile >= tiles) return;
 
   O kreg[E];
@@ -599,8 +695,9 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
 
   while (tile < tiles) {
     // claim the tile after next now; its index is published after the next barrier
+    const bool reclaim = cidx == kFastClaim;
     uint32_t claimed = 0;
-    if (t == 0) claimed = atomicAdd(queue, 1u);
+    if (reclaim && t == 0) claimed = atomicAdd(queue, (uint32_t)kFastClaim);
     SmallTab<K> &T = sm.tab[cur];
     SmallTab<K> &N = sm.tab[cur ^ 1];
     const int kind = T.kind;
@@ -610,10 +707,14 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
     lds_barrier();
     if (t == 0) {
       build_small<K>(N, *reinterpret_cast<const TileDesc<K> *>(sm.raw), nxt < tiles);
-      sm.claim[1] = claimed;
+      if (reclaim) sm.claim[1] = claimed;
     }
     lds_barrier();
-    const uint64_t after = sm.claim[1];
+    if (reclaim) {
+      cbase = sm.claim[1];
+      cidx = 0;
+    }
+    const uint64_t after = cbase + (uint64_t)cidx++;
     if (t < NW && after < tiles) dreg = descw[after * DW + t];
     if (N.kind == kTabFast) {
       addr_desc<E, THREADS, MAXS>(ga, N.sl_off, N.delta, N.S, N.Tt, t);

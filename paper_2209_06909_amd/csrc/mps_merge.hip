@@ -163,9 +163,13 @@ static void launch_cuts_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
                           const uint64_t *tile_base, int level, hipStream_t s) {
   using U = typename Key<KT>::U;
   const unsigned gc = 512;
+  const uint64_t ns = (w.N + kSampleStride - 1) / kSampleStride;
+  const unsigned gs = (unsigned)((ns + 255) / 256 < 4096 ? (ns + 255) / 256 : 4096);
+  hipLaunchKernelGGL((k_sample<KT>), dim3(gs), dim3(256), 0, s, (const U *)a.in_keys, w.N, w.plan,
+                     level, w.samples);
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
-                     tile_base, w.plan, level, w.tile, w.corank);
+                     tile_base, w.plan, level, w.tile, w.corank, (const uint64_t *)w.samples);
   TileDesc<K> *desc = reinterpret_cast<TileDesc<K> *>(w.tile_desc);
   hipLaunchKernelGGL((k_tile_desc<K>), dim3(gc), dim3(256), 0, s, w.run_start, w.Ls, w.Rs,
                      w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level,
