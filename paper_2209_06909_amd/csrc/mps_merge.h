@@ -65,50 +65,55 @@ __device__ inline bool st_less(O x, int a, O y, int b) {
 // from above and that of the smallest untaken element from below.  get(j, i)
 // is the order key of element i of list j.
 template <typename O, int K, typename Get>
-__device__ inline void corank_search(int d, uint64_t q, uint64_t (&lo)[K], uint64_t (&hi)[K],
+__device__ inline void corank_search(int d, uint64_t q64, uint64_t (&lo64)[K], uint64_t (&hi64)[K],
                                      uint64_t (&cut)[K], Get get) {
-  uint64_t mm[K];
-  for (int j = 0; j < K; j++) mm[j] = 0;
+  // A node holds at most 2^31 elements, so ranks and windows fit in 32 bits.
+  uint32_t lo[K], hi[K], mm[K];
+  for (int j = 0; j < K; j++) {
+    lo[j] = (uint32_t)lo64[j];
+    hi[j] = (uint32_t)hi64[j];
+    mm[j] = 0;
+  }
+  const uint32_t q = (uint32_t)q64;
   for (int it = 0; it < 4096; it++) {
-    uint64_t slo = 0, W = 0;
+    uint32_t slo = 0, W = 0;
     for (int j = 0; j < d; j++) { slo += lo[j]; W += hi[j] - lo[j]; }
-    uint64_t rem = q - slo;
+    const uint32_t rem = q - slo;
     if (rem == 0) { for (int j = 0; j < d; j++) mm[j] = 0; break; }
     if (rem == W) { for (int j = 0; j < d; j++) mm[j] = hi[j] - lo[j]; break; }
     // Proportional split of rem over the windows.  The split only steers the
-    // search (any split with 0 <= mm_j <= w_j summing to rem is a valid probe), so
-    // it is computed in double precision -- 64-bit integer division has no
-    // hardware instruction and would dominate the search -- and then corrected
-    // to sum exactly to rem.
-    const double f = (double)rem / (double)W;
-    uint64_t sm = 0;
+    // search (any split with 0 <= mm_j <= w_j summing to rem is a valid probe),
+    // so it is computed in single precision and then corrected to sum exactly to
+    // rem.
+    const float f = (float)rem / (float)W;
+    uint32_t sm = 0;
     for (int j = 0; j < d; j++) {
-      const uint64_t w = hi[j] - lo[j];
-      uint64_t v = (uint64_t)((double)w * f);
+      const uint32_t w = hi[j] - lo[j];
+      const uint32_t v = (uint32_t)((float)w * f);
       mm[j] = v < w ? v : w;
       sm += mm[j];
     }
     for (int j = 0; j < d && sm > rem; j++) {
-      const uint64_t dec = mm[j] < sm - rem ? mm[j] : sm - rem;
+      const uint32_t dec = mm[j] < sm - rem ? mm[j] : sm - rem;
       mm[j] -= dec;
       sm -= dec;
     }
     for (int j = 0; j < d && sm < rem; j++) {
-      const uint64_t w = hi[j] - lo[j];
-      const uint64_t inc = w - mm[j] < rem - sm ? w - mm[j] : rem - sm;
+      const uint32_t w = hi[j] - lo[j];
+      const uint32_t inc = w - mm[j] < rem - sm ? w - mm[j] : rem - sm;
       mm[j] += inc;
       sm += inc;
     }
     int a = -1, b = -1;
     O xa = 0, yb = 0;
     for (int j = 0; j < d; j++) {
-      uint64_t w = hi[j] - lo[j];
+      const uint32_t w = hi[j] - lo[j];
       if (mm[j] > 0) {
-        O x = get(j, lo[j] + mm[j] - 1);
+        O x = get(j, (uint64_t)(lo[j] + mm[j] - 1));
         if (a < 0 || !st_less(x, j, xa, a)) { xa = x; a = j; }
       }
       if (mm[j] < w) {
-        O y = get(j, lo[j] + mm[j]);
+        O y = get(j, (uint64_t)(lo[j] + mm[j]));
         if (b < 0 || st_less(y, j, yb, b)) { yb = y; b = j; }
       }
     }
@@ -119,7 +124,7 @@ __device__ inline void corank_search(int d, uint64_t q, uint64_t (&lo)[K], uint6
     hi[a] = lo[a] + mm[a] - 1;
     lo[b] = lo[b] + mm[b] + 1;
   }
-  for (int j = 0; j < d; j++) cut[j] = lo[j] + mm[j];
+  for (int j = 0; j < d; j++) cut[j] = (uint64_t)(lo[j] + mm[j]);
 }
 
 // Every kSampleStride-th key of a level's input (global positions 0, S, 2S, ...),
