@@ -119,18 +119,30 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
   const uint64_t wave_word0 = word0 + (uint64_t)wave * 64;
   O prev_last = 0;
   if (wave_word0 < nwords && wave_word0 > 0) prev_last = K::ord(keys[wave_word0 * 64 - 1]);
-  for (int i = 0; i < 64; i++) {
-    uint64_t w = wave_word0 + i;
-    if (w >= nwords) break;  // uniform across the wave
-    uint64_t p = w * 64 + lane;
-    O x = p < N ? K::ord(keys[p]) : (O)0;
-    O xprev = shfl_any<O>(x, lane > 0 ? lane - 1 : 0);
-    if (lane == 0) xprev = prev_last;
-    prev_last = shfl_any<O>(x, 63);
-    uint64_t sbw = shfl64(sb_own, i);
-    bool d = p < N && p > 0 && !((sbw >> lane) & 1) && x < xprev;
-    uint64_t mask = ballot64(d);
-    if (lane == i) d_own = mask;
+  // 64 words per wave, eight at a time: the eight coalesced loads are issued
+  // together, then the words are processed in order.
+  constexpr int kU = 8;
+  for (int i0 = 0; i0 < 64; i0 += kU) {
+    if (wave_word0 + i0 >= nwords) break;  // uniform across the wave
+    O xs[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint64_t p = (wave_word0 + i0 + u) * 64 + lane;
+      xs[u] = p < N ? K::ord(keys[p]) : (O)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int i = i0 + u;
+      const uint64_t p = (wave_word0 + i) * 64 + lane;
+      const O x = xs[u];
+      O xprev = shfl_any<O>(x, lane > 0 ? lane - 1 : 0);
+      if (lane == 0) xprev = prev_last;
+      prev_last = shfl_any<O>(x, 63);
+      const uint64_t sbw = shfl64(sb_own, i);
+      const bool d = p < N && p > 0 && !((sbw >> lane) & 1) && x < xprev;
+      const uint64_t mask = ballot64(d);
+      if (lane == i) d_own = mask;
+    }
   }
   if (my_word < nwords) dbits[my_word] = d_own;
   sD[t] = d_own;

@@ -30,7 +30,20 @@ __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, 
   return lo;
 }
 
-// Each workgroup step covers kPlaceBlock positions.  The runs overlapping it
+// Same, for an answer expected close to lo (rs[lo] <= e): exponential steps
+// from lo, then a binary search inside the last step.
+__device__ inline uint64_t run_near(const uint64_t *rs, uint64_t lo, uint64_t hi, uint64_t e) {
+  uint64_t step = 1;
+  while (lo + step <= hi && rs[lo + step] <= e) {
+    lo += step;
+    step <<= 1;
+  }
+  return run_of(rs, lo, lo + step - 1 < hi ? lo + step - 1 : hi, e);
+}
+
+// Each workgroup takes a contiguous range of blocks of kPlaceBlock positions,
+// so the runs of one block are found by a short search onward from the
+// previous block's.  The runs overlapping it
 // are staged in LDS (start and a flag byte: bit 0 odd depth, bit 1 descending)
 // unless there are too many; then every position finds its run and what to do
 // with it, all loads are issued, then all stores.  Odd-depth leaves are copied
@@ -52,11 +65,18 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
   const uint64_t r = plan->r;
   const int t = threadIdx.x;
   const uint64_t nblk = (N + kPlaceBlock - 1) / kPlaceBlock;
-  for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+  const uint64_t per = (nblk + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * per;
+  const uint64_t b1 = b0 + per < nblk ? b0 + per : nblk;
+  uint64_t jc = 0;   // thread 0: run containing the current block's first position
+  if (t == 0 && b0 < b1) jc = run_of(rs, 0, r - 1, b0 * kPlaceBlock);
+  for (uint64_t b = b0; b < b1; b++) {
     const uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
     if (t == 0) {
-      sJ[0] = run_of(rs, 0, r - 1, bs);
-      sJ[1] = run_of(rs, sJ[0], r - 1, be - 1);
+      const uint64_t j1 = run_near(rs, jc, r - 1, be - 1);
+      sJ[0] = jc;
+      sJ[1] = j1;
+      if (be < N) jc = run_near(rs, j1, r - 1, be);
     }
     __syncthreads();
     const uint64_t j0 = sJ[0], j1 = sJ[1];
@@ -163,11 +183,14 @@ static void launch_cuts_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
                           const uint64_t *tile_base, int level, hipStream_t s) {
   using U = typename Key<KT>::U;
   const unsigned gc = 512;
+  // the co-rank runs one group of K lanes per tile boundary
+  const uint64_t cgroups = (w.N / (uint64_t)w.tile + 2) * K;
+  const unsigned gk = (unsigned)((cgroups + 255) / 256 < 16384 ? (cgroups + 255) / 256 : 16384);
   const uint64_t ns = (w.N + kSampleStride - 1) / kSampleStride;
   const unsigned gs = (unsigned)((ns + 255) / 256 < 4096 ? (ns + 255) / 256 : 4096);
   hipLaunchKernelGGL((k_sample<KT>), dim3(gs), dim3(256), 0, s, (const U *)a.in_keys, w.N, w.plan,
                      level, w.samples);
-  hipLaunchKernelGGL((k_corank<KT, K>), dim3(gc), dim3(256), 0, s, (const U *)a.in_keys,
+  hipLaunchKernelGGL((k_corank<KT, K>), dim3(gk), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
                      tile_base, w.plan, level, w.tile, w.corank, (const uint64_t *)w.samples);
   TileDesc<K> *desc = reinterpret_cast<TileDesc<K> *>(w.tile_desc);
