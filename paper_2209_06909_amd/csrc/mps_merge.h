@@ -142,14 +142,96 @@ __global__ __launch_bounds__(256) void k_sample(const typename Key<KT>::U *__res
     smp[i] = (uint64_t)Key<KT>::ord(in_keys[i * kSampleStride]);
 }
 
-// Cuts of every tile boundary of a level.  For a large node the windows are
-// first narrowed on the sample: child j's samples are the level samples whose
-// positions fall in the child (local positions o_j + x*S).  If the true cut
-// takes c_j* samples of child j, then a_j*/S - 1 < c_j* < a_j*/S + 1, so the
-// sample rank Q* = sum c_j* lies strictly between q/S - d and q/S + d.  Sample
-// cuts are nested in the stable order, so the sample cut at rank
-// Qlo <= Q* takes only truly taken samples (a lower bound per child) and the
-// one at Qhi >= Q* leaves only truly untaken samples untaken (an upper bound).
+// The same search run by a group of K lanes, lane j holding child j's window
+// (lanes j >= d hold empty windows): sums, the split correction and the
+// largest-taken / smallest-untaken choice are group reductions over shuffles,
+// so one round costs a few instructions per lane instead of a loop over the
+// children, and the probes of one round are issued by different lanes.  The
+// loop condition is uniform within a group.  Returns lane j's cut.
+template <int K>
+__device__ inline uint32_t gsum(uint32_t v) {
+#pragma unroll
+  for (int o = 1; o < K; o <<= 1) v += __shfl_xor(v, o, K);
+  return v;
+}
+
+template <int K>
+__device__ inline uint32_t gexcl(uint32_t v, int j) {   // exclusive prefix sum in the group
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < K; o <<= 1) {
+    uint32_t y = __shfl_up(incl, o, K);
+    if (j >= o) incl += y;
+  }
+  return incl - v;
+}
+
+template <typename O>
+__device__ inline O gshfl(O v, int src, int width);
+template <>
+__device__ inline uint32_t gshfl<uint32_t>(uint32_t v, int src, int width) {
+  return __shfl(v, src, width);
+}
+template <>
+__device__ inline uint64_t gshfl<uint64_t>(uint64_t v, int src, int width) {
+  uint32_t lo = __shfl((uint32_t)v, src, width), hi = __shfl((uint32_t)(v >> 32), src, width);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename O, int K, typename Get>
+__device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, int j, Get get) {
+  uint32_t mm = 0;
+  for (int it = 0; it < 4096; it++) {
+    const uint32_t w = hi - lo;
+    const uint32_t slo = gsum<K>(lo), W = gsum<K>(w);
+    const uint32_t rem = q - slo;
+    if (rem == 0) { mm = 0; break; }
+    if (rem == W) { mm = w; break; }
+    const float f = (float)rem / (float)W;
+    uint32_t v = (uint32_t)((float)w * f);
+    v = v < w ? v : w;
+    const uint32_t sm = gsum<K>(v);
+    if (sm > rem) {          // take the excess from the lanes in order
+      const uint32_t ex = sm - rem, before = gexcl<K>(v, j);
+      const uint32_t dec = ex > before ? (ex - before < v ? ex - before : v) : 0;
+      v -= dec;
+    } else if (sm < rem) {   // give the deficit to the lanes in order
+      const uint32_t de = rem - sm, cap = w - v, before = gexcl<K>(cap, j);
+      const uint32_t inc = de > before ? (de - before < cap ? de - before : cap) : 0;
+      v += inc;
+    }
+    mm = v;
+    // candidate largest taken (x) and smallest untaken (y) of this lane
+    const bool hx = mm > 0, hy = mm < w;
+    O x = hx ? get(j, (uint64_t)(lo + mm - 1)) : (O)0;
+    O y = hy ? get(j, (uint64_t)(lo + mm)) : (O)0;
+    int a = hx ? j : -1, b = hy ? j : -1;
+#pragma unroll
+    for (int o = 1; o < K; o <<= 1) {
+      const int sl = j ^ o;
+      const O xo = gshfl<O>(x, sl, K), yo = gshfl<O>(y, sl, K);
+      const int ao = __shfl(a, sl, K), bo = __shfl(b, sl, K);
+      // stable order (key, child): keep the later of the two taken candidates and
+      // the earlier of the two untaken ones
+      if (ao >= 0 && (a < 0 || st_less(x, a, xo, ao))) { x = xo; a = ao; }
+      if (bo >= 0 && (b < 0 || st_less(yo, bo, y, b))) { y = yo; b = bo; }
+    }
+    if (a < 0 || b < 0 || a == b || st_less(x, a, y, b)) break;
+    if (j == a) hi = lo + mm - 1;
+    if (j == b) lo = lo + mm + 1;
+  }
+  return lo + mm;
+}
+
+// Cuts of every tile boundary of a level, one group of K lanes per boundary.
+// For a large node the windows are first narrowed on the sample: child j's
+// samples are the level samples whose positions fall in the child (local
+// positions o_j + x*S).  If the true cut takes c_j* samples of child j, then
+// a_j*/S - 1 < c_j* < a_j*/S + 1, so the sample rank Q* = sum c_j* lies
+// strictly between q/S - d and q/S + d.  Sample cuts are nested in the stable
+// order, so the sample cut at rank Qlo <= Q* takes only truly taken samples (a
+// lower bound per child) and the one at Qhi >= Q* leaves only truly untaken
+// samples untaken (an upper bound).
 template <int KT, int K>
 __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__restrict__ in_keys,
                                                 const uint64_t *__restrict__ rs,
@@ -173,10 +255,12 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
   const uint64_t nlev = plan->lvl_begin[level + 1] - lb;
   const uint64_t np0 = np[lb];
   const uint32_t *tjl = tj + tile_base[level];
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tiles;
-       t += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t out[K];
-    for (int j = 0; j < K; j++) out[j] = 0;
+  const int j = (int)(threadIdx.x % K);
+  // whole groups iterate together: the bound is a multiple of the group size
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < tiles * K;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t t = g / K;
+    uint32_t out = 0;
     if (t > 0) {
       uint64_t Q = t * (uint64_t)tile;
       uint32_t jn = tjl[t];
@@ -184,62 +268,47 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
       NodeIn nd;
       if (jn >= nlev || !load_node<K>(list[lb + jn], r, rs, Ls, Rs, mem, arity, nd) ||
           q >= nd.c[nd.d] - nd.c[0]) {
-        atomicOr(&plan->error, 128u);
+        if (j == 0) atomicOr(&plan->error, 128u);
         q = 0;
       }
-      if (q > 0) {
+      if (q > 0) {   // uniform within the group
         const int d = nd.d;
-        uint64_t lo[K], hi[K], cut[K];
-        for (int j = 0; j < K; j++) {
-          uint64_t len = j < d ? nd.c[j + 1] - nd.c[j] : 0;
-          lo[j] = 0;
-          hi[j] = len < q ? len : q;
-        }
+        const bool live = j < d;
+        const uint64_t cj = live ? nd.c[j] : 0, len = live ? nd.c[j + 1] - nd.c[j] : 0;
+        uint32_t lo = 0, hi = (uint32_t)(len < q ? len : q);
         if (nd.c[d] - nd.c[0] >= 16 * S * (uint64_t)d) {
-          uint64_t i0[K], m[K], off[K], slo[K], shi[K], clo[K], chi[K];
-          uint64_t ms = 0;
-          for (int j = 0; j < K; j++) {
-            i0[j] = m[j] = off[j] = 0;
-            if (j >= d) continue;
-            i0[j] = (nd.c[j] + S - 1) / S;
-            const uint64_t i1 = (nd.c[j + 1] + S - 1) / S;
-            m[j] = i1 - i0[j];
-            off[j] = i0[j] * S - nd.c[j];
-            ms += m[j];
-          }
-          auto gs = [&](int j, uint64_t x) { return (O)smp[i0[j] + x]; };
+          const uint64_t i0 = live ? (cj + S - 1) / S : 0;
+          const uint32_t m = live ? (uint32_t)((nd.c[j + 1] + S - 1) / S - i0) : 0;
+          const uint64_t off = live ? i0 * S - cj : 0;
+          const uint32_t ms = gsum<K>(m);
+          auto gs = [&](int, uint64_t x) { return (O)smp[i0 + x]; };
           const uint64_t qs = q / S;
           uint64_t qlo = qs > (uint64_t)d ? qs - d : 0;
           qlo = qlo < ms ? qlo : ms;
           const uint64_t qhi = qs + d + 1 < ms ? qs + d + 1 : ms;
-          for (int j = 0; j < K; j++) { slo[j] = 0; shi[j] = j < d ? (m[j] < qlo ? m[j] : qlo) : 0; }
-          corank_search<O, K>(d, qlo, slo, shi, clo, gs);
-          for (int j = 0; j < K; j++) { slo[j] = 0; shi[j] = j < d ? (m[j] < qhi ? m[j] : qhi) : 0; }
-          corank_search<O, K>(d, qhi, slo, shi, chi, gs);
-          uint64_t sl = 0, sh = 0;
-          uint64_t nlo[K], nhi[K];
-          for (int j = 0; j < d; j++) {
-            const uint64_t len = nd.c[j + 1] - nd.c[j];
-            nlo[j] = clo[j] >= 1 ? off[j] + (clo[j] - 1) * S + 1 : 0;
-            nhi[j] = chi[j] < m[j] ? off[j] + chi[j] * S : len;
-            if (nhi[j] > hi[j]) nhi[j] = hi[j];
-            sl += nlo[j];
-            sh += nhi[j];
-          }
-          bool sane = sl <= q && sh >= q;
-          for (int j = 0; j < d; j++) sane = sane && nlo[j] <= nhi[j];
-          if (sane) {
-            for (int j = 0; j < d; j++) { lo[j] = nlo[j]; hi[j] = nhi[j]; }
-          } else {
-            atomicOr(&plan->error, 512u);   // never expected: fall back to whole windows
+          const uint32_t clo = corank_group<O, K>((uint32_t)qlo, 0u,
+                                                  m < qlo ? m : (uint32_t)qlo, j, gs);
+          const uint32_t chi = corank_group<O, K>((uint32_t)qhi, 0u,
+                                                  m < qhi ? m : (uint32_t)qhi, j, gs);
+          uint64_t nlo = clo >= 1 ? off + (uint64_t)(clo - 1) * S + 1 : 0;
+          uint64_t nhi = chi < m ? off + (uint64_t)chi * S : len;
+          if (nhi > hi) nhi = hi;
+          if (!live) nlo = nhi = 0;
+          const uint32_t sl = gsum<K>((uint32_t)nlo), sh = gsum<K>((uint32_t)nhi);
+          const uint32_t bad = gsum<K>(nlo > nhi ? 1u : 0u);
+          if (bad == 0 && sl <= q && sh >= q) {
+            lo = (uint32_t)nlo;
+            hi = (uint32_t)nhi;
+          } else if (j == 0) {
+            atomicOr(&plan->error, 512u);   // never expected: keep the whole windows
           }
         }
-        auto gk = [&](int j, uint64_t x) { return Key<KT>::ord(in_keys[nd.c[j] + x]); };
-        corank_search<O, K>(d, q, lo, hi, cut, gk);
-        for (int j = 0; j < d; j++) out[j] = (uint32_t)cut[j];
+        auto gk = [&](int, uint64_t x) { return Key<KT>::ord(in_keys[cj + x]); };
+        out = corank_group<O, K>((uint32_t)q, lo, hi, j, gk);
+        if (!live) out = 0;
       }
     }
-    for (int j = 0; j < K; j++) cr[t * K + j] = out[j];
+    cr[t * K + j] = out;
   }
 }
 
