@@ -103,7 +103,9 @@ __device__ inline uint64_t dbit_at(const typename Key<KT>::U *keys, const uint64
 template <int KT>
 __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
     const typename Key<KT>::U *__restrict__ keys, uint64_t N, const uint64_t *__restrict__ off,
-    uint64_t m, uint64_t *__restrict__ dbits, DetAgg *__restrict__ agg) {
+    uint64_t m, uint64_t *__restrict__ dbits, DetAgg *__restrict__ agg,
+    uint64_t *__restrict__ smp) {
+  static_assert(kSampleStride % 64 == 0, "samples fall on 64-key word starts");
   using K = Key<KT>;
   using O = typename K::U;
   __shared__ uint64_t sD[kDetThreads], sSB[kDetThreads];
@@ -142,6 +144,8 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
       const bool d = p < N && p > 0 && !((sbw >> lane) & 1) && x < xprev;
       const uint64_t mask = ballot64(d);
       if (lane == i) d_own = mask;
+      if (lane == 0 && p < N && (p & (kSampleStride - 1)) == 0)
+        smp[p / kSampleStride] = (uint64_t)x;   // co-rank sample
     }
   }
   if (my_word < nwords) dbits[my_word] = d_own;
@@ -333,9 +337,9 @@ hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s)
   if (nblk == 0) return hipSuccess;
   dim3 g((unsigned)nblk), b(kDetThreads);
   switch (kt) {
-    case 0: hipLaunchKernelGGL(k_detect_bits<0>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_agg); break;
-    case 1: hipLaunchKernelGGL(k_detect_bits<1>, g, b, 0, s, (const uint64_t *)keys, N, w.off, w.m, w.dbits, w.det_agg); break;
-    default: hipLaunchKernelGGL(k_detect_bits<2>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_agg); break;
+    case 0: hipLaunchKernelGGL(k_detect_bits<0>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_agg, w.samples); break;
+    case 1: hipLaunchKernelGGL(k_detect_bits<1>, g, b, 0, s, (const uint64_t *)keys, N, w.off, w.m, w.dbits, w.det_agg, w.samples); break;
+    default: hipLaunchKernelGGL(k_detect_bits<2>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_agg, w.samples); break;
   }
   hipLaunchKernelGGL(k_detect_scan, dim3(1), dim3(kScanThreads), 0, s, w.det_agg, nblk, N, w.rmax,
                      w.det_zin, w.det_off, w.run_start, w.plan);

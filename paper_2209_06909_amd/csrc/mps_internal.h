@@ -92,7 +92,8 @@ struct Work {
   uint32_t *corank;                  // [(N/tile + 2) * k]
   void *tile_desc;                   // [(N/tile + 2)] per-tile merge descriptors
   uint32_t *gen_list;                // [(N/tile + 2)] tiles of the current level on the general path
-  uint64_t *samples;                 // [N/kSampleStride + 2] sampled order keys of a level's input
+  uint64_t *samples;                 // [N/kSampleStride + 2] order key at every kSampleStride-th
+                                     // position of the array as the last kernel left it
   Plan *plan;
 };
 
@@ -161,7 +162,10 @@ struct LevelArgs {
 // Merge tile configurations (outputs per tile x threads per workgroup):
 // 1024x256, 2048x256, 2048x512 (default), 4096x512 and 4096x1024.
 constexpr int kTileMin = 1024;
-constexpr uint64_t kSampleStride = 256;   // co-rank sample: every 256th key of a level's input
+// Co-rank sample: the order key at every kSampleStride-th position, kept
+// current by the kernels that write keys (run detection, placement, every
+// level merge).  A multiple of 64.
+constexpr uint64_t kSampleStride = 256;
 constexpr int kTileDefault = 2048;
 constexpr int kTileDescBytes = 256;  // >= sizeof(TileDesc<8>)
 

@@ -127,21 +127,6 @@ __device__ inline void corank_search(int d, uint64_t q64, uint64_t (&lo64)[K], u
   for (int j = 0; j < d; j++) cut[j] = (uint64_t)(lo[j] + mm[j]);
 }
 
-// Every kSampleStride-th key of a level's input (global positions 0, S, 2S, ...),
-// as order keys, so that co-ranking can narrow its windows on a sample that
-// stays in cache before it probes the full arrays.
-
-template <int KT>
-__global__ __launch_bounds__(256) void k_sample(const typename Key<KT>::U *__restrict__ in_keys,
-                                               uint64_t N, const Plan *__restrict__ plan,
-                                               int level, uint64_t *__restrict__ smp) {
-  if (plan->lvl_tiles[level] == 0) return;
-  const uint64_t ns = (N + kSampleStride - 1) / kSampleStride;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    smp[i] = (uint64_t)Key<KT>::ord(in_keys[i * kSampleStride]);
-}
-
 // The same search run by a group of K lanes, lane j holding child j's window
 // (lanes j >= d hold empty windows): sums, the split correction and the
 // largest-taken / smallest-untaken choice are group reductions over shuffles,
@@ -224,9 +209,10 @@ __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, in
 }
 
 // Cuts of every tile boundary of a level, one group of K lanes per boundary.
-// For a large node the windows are first narrowed on the sample: child j's
-// samples are the level samples whose positions fall in the child (local
-// positions o_j + x*S).  If the true cut takes c_j* samples of child j, then
+// For a large node the windows are first narrowed on the sample: the order
+// key at every S-th position of the level's input, kept current by the
+// kernels that write keys.  Child j's samples are those whose positions fall
+// in the child (local positions o_j + x*S).  If the true cut takes c_j* samples of child j, then
 // a_j*/S - 1 < c_j* < a_j*/S + 1, so the sample rank Q* = sum c_j* lies
 // strictly between q/S - d and q/S + d.  Sample cuts are nested in the stable
 // order, so the sample cut at rank Qlo <= Q* takes only truly taken samples (a
@@ -691,10 +677,12 @@ __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB
   return (LOGK & 1) ? 1 : 0;
 }
 
+// Coalesced stores of a merged tile; outputs at multiples of kSampleStride also
+// refresh the co-rank sample of their position.
 template <typename Kt, typename O, int E, int THREADS>
 __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
                                   uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
-                                  const uint64_t *pc_out, int P, int Tt, int t) {
+                                  const uint64_t *pc_out, int P, int Tt, int t, uint64_t *smp) {
 #pragma unroll
   for (int i = 0; i < E; i++) {
     int e = t + i * THREADS;
@@ -703,6 +691,7 @@ __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
       uint64_t g = pc_out[p] + (uint64_t)(e - pc_loff[p]);
       out_keys[g] = Kt::unord(ks[e]);
       if (has_vals) out_vals[g] = vs[e];
+      if ((g & (kSampleStride - 1)) == 0) smp[g / kSampleStride] = (uint64_t)ks[e];
     }
   }
 }
@@ -721,7 +710,8 @@ template <int KT, int K, int TILE, int THREADS, bool HV>
 __global__ __launch_bounds__(THREADS) void k_merge_fast(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
-    Plan *__restrict__ plan, int level, const TileDesc<K> *__restrict__ desc) {
+    Plan *__restrict__ plan, int level, const TileDesc<K> *__restrict__ desc,
+    uint64_t *__restrict__ smp) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
   using SM = FastSmem<O, K, TILE>;
@@ -798,7 +788,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
       int res = merge_stages_fast<O, K, TILE, THREADS, HV>(kA, vA, kB, vB, T.sl_off, T.S,
                                                            T.pc_sl, T.P, T.Tt, t);
       store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
-                                    T.pc_loff, T.pc_out, T.P, T.Tt, t);
+                                    T.pc_loff, T.pc_out, T.P, T.Tt, t, smp);
     } else if (kind == kTabBad) {
       if (t == 0) atomicOr(&plan->error, 32u);
     }
@@ -821,7 +811,8 @@ __global__ __launch_bounds__(THREADS) void k_merge_general(
     const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
     const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
     const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level,
-    const uint32_t *__restrict__ cr, const uint32_t *__restrict__ gen_list) {
+    const uint32_t *__restrict__ cr, const uint32_t *__restrict__ gen_list,
+    uint64_t *__restrict__ smp) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
   using SM = GenSmem<O, K, TILE, THREADS>;
@@ -936,7 +927,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_general(
         int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, HV, sm.sl_off, S, sm.pc_sl,
                                                     P, Tt, t);
         store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
-                                      sm.pc_loff, sm.pc_out, P, Tt, t);
+                                      sm.pc_loff, sm.pc_out, P, Tt, t, smp);
       }
     }
     if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
@@ -977,22 +968,22 @@ void launch_merges_kt(const LevelArgs &a, const Work &w, const uint32_t *tj,
     unsigned gf = fill_grid((const void *)kf, THREADS, 1024);
     unsigned gg = fill_grid((const void *)kg, THREADS, 1024);
     hipLaunchKernelGGL(kf, dim3(gf), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.plan, level, desc);
+                       (U *)a.out_keys, a.out_vals, w.plan, level, desc, w.samples);
     hipLaunchKernelGGL(kg, dim3(gg), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
                        (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
                        w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
-                       w.gen_list);
+                       w.gen_list, w.samples);
   } else {
     auto kf = k_merge_fast<KT, K, TILE, THREADS, false>;
     auto kg = k_merge_general<KT, K, TILE, THREADS, false>;
     unsigned gf = fill_grid((const void *)kf, THREADS, 1024);
     unsigned gg = fill_grid((const void *)kg, THREADS, 1024);
     hipLaunchKernelGGL(kf, dim3(gf), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.plan, level, desc);
+                       (U *)a.out_keys, a.out_vals, w.plan, level, desc, w.samples);
     hipLaunchKernelGGL(kg, dim3(gg), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
                        (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
                        w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
-                       w.gen_list);
+                       w.gen_list, w.samples);
   }
 }
 

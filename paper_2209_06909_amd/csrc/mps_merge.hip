@@ -50,15 +50,18 @@ __device__ inline uint64_t run_near(const uint64_t *rs, uint64_t lo, uint64_t hi
 // to the other buffer (reversed if descending); even-depth descending runs are
 // reversed in place by the threads of their first half, each swapping with
 // its mirror position.
-template <typename U>
-__global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
+template <int KT>
+__global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__restrict__ keys,
                                                          uint32_t *__restrict__ vals,
-                                                         U *__restrict__ akeys,
+                                                         typename Key<KT>::U *__restrict__ akeys,
                                                          uint32_t *__restrict__ avals, uint64_t N,
                                                          const uint64_t *__restrict__ rs,
                                                          const uint8_t *__restrict__ desc,
                                                          const uint8_t *__restrict__ leaf_depth,
-                                                         const Plan *__restrict__ plan) {
+                                                         const Plan *__restrict__ plan,
+                                                         uint64_t *__restrict__ smp) {
+  using U = typename Key<KT>::U;
+  constexpr uint64_t SM = kSampleStride - 1;
   __shared__ uint64_t sRs[kPlaceRuns + 1];
   __shared__ uint8_t sFl[kPlaceRuns];
   __shared__ uint64_t sJ[2];
@@ -144,9 +147,11 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
 #pragma unroll
       for (int i = 0; i < kPlaceE; i++) {
         const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
+        // a key that lands on a new position refreshes that position's co-rank sample
         if (act[i] == 1) {
           akeys[dst[i]] = ka[i];
           if (vals) avals[dst[i]] = va[i];
+          if (dst[i] != e && (dst[i] & SM) == 0) smp[dst[i] / kSampleStride] = Key<KT>::ord(ka[i]);
         } else if (act[i] == 2) {
           keys[e] = kb[i];
           keys[dst[i]] = ka[i];
@@ -154,6 +159,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(U *__restrict__ keys,
             vals[e] = vb[i];
             vals[dst[i]] = va[i];
           }
+          if ((e & SM) == 0) smp[e / kSampleStride] = Key<KT>::ord(kb[i]);
+          if ((dst[i] & SM) == 0) smp[dst[i] / kSampleStride] = Key<KT>::ord(ka[i]);
         }
       }
     }
@@ -167,13 +174,17 @@ hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipSt
   unsigned g = (unsigned)(nblk < 8192 ? nblk : 8192);
   if (g == 0) return hipSuccess;
   if (kt == 1)
-    hipLaunchKernelGGL(k_place<uint64_t>, dim3(g), dim3(kPlaceThreads), 0, s, (uint64_t *)keys, vals,
+    hipLaunchKernelGGL(k_place<1>, dim3(g), dim3(kPlaceThreads), 0, s, (uint64_t *)keys, vals,
                        (uint64_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
-                       w.leaf_depth, w.plan);
-  else
-    hipLaunchKernelGGL(k_place<uint32_t>, dim3(g), dim3(kPlaceThreads), 0, s, (uint32_t *)keys, vals,
+                       w.leaf_depth, w.plan, w.samples);
+  else if (kt == 2)
+    hipLaunchKernelGGL(k_place<2>, dim3(g), dim3(kPlaceThreads), 0, s, (uint32_t *)keys, vals,
                        (uint32_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
-                       w.leaf_depth, w.plan);
+                       w.leaf_depth, w.plan, w.samples);
+  else
+    hipLaunchKernelGGL(k_place<0>, dim3(g), dim3(kPlaceThreads), 0, s, (uint32_t *)keys, vals,
+                       (uint32_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
+                       w.leaf_depth, w.plan, w.samples);
   return hipGetLastError();
 }
 
@@ -186,10 +197,6 @@ static void launch_cuts_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
   // the co-rank runs one group of K lanes per tile boundary
   const uint64_t cgroups = (w.N / (uint64_t)w.tile + 2) * K;
   const unsigned gk = (unsigned)((cgroups + 255) / 256 < 16384 ? (cgroups + 255) / 256 : 16384);
-  const uint64_t ns = (w.N + kSampleStride - 1) / kSampleStride;
-  const unsigned gs = (unsigned)((ns + 255) / 256 < 4096 ? (ns + 255) / 256 : 4096);
-  hipLaunchKernelGGL((k_sample<KT>), dim3(gs), dim3(256), 0, s, (const U *)a.in_keys, w.N, w.plan,
-                     level, w.samples);
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gk), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
                      tile_base, w.plan, level, w.tile, w.corank, (const uint64_t *)w.samples);
