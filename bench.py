@@ -303,8 +303,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sort runs on one device; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library sorts on one device and has no "
+              "multi-GPU path (how the sort would shard is a design note)", file=sys.stderr)
         sys.exit(2)
 
     import torch

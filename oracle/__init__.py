@@ -1,7 +1,7 @@
 """Reference CPU implementation of k-way Powersort (TEST INFRASTRUCTURE ONLY).
 
 This package is the checker the GPU library is compared against.  Only the
-test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+test suite, the package smoke check at the repository root and the CPU-baseline leg of
 ``bench.py`` may import it; the product path never does, and it shares no
 code with the GPU library.  The arithmetic lives in ``oracle.c`` (plain C,
 single-threaded); this module only marshals numpy arrays through ctypes.
