@@ -67,6 +67,31 @@ __global__ __launch_bounds__(kCopyThreads) void k_pack(const ReqDesc *__restrict
     __syncthreads();
     uint32_t r = s_r;
     const uint64_t c1 = c0 + kCopyChunk < T ? c0 + kCopyChunk : T;
+    if (c1 - c0 == kCopyChunk && off[r + 1] >= c1) {
+      // The whole chunk lies in request r: every lane issues all of its loads
+      // before its first store, so a wave keeps kCopyChunk / kCopyThreads
+      // accesses of each array in flight.
+      constexpr int E = kCopyChunk / kCopyThreads;
+      const uint64_t b = c0 - off[r] + threadIdx.x;
+      const U *src = dir == 0 ? static_cast<const U *>(d[r].kin) + b : pk + c0 + threadIdx.x;
+      U *dst = dir == 0 ? pk + c0 + threadIdx.x : static_cast<U *>(d[r].kout) + b;
+      U kv[E];
+#pragma unroll
+      for (int e = 0; e < E; e++) kv[e] = src[e * kCopyThreads];
+      if (pp) {
+        const uint32_t *psrc = dir == 0 ? d[r].pin + b : pp + c0 + threadIdx.x;
+        uint32_t *pdst = dir == 0 ? pp + c0 + threadIdx.x : d[r].pout + b;
+        uint32_t pv[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) pv[e] = psrc[e * kCopyThreads];
+#pragma unroll
+        for (int e = 0; e < E; e++) pdst[e * kCopyThreads] = pv[e];
+      }
+#pragma unroll
+      for (int e = 0; e < E; e++) dst[e * kCopyThreads] = kv[e];
+      __syncthreads();
+      continue;
+    }
     for (uint64_t p = c0 + threadIdx.x; p < c1; p += kCopyThreads) {
       while (off[r + 1] <= p) r++;
       const uint64_t i = p - off[r];
