@@ -599,47 +599,47 @@ __device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, boo
   return (LOGK & 1) ? 1 : 0;
 }
 
-// The same stages for a descriptor tile (at most two pieces, MAXS slices).
-// Slice offsets are uniform and held in registers; the lane's merge unit is
-// found with compares instead of searches; the merge-path search is a
-// lower_bound; the sequential merge walks LDS byte offsets (the key buffers
-// carry one element of padding, so reading one past a unit is harmless).
+// The same stages for a descriptor tile (at most two pieces, 2K slices).  A
+// lane owns the E outputs [t*E, t*E+E) at every stage; the slices holding its
+// first and last output are found once per tile.  At stage st the merge unit
+// of slice s is the group of 2^st slices of its piece that contains s, and the
+// unit's bounds are read from the slice-offset table in LDS.  When all E
+// outputs lie in one unit (nearly every lane), one merge-path search and an
+// unrolled E-step merge produce them, and their payloads are gathered after
+// the keys.  Lanes whose outputs straddle a unit boundary walk unit by unit.
+// The key buffers carry one element of padding, so reading one past a unit is
+// harmless.
 template <typename O, int K, int TILE, int THREADS, bool HV>
 __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB,
                                         const uint16_t *sl_off_l, int S, const uint16_t *pc_sl_l,
                                         int P, int Tt, int t) {
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
-  constexpr int MAXS = 2 * K;
   constexpr int KS = (int)sizeof(O);
-  int so[MAXS + 1];
-#pragma unroll
-  for (int j = 0; j <= MAXS; j++) so[j] = j <= S ? (int)sl_off_l[j] : Tt;
   const int s1 = P == 2 ? (int)pc_sl_l[1] : S;   // first slice of the second piece
+  const int e0 = t * E;
+  const int e1 = e0 + E < Tt ? e0 + E : Tt;
+  int sa = 0, sb = 0;
+  if (e0 < e1) {
+    sa = ub16(sl_off_l, S + 1, e0) - 1;
+    sb = ub16(sl_off_l, S + 1, e1 - 1) - 1;
+  }
   O *ks = kA, *kd = kB;
   uint32_t *vs = vA, *vd = vB;
 #pragma unroll
   for (int st = 1; st <= LOGK; st++) {
-    int e = t * E;
-    const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
-    while (e < e_end) {
-      int s = 0;
-#pragma unroll
-      for (int j = 1; j < MAXS; j++) s += (j < S && so[j] <= e) ? 1 : 0;
-      const int s0 = s >= s1 ? s1 : 0;
-      const int pend = s >= s1 ? S : s1;
-      const int h = 1 << (st - 1);
-      const int g0 = s0 + (((s - s0) >> st) << st);
-      const int iM = g0 + h < pend ? g0 + h : pend;
-      const int iR = g0 + 2 * h < pend ? g0 + 2 * h : pend;
-      int u0 = so[0], u1 = so[0], u2 = so[0];
-#pragma unroll
-      for (int j = 1; j <= MAXS; j++) {
-        u0 = j == g0 ? so[j] : u0;
-        u1 = j == iM ? so[j] : u1;
-        u2 = j == iR ? so[j] : u2;
-      }
-      const int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
+    const int h = 1 << (st - 1);
+    const int pa0 = sa >= s1 ? s1 : 0;
+    const int ga = pa0 + (((sa - pa0) >> st) << st);
+    const int pb0 = sb >= s1 ? s1 : 0;
+    const int gb = pb0 + (((sb - pb0) >> st) << st);
+    const char *kb8 = reinterpret_cast<const char *>(ks);
+    if (e0 < e1 && e1 - e0 == E && ga == gb) {
+      const int pend = sa >= s1 ? S : s1;
+      const int iM = ga + h < pend ? ga + h : pend;
+      const int iR = ga + 2 * h < pend ? ga + 2 * h : pend;
+      const int u0 = sl_off_l[ga], u1 = sl_off_l[iM], u2 = sl_off_l[iR];
+      const int nL = u1 - u0, nR = u2 - u1, diag = e0 - u0;
       int lo = diag - nR > 0 ? diag - nR : 0;
       int cnt = (diag < nL ? diag : nL) - lo;
       // smallest i in [lo, lo+cnt] with ks[u0+i] > ks[u1+diag-1-i]
@@ -650,24 +650,71 @@ __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB
         lo = p ? mid + 1 : lo;
         cnt = p ? cnt - half - 1 : half;
       }
-      const int stop = e_end < u2 ? e_end : u2;
-      if (stop <= e) break;  // cannot happen with valid tables (e < u2)
-      // byte offsets into the key buffer; payload offsets are key offsets * 4 / KS
-      const char *kb8 = reinterpret_cast<const char *>(ks);
       uint32_t pa = (uint32_t)(u0 + lo) * KS, pb = (uint32_t)(u1 + diag - lo) * KS;
       const uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
       O ka = *reinterpret_cast<const O *>(kb8 + pa);
       O kb = *reinterpret_cast<const O *>(kb8 + pb);
-      for (; e < stop; e++) {
+      O ok[E];
+      uint32_t os[E];
+#pragma unroll
+      for (int i = 0; i < E; i++) {
         const bool takeL = pa < ea && (pb >= eb || ka <= kb);
-        const uint32_t src = takeL ? pa : pb;
-        kd[e] = takeL ? ka : kb;
-        if (HV) vd[e] = vs[src / KS];
+        ok[i] = takeL ? ka : kb;
+        os[i] = takeL ? pa : pb;
         pa += takeL ? KS : 0;
         pb += takeL ? 0 : KS;
-        const O kn = *reinterpret_cast<const O *>(kb8 + (takeL ? pa : pb));
-        ka = takeL ? kn : ka;
-        kb = takeL ? kb : kn;
+        if (i + 1 < E) {
+          const O kn = *reinterpret_cast<const O *>(kb8 + (takeL ? pa : pb));
+          ka = takeL ? kn : ka;
+          kb = takeL ? kb : kn;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < E; i++) kd[e0 + i] = ok[i];
+      if (HV) {
+        uint32_t pv[E];
+#pragma unroll
+        for (int i = 0; i < E; i++) pv[i] = vs[os[i] / KS];
+#pragma unroll
+        for (int i = 0; i < E; i++) vd[e0 + i] = pv[i];
+      }
+    } else {
+      int e = e0;
+      while (e < e1) {
+        const int s = ub16(sl_off_l, S + 1, e) - 1;
+        const int s0 = s >= s1 ? s1 : 0;
+        const int pend = s >= s1 ? S : s1;
+        const int g0 = s0 + (((s - s0) >> st) << st);
+        const int iM = g0 + h < pend ? g0 + h : pend;
+        const int iR = g0 + 2 * h < pend ? g0 + 2 * h : pend;
+        const int u0 = sl_off_l[g0], u1 = sl_off_l[iM], u2 = sl_off_l[iR];
+        const int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
+        int lo = diag - nR > 0 ? diag - nR : 0;
+        int cnt = (diag < nL ? diag : nL) - lo;
+        while (cnt > 0) {
+          const int half = cnt >> 1;
+          const int mid = lo + half;
+          const bool p = ks[u0 + mid] <= ks[u1 + diag - 1 - mid];
+          lo = p ? mid + 1 : lo;
+          cnt = p ? cnt - half - 1 : half;
+        }
+        const int stop = e1 < u2 ? e1 : u2;
+        if (stop <= e) break;  // cannot happen with valid tables (e < u2)
+        uint32_t pa = (uint32_t)(u0 + lo) * KS, pb = (uint32_t)(u1 + diag - lo) * KS;
+        const uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
+        O ka = *reinterpret_cast<const O *>(kb8 + pa);
+        O kb = *reinterpret_cast<const O *>(kb8 + pb);
+        for (; e < stop; e++) {
+          const bool takeL = pa < ea && (pb >= eb || ka <= kb);
+          const uint32_t src = takeL ? pa : pb;
+          kd[e] = takeL ? ka : kb;
+          if (HV) vd[e] = vs[src / KS];
+          pa += takeL ? KS : 0;
+          pb += takeL ? 0 : KS;
+          const O kn = *reinterpret_cast<const O *>(kb8 + (takeL ? pa : pb));
+          ka = takeL ? kn : ka;
+          kb = takeL ? kb : kn;
+        }
       }
     }
     lds_barrier();
