@@ -165,7 +165,7 @@ constexpr int kTileMin = 1024;
 // Co-rank sample: the order key at every kSampleStride-th position, kept
 // current by the kernels that write keys (run detection, placement, every
 // level merge).  A multiple of 64.
-constexpr uint64_t kSampleStride = 256;
+constexpr uint64_t kSampleStride = 64;
 constexpr int kTileDefault = 2048;
 constexpr int kTileDescBytes = 256;  // >= sizeof(TileDesc<8>)
 

@@ -58,81 +58,15 @@ __device__ inline bool st_less(O x, int a, O y, int b) {
 
 // ---------------------------------------------------------------- co-rank
 // Cut of a node at output rank q: c_j = number of elements of child j among
-// the first q outputs.  Windows [lo_j, hi_j] always contain c_j.  Each round
-// splits the remaining rank over the windows proportionally, checks whether
-// the split is a consistent cut (largest taken < smallest untaken in the
-// stable order) and otherwise shrinks the window of the largest taken element
-// from above and that of the smallest untaken element from below.  get(j, i)
-// is the order key of element i of list j.
-template <typename O, int K, typename Get>
-__device__ inline void corank_search(int d, uint64_t q64, uint64_t (&lo64)[K], uint64_t (&hi64)[K],
-                                     uint64_t (&cut)[K], Get get) {
-  // A node holds at most 2^31 elements, so ranks and windows fit in 32 bits.
-  uint32_t lo[K], hi[K], mm[K];
-  for (int j = 0; j < K; j++) {
-    lo[j] = (uint32_t)lo64[j];
-    hi[j] = (uint32_t)hi64[j];
-    mm[j] = 0;
-  }
-  const uint32_t q = (uint32_t)q64;
-  for (int it = 0; it < 4096; it++) {
-    uint32_t slo = 0, W = 0;
-    for (int j = 0; j < d; j++) { slo += lo[j]; W += hi[j] - lo[j]; }
-    const uint32_t rem = q - slo;
-    if (rem == 0) { for (int j = 0; j < d; j++) mm[j] = 0; break; }
-    if (rem == W) { for (int j = 0; j < d; j++) mm[j] = hi[j] - lo[j]; break; }
-    // Proportional split of rem over the windows.  The split only steers the
-    // search (any split with 0 <= mm_j <= w_j summing to rem is a valid probe),
-    // so it is computed in single precision and then corrected to sum exactly to
-    // rem.
-    const float f = (float)rem / (float)W;
-    uint32_t sm = 0;
-    for (int j = 0; j < d; j++) {
-      const uint32_t w = hi[j] - lo[j];
-      const uint32_t v = (uint32_t)((float)w * f);
-      mm[j] = v < w ? v : w;
-      sm += mm[j];
-    }
-    for (int j = 0; j < d && sm > rem; j++) {
-      const uint32_t dec = mm[j] < sm - rem ? mm[j] : sm - rem;
-      mm[j] -= dec;
-      sm -= dec;
-    }
-    for (int j = 0; j < d && sm < rem; j++) {
-      const uint32_t w = hi[j] - lo[j];
-      const uint32_t inc = w - mm[j] < rem - sm ? w - mm[j] : rem - sm;
-      mm[j] += inc;
-      sm += inc;
-    }
-    int a = -1, b = -1;
-    O xa = 0, yb = 0;
-    for (int j = 0; j < d; j++) {
-      const uint32_t w = hi[j] - lo[j];
-      if (mm[j] > 0) {
-        O x = get(j, (uint64_t)(lo[j] + mm[j] - 1));
-        if (a < 0 || !st_less(x, j, xa, a)) { xa = x; a = j; }
-      }
-      if (mm[j] < w) {
-        O y = get(j, (uint64_t)(lo[j] + mm[j]));
-        if (b < 0 || st_less(y, j, yb, b)) { yb = y; b = j; }
-      }
-    }
-    // Consistent cut: the largest taken element precedes the smallest
-    // untaken one.  Within one child positions decide, so a == b is
-    // always consistent; across children (key, child) decides.
-    if (a < 0 || b < 0 || a == b || st_less(xa, a, yb, b)) break;
-    hi[a] = lo[a] + mm[a] - 1;
-    lo[b] = lo[b] + mm[b] + 1;
-  }
-  for (int j = 0; j < d; j++) cut[j] = (uint64_t)(lo[j] + mm[j]);
-}
-
-// The same search run by a group of K lanes, lane j holding child j's window
-// (lanes j >= d hold empty windows): sums, the split correction and the
-// largest-taken / smallest-untaken choice are group reductions over shuffles,
-// so one round costs a few instructions per lane instead of a loop over the
-// children, and the probes of one round are issued by different lanes.  The
-// loop condition is uniform within a group.  Returns lane j's cut.
+// the first q outputs, found by a group of K lanes, lane j holding child j's
+// window [lo_j, hi_j], which always contains c_j.  Each round splits the
+// remaining rank over the windows proportionally and checks whether the split
+// is a consistent cut (largest taken < smallest untaken in the stable order);
+// otherwise the windows are narrowed around the split.  Lanes j >= d hold
+// empty windows.  Sums, the split correction and the largest-taken /
+// smallest-untaken choice are group reductions over shuffles, so one round
+// costs a few instructions per lane and its probes are issued by different
+// lanes.  The loop condition is uniform within a group.  Returns lane j's cut.
 template <int K>
 __device__ inline uint32_t gsum(uint32_t v) {
 #pragma unroll
@@ -190,6 +124,7 @@ __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, in
     const bool hx = mm > 0, hy = mm < w;
     O x = hx ? get(j, (uint64_t)(lo + mm - 1)) : (O)0;
     O y = hy ? get(j, (uint64_t)(lo + mm)) : (O)0;
+    const O xj = x, yj = y;
     int a = hx ? j : -1, b = hy ? j : -1;
 #pragma unroll
     for (int o = 1; o < K; o <<= 1) {
@@ -202,8 +137,14 @@ __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, in
       if (bo >= 0 && (b < 0 || st_less(yo, bo, y, b))) { y = yo; b = bo; }
     }
     if (a < 0 || b < 0 || a == b || st_less(x, a, y, b)) break;
-    if (j == a) hi = lo + mm - 1;
-    if (j == b) lo = lo + mm + 1;
+    // Inconsistent: the true cut leaves x (child a) untaken and takes y
+    // (child b), hence leaves everything after x untaken and takes everything
+    // before y.  Every lane narrows its own window with that.
+    const uint32_t at = lo + mm;
+    if (j == a) hi = at - 1;
+    else if (hy && st_less(x, a, yj, j)) hi = hi < at ? hi : at;
+    if (j == b) lo = at + 1;
+    else if (hx && st_less(xj, j, y, b)) lo = at;
   }
   return lo + mm;
 }
@@ -274,8 +215,10 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
           const uint64_t qhi = qs + d + 1 < ms ? qs + d + 1 : ms;
           const uint32_t clo = corank_group<O, K>((uint32_t)qlo, 0u,
                                                   m < qlo ? m : (uint32_t)qlo, j, gs);
-          const uint32_t chi = corank_group<O, K>((uint32_t)qhi, 0u,
-                                                  m < qhi ? m : (uint32_t)qhi, j, gs);
+          // the cut at qhi contains the one at qlo and exceeds it by qhi - qlo in total
+          const uint32_t dq = (uint32_t)(qhi - qlo);
+          const uint32_t chi = corank_group<O, K>((uint32_t)qhi, clo,
+                                                  m - clo < dq ? m : clo + dq, j, gs);
           uint64_t nlo = clo >= 1 ? off + (uint64_t)(clo - 1) * S + 1 : 0;
           uint64_t nhi = chi < m ? off + (uint64_t)chi * S : len;
           if (nhi > hi) nhi = hi;
@@ -414,13 +357,13 @@ struct SmallTab {
   int S, P, Tt, kind;
 };
 
-// LDS of the descriptor-tile kernel: two stage buffers and the small tables.
+// LDS of the descriptor-tile kernel: one stage buffer (the stages merge in
+// place through registers) and the small tables.
 template <typename O, int K, int TILE>
 struct FastSmem {
   static constexpr size_t kBuf = (size_t)(TILE + 2) * sizeof(O) + (size_t)TILE * 4;
   static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
   alignas(16) unsigned char bufA[kBuf];
-  alignas(16) unsigned char bufB[kBuf];
   SmallTab<K> tab[2];
   alignas(16) uint32_t raw[kDescWords];
   uint32_t claim[2];   // tile indices taken from the work queue
@@ -599,33 +542,56 @@ __device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, boo
   return (LOGK & 1) ? 1 : 0;
 }
 
-// The same stages for a descriptor tile (at most two pieces, 2K slices).  A
-// lane owns the E outputs [t*E, t*E+E) at every stage; the slices holding its
-// first and last output are found once per tile.  At stage st the merge unit
-// of slice s is the group of 2^st slices of its piece that contains s, and the
-// unit's bounds are read from the slice-offset table in LDS.  When all E
-// outputs lie in one unit (nearly every lane), one merge-path search and an
-// unrolled E-step merge produce them, and their payloads are gathered after
-// the keys.  Lanes whose outputs straddle a unit boundary walk unit by unit.
-// The key buffers carry one element of padding, so reading one past a unit is
-// harmless.
+// Merge-path cut of one lane: the smallest i in [lo, hi] with a[i] > b[-i],
+// where a[i] <= b[-i] holds for a prefix of [lo, hi) and hi - lo <= TILE/2.
+// Binary lifting over uniform steps: lo only moves past positions whose
+// comparison holds.  Unrolled for 8-byte keys; kept rolled for 4-byte keys,
+// whose kernels would otherwise lose a workgroup per CU to register use.
+template <typename O, int TILE>
+__device__ inline int lift_search(const O *a, const O *b, int lo, int hi) {
+  if constexpr (sizeof(O) == 8) {
+#pragma unroll
+    for (int step = TILE / 2; step > 0; step >>= 1) {
+      const int j = lo + step - 1;
+      if (j < hi && a[j] <= b[-j]) lo = j + 1;
+    }
+  } else {
+#pragma unroll 1
+    for (int step = TILE / 2; step > 0; step >>= 1) {
+      const int j = lo + step - 1;
+      if (j < hi && a[j] <= b[-j]) lo = j + 1;
+    }
+  }
+  return lo;
+}
+
+// The same stages for a descriptor tile (at most two pieces, 2K slices), in
+// place in one LDS buffer.  A lane owns the E outputs [t*E, t*E+E) at every
+// stage: it merges them into registers, and after a barrier (every read of
+// the stage done) writes them back over the stage's input.  The slices holding
+// the lane's first and last output are found once per tile.  At stage st the
+// merge unit of slice s is the group of 2^st slices of its piece that contains
+// s, and the unit's bounds are read from the slice-offset table in LDS.  When
+// all E outputs lie in one unit (nearly every lane), one merge-path search and
+// an unrolled E-step merge produce them; lanes whose outputs straddle a unit
+// boundary walk unit by unit.  The key buffer carries one element of padding,
+// so reading one past a unit is harmless.
 template <typename O, int K, int TILE, int THREADS, bool HV>
-__device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB,
-                                        const uint16_t *sl_off_l, int S, const uint16_t *pc_sl_l,
-                                        int P, int Tt, int t) {
+__device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t *sl_off_l, int S,
+                                            const uint16_t *pc_sl_l, int P, int Tt, int t) {
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
   constexpr int KS = (int)sizeof(O);
   const int s1 = P == 2 ? (int)pc_sl_l[1] : S;   // first slice of the second piece
   const int e0 = t * E;
   const int e1 = e0 + E < Tt ? e0 + E : Tt;
+  const bool full = e1 - e0 == E;
   int sa = 0, sb = 0;
   if (e0 < e1) {
     sa = ub16(sl_off_l, S + 1, e0) - 1;
     sb = ub16(sl_off_l, S + 1, e1 - 1) - 1;
   }
-  O *ks = kA, *kd = kB;
-  uint32_t *vs = vA, *vd = vB;
+  const char *kb8 = reinterpret_cast<const char *>(ks);
 #pragma unroll
   for (int st = 1; st <= LOGK; st++) {
     const int h = 1 << (st - 1);
@@ -633,29 +599,27 @@ __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB
     const int ga = pa0 + (((sa - pa0) >> st) << st);
     const int pb0 = sb >= s1 ? s1 : 0;
     const int gb = pb0 + (((sb - pb0) >> st) << st);
-    const char *kb8 = reinterpret_cast<const char *>(ks);
-    if (e0 < e1 && e1 - e0 == E && ga == gb) {
+    O ok[E];
+    uint32_t os[E];   // LDS byte offset of each output's source key
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      ok[i] = 0;
+      os[i] = 0;
+    }
+    if (full && ga == gb) {
       const int pend = sa >= s1 ? S : s1;
       const int iM = ga + h < pend ? ga + h : pend;
       const int iR = ga + 2 * h < pend ? ga + 2 * h : pend;
       const int u0 = sl_off_l[ga], u1 = sl_off_l[iM], u2 = sl_off_l[iR];
       const int nL = u1 - u0, nR = u2 - u1, diag = e0 - u0;
       int lo = diag - nR > 0 ? diag - nR : 0;
-      int cnt = (diag < nL ? diag : nL) - lo;
-      // smallest i in [lo, lo+cnt] with ks[u0+i] > ks[u1+diag-1-i]
-      while (cnt > 0) {
-        const int half = cnt >> 1;
-        const int mid = lo + half;
-        const bool p = ks[u0 + mid] <= ks[u1 + diag - 1 - mid];
-        lo = p ? mid + 1 : lo;
-        cnt = p ? cnt - half - 1 : half;
-      }
+      const int hi = diag < nL ? diag : nL;
+      // smallest i in [lo, hi] with ks[u0+i] > ks[u1+diag-1-i]
+      lo = lift_search<O, TILE>(ks + u0, ks + u1 + diag - 1, lo, hi);
       uint32_t pa = (uint32_t)(u0 + lo) * KS, pb = (uint32_t)(u1 + diag - lo) * KS;
       const uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
       O ka = *reinterpret_cast<const O *>(kb8 + pa);
       O kb = *reinterpret_cast<const O *>(kb8 + pb);
-      O ok[E];
-      uint32_t os[E];
 #pragma unroll
       for (int i = 0; i < E; i++) {
         const bool takeL = pa < ea && (pb >= eb || ka <= kb);
@@ -669,16 +633,7 @@ __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB
           kb = takeL ? kb : kn;
         }
       }
-#pragma unroll
-      for (int i = 0; i < E; i++) kd[e0 + i] = ok[i];
-      if (HV) {
-        uint32_t pv[E];
-#pragma unroll
-        for (int i = 0; i < E; i++) pv[i] = vs[os[i] / KS];
-#pragma unroll
-        for (int i = 0; i < E; i++) vd[e0 + i] = pv[i];
-      }
-    } else {
+    } else if (e0 < e1) {
       int e = e0;
       while (e < e1) {
         const int s = ub16(sl_off_l, S + 1, e) - 1;
@@ -706,9 +661,14 @@ __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB
         O kb = *reinterpret_cast<const O *>(kb8 + pb);
         for (; e < stop; e++) {
           const bool takeL = pa < ea && (pb >= eb || ka <= kb);
+          const O kv = takeL ? ka : kb;
           const uint32_t src = takeL ? pa : pb;
-          kd[e] = takeL ? ka : kb;
-          if (HV) vd[e] = vs[src / KS];
+          const int q = e - e0;
+#pragma unroll
+          for (int i = 0; i < E; i++) {
+            ok[i] = i == q ? kv : ok[i];
+            os[i] = i == q ? src : os[i];
+          }
           pa += takeL ? KS : 0;
           pb += takeL ? 0 : KS;
           const O kn = *reinterpret_cast<const O *>(kb8 + (takeL ? pa : pb));
@@ -717,11 +677,30 @@ __device__ inline int merge_stages_fast(O *kA, uint32_t *vA, O *kB, uint32_t *vB
         }
       }
     }
+    uint32_t pv[E];
+    if (HV) {
+#pragma unroll
+      for (int i = 0; i < E; i++) pv[i] = vs[os[i] / KS];
+    }
+    lds_barrier();   // every read of this stage is done
+    if (full) {
+#pragma unroll
+      for (int i = 0; i < E; i++) ks[e0 + i] = ok[i];
+      if (HV) {
+#pragma unroll
+        for (int i = 0; i < E; i++) vs[e0 + i] = pv[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; i++) {
+        if (e0 + i < e1) {
+          ks[e0 + i] = ok[i];
+          if (HV) vs[e0 + i] = pv[i];
+        }
+      }
+    }
     lds_barrier();
-    O *tk = ks; ks = kd; kd = tk;
-    uint32_t *tv = vs; vs = vd; vd = tv;
   }
-  return (LOGK & 1) ? 1 : 0;
 }
 
 // Coalesced stores of a merged tile; outputs at multiples of kSampleStride also
@@ -736,6 +715,27 @@ __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
     if (e < Tt) {
       int p = P == 1 ? 0 : ub16(pc_loff, P + 1, e) - 1;
       uint64_t g = pc_out[p] + (uint64_t)(e - pc_loff[p]);
+      out_keys[g] = Kt::unord(ks[e]);
+      if (has_vals) out_vals[g] = vs[e];
+      if ((g & (kSampleStride - 1)) == 0) smp[g / kSampleStride] = (uint64_t)ks[e];
+    }
+  }
+}
+
+// store_tile for a descriptor tile (one or two pieces): the output index of
+// position e is base0 + e before the second piece and base1 + e from it on.
+template <typename Kt, typename O, int E, int THREADS>
+__device__ inline void store_tile2(const O *ks, const uint32_t *vs, O *out_keys,
+                                   uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
+                                   const uint64_t *pc_out, int P, int Tt, int t, uint64_t *smp) {
+  const int split = P == 2 ? (int)pc_loff[1] : Tt;
+  const uint64_t base0 = pc_out[0] - (uint64_t)pc_loff[0];
+  const uint64_t base1 = P == 2 ? pc_out[1] - (uint64_t)pc_loff[1] : base0;
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    int e = t + i * THREADS;
+    if (e < Tt) {
+      uint64_t g = (e < split ? base0 : base1) + (uint64_t)e;
       out_keys[g] = Kt::unord(ks[e]);
       if (has_vals) out_vals[g] = vs[e];
       if ((g & (kSampleStride - 1)) == 0) smp[g / kSampleStride] = (uint64_t)ks[e];
@@ -769,8 +769,6 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
   uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)(TILE + 2) * sizeof(O));
-  O *kB = reinterpret_cast<O *>(sm.bufB);
-  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)(TILE + 2) * sizeof(O));
   const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
 
   const uint64_t tiles = plan->lvl_tiles[level];
@@ -832,9 +830,8 @@ __global__ __launch_bounds__(THREADS) void k_merge_fast(
       issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
     }
     if (kind == kTabFast) {
-      int res = merge_stages_fast<O, K, TILE, THREADS, HV>(kA, vA, kB, vB, T.sl_off, T.S,
-                                                           T.pc_sl, T.P, T.Tt, t);
-      store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
+      merge_stages_inplace<O, K, TILE, THREADS, HV>(kA, vA, T.sl_off, T.S, T.pc_sl, T.P, T.Tt, t);
+      store_tile2<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV,
                                     T.pc_loff, T.pc_out, T.P, T.Tt, t, smp);
     } else if (kind == kTabBad) {
       if (t == 0) atomicOr(&plan->error, 32u);
