@@ -19,7 +19,6 @@ namespace mps {
 constexpr int kPlaceThreads = 256;
 constexpr int kPlaceE = 8;                                   // positions per thread
 constexpr uint64_t kPlaceBlock = (uint64_t)kPlaceThreads * kPlaceE;
-constexpr int kPlaceRuns = 512;                              // run table entries staged in LDS
 
 __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, uint64_t e) {
   // last j in [lo, hi] with rs[j] <= e
@@ -30,26 +29,107 @@ __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, 
   return lo;
 }
 
-// Same, for an answer expected close to lo (rs[lo] <= e): exponential steps
-// from lo, then a binary search inside the last step.
-__device__ inline uint64_t run_near(const uint64_t *rs, uint64_t lo, uint64_t hi, uint64_t e) {
-  uint64_t step = 1;
-  while (lo + step <= hi && rs[lo + step] <= e) {
-    lo += step;
-    step <<= 1;
+// Positions of a block that is not one ascending run: each finds its run (in
+// the staged table, else in the global one) and acts on it, in two halves of
+// kPlaceE/2 positions per thread.
+template <int KT>
+__device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
+                                           uint32_t *__restrict__ vals,
+                                           typename Key<KT>::U *__restrict__ akeys,
+                                           uint32_t *__restrict__ avals,
+                                           const uint64_t *__restrict__ rs,
+                                           const uint8_t *__restrict__ desc,
+                                           const uint8_t *__restrict__ leaf_depth, uint64_t r,
+                                           uint64_t *__restrict__ smp, const uint64_t *sRs,
+                                           const uint8_t *sFl, int nr, bool staged, uint64_t jc,
+                                           uint64_t bs, uint64_t be, int t) {
+  using U = typename Key<KT>::U;
+  constexpr uint64_t SM = kSampleStride - 1;
+  constexpr int T = kPlaceThreads;
+  constexpr int HE = kPlaceE / 2;
+#pragma unroll 1
+  for (int h = 0; h < 2; h++) {
+    uint64_t dst[HE];
+    int act[HE];
+#pragma unroll
+    for (int i = 0; i < HE; i++) {
+      const uint64_t e = bs + t + (uint64_t)(h * HE + i) * T;
+      act[i] = 0;
+      dst[i] = e;
+      if (e < be) {
+        uint64_t s, f;
+        int fl;
+        if (staged) {
+          int lo = 0, hi = nr - 1;   // last staged run with start <= e
+          while (hi > lo) {
+            int mid = (lo + hi + 1) >> 1;
+            if (sRs[mid] <= e) lo = mid; else hi = mid - 1;
+          }
+          s = sRs[lo];
+          f = sRs[lo + 1];
+          fl = sFl[lo];
+        } else {
+          const uint64_t j = run_of(rs, jc, r - 1, e);
+          s = rs[j];
+          f = rs[j + 1];
+          fl = (leaf_depth[j] & 1) | (desc[j] ? 2 : 0);
+        }
+        if (fl & 1) {
+          act[i] = 1;
+          dst[i] = (fl & 2) ? s + f - 1 - e : e;
+        } else if ((fl & 2) && e - s < (f - s) / 2) {
+          act[i] = 2;
+          dst[i] = s + f - 1 - e;
+        }
+      }
+    }
+    U ka[HE], kb[HE];
+    uint32_t va[HE], vb[HE];
+#pragma unroll
+    for (int i = 0; i < HE; i++) {
+      const uint64_t e = bs + t + (uint64_t)(h * HE + i) * T;
+      if (act[i]) {
+        ka[i] = keys[e];
+        if (vals) va[i] = vals[e];
+      }
+      if (act[i] == 2) {
+        kb[i] = keys[dst[i]];
+        if (vals) vb[i] = vals[dst[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < HE; i++) {
+      const uint64_t e = bs + t + (uint64_t)(h * HE + i) * T;
+      // a key that lands on a new position refreshes that position's co-rank sample
+      if (act[i] == 1) {
+        akeys[dst[i]] = ka[i];
+        if (vals) avals[dst[i]] = va[i];
+        if (dst[i] != e && (dst[i] & SM) == 0) smp[dst[i] / kSampleStride] = Key<KT>::ord(ka[i]);
+      } else if (act[i] == 2) {
+        keys[e] = kb[i];
+        keys[dst[i]] = ka[i];
+        if (vals) {
+          vals[e] = vb[i];
+          vals[dst[i]] = va[i];
+        }
+        if ((e & SM) == 0) smp[e / kSampleStride] = Key<KT>::ord(kb[i]);
+        if ((dst[i] & SM) == 0) smp[dst[i] / kSampleStride] = Key<KT>::ord(ka[i]);
+      }
+    }
   }
-  return run_of(rs, lo, lo + step - 1 < hi ? lo + step - 1 : hi, e);
 }
 
-// Each workgroup takes a contiguous range of blocks of kPlaceBlock positions,
-// so the runs of one block are found by a short search onward from the
-// previous block's.  The runs overlapping it
-// are staged in LDS (start and a flag byte: bit 0 odd depth, bit 1 descending)
-// unless there are too many; then every position finds its run and what to do
-// with it, all loads are issued, then all stores.  Odd-depth leaves are copied
-// to the other buffer (reversed if descending); even-depth descending runs are
-// reversed in place by the threads of their first half, each swapping with
-// its mirror position.
+// Each workgroup takes a contiguous range of blocks of kPlaceBlock positions.
+// For every block the threads stage, in one round of loads, the starts and
+// flags (bit 0 odd depth, bit 1 descending) of the kPlaceThreads runs from the
+// one holding the block's first position; barrier counts over that table give
+// the runs overlapping the block and the run holding the next block's first
+// position.  A block inside one ascending run is copied to the other buffer
+// (odd depth) or left alone (even depth).  Otherwise every position finds its
+// run and what to do with it: odd-depth leaves are copied to the other buffer
+// (reversed if descending); even-depth descending runs are reversed in place
+// by the threads of their first half, each swapping with its mirror position.
+// A block overlapping more runs than staged finds them in the global table.
 template <int KT>
 __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__restrict__ keys,
                                                          uint32_t *__restrict__ vals,
@@ -62,109 +142,71 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
                                                          uint64_t *__restrict__ smp) {
   using U = typename Key<KT>::U;
   constexpr uint64_t SM = kSampleStride - 1;
-  __shared__ uint64_t sRs[kPlaceRuns + 1];
-  __shared__ uint8_t sFl[kPlaceRuns];
-  __shared__ uint64_t sJ[2];
+  constexpr int T = kPlaceThreads;
+  __shared__ uint64_t sRs[T + 1];
+  __shared__ uint8_t sFl[T];
+  __shared__ uint64_t sJ;
   const uint64_t r = plan->r;
   const int t = threadIdx.x;
   const uint64_t nblk = (N + kPlaceBlock - 1) / kPlaceBlock;
   const uint64_t per = (nblk + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * per;
   const uint64_t b1 = b0 + per < nblk ? b0 + per : nblk;
-  uint64_t jc = 0;   // thread 0: run containing the current block's first position
-  if (t == 0 && b0 < b1) jc = run_of(rs, 0, r - 1, b0 * kPlaceBlock);
+  if (b0 >= b1 || r == 0) return;   // uniform in the workgroup
+  if (t == 0) sJ = run_of(rs, 0, r - 1, b0 * kPlaceBlock);
+  __syncthreads();
+  uint64_t jc = sJ;   // run holding the current block's first position
   for (uint64_t b = b0; b < b1; b++) {
     const uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
-    if (t == 0) {
-      const uint64_t j1 = run_near(rs, jc, r - 1, be - 1);
-      sJ[0] = jc;
-      sJ[1] = j1;
-      if (be < N) jc = run_near(rs, j1, r - 1, be);
+    {
+      const uint64_t i = jc + (uint64_t)t;
+      sRs[t] = i <= r ? rs[i] : ~0ull;   // rs[r] = N
+      sFl[t] = i < r ? (uint8_t)((leaf_depth[i] & 1) | (desc[i] ? 2 : 0)) : (uint8_t)0;
+      if (t == 0) sRs[T] = jc + T <= r ? rs[jc + T] : ~0ull;
     }
-    __syncthreads();
-    const uint64_t j0 = sJ[0], j1 = sJ[1];
-    const int nr = (int)(j1 - j0 + 1);
-    const bool staged = nr <= kPlaceRuns;
-    int any = 0;
+    // runs overlapping [bs, be): jc .. jc+nr-1 (sRs[0] <= bs, so nr >= 1)
+    // the values that choose the path are uniform; readfirstlane lets the
+    // compiler branch on them as such
+    const int nr = __builtin_amdgcn_readfirstlane(__syncthreads_count(sRs[t] < be));
+    const bool staged = __builtin_amdgcn_readfirstlane(nr < T || sRs[T] >= be ? 1 : 0) != 0;
+    uint64_t jn = jc;
     if (staged) {
-      for (int i = t; i <= nr; i += kPlaceThreads) sRs[i] = rs[j0 + i];
-      for (int i = t; i < nr; i += kPlaceThreads) {
-        uint8_t f = (uint8_t)((leaf_depth[j0 + i] & 1) | (desc[j0 + i] ? 2 : 0));
-        sFl[i] = f;
-        any |= f;
-      }
+      jn = jc + (uint64_t)(nr - 1) + (sRs[nr] == be ? 1u : 0u);
+    } else {
+      if (t == 0) sJ = run_of(rs, jc, r - 1, be < N ? be : N - 1);
+      __syncthreads();
+      jn = sJ;
     }
-    any = __syncthreads_or(any) || !staged;
-    if (any) {
-      uint64_t dst[kPlaceE];
-      int act[kPlaceE];
+    const int fl0 = __builtin_amdgcn_readfirstlane((int)sFl[0]);
+    if (staged && nr == 1 && fl0 == 1) {
+      // one odd-depth ascending run: straight copy to the other buffer
+      const int lim = (int)(be - bs);
+      const U *ks = keys + bs;
+      U *kd = akeys + bs;
+      U kv[kPlaceE];
+      uint32_t vv[kPlaceE];
 #pragma unroll
       for (int i = 0; i < kPlaceE; i++) {
-        const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
-        act[i] = 0;
-        dst[i] = e;
-        if (e < be) {
-          uint64_t s, f;
-          int fl;
-          if (staged) {
-            int lo = 0, hi = nr - 1;   // last run with start <= e
-            while (hi > lo) {
-              int mid = (lo + hi + 1) >> 1;
-              if (sRs[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            s = sRs[lo];
-            f = sRs[lo + 1];
-            fl = sFl[lo];
-          } else {
-            uint64_t j = run_of(rs, j0, j1, e);
-            s = rs[j];
-            f = rs[j + 1];
-            fl = (leaf_depth[j] & 1) | (desc[j] ? 2 : 0);
-          }
-          if (fl & 1) {
-            act[i] = 1;
-            dst[i] = (fl & 2) ? s + f - 1 - e : e;
-          } else if ((fl & 2) && e - s < (f - s) / 2) {
-            act[i] = 2;
-            dst[i] = s + f - 1 - e;
-          }
-        }
-      }
-      U ka[kPlaceE], kb[kPlaceE];
-      uint32_t va[kPlaceE], vb[kPlaceE];
-#pragma unroll
-      for (int i = 0; i < kPlaceE; i++) {
-        const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
-        if (act[i]) {
-          ka[i] = keys[e];
-          if (vals) va[i] = vals[e];
-        }
-        if (act[i] == 2) {
-          kb[i] = keys[dst[i]];
-          if (vals) vb[i] = vals[dst[i]];
+        const int o = t + i * T;
+        if (o < lim) {
+          kv[i] = ks[o];
+          if (vals) vv[i] = vals[bs + o];
         }
       }
 #pragma unroll
       for (int i = 0; i < kPlaceE; i++) {
-        const uint64_t e = bs + t + (uint64_t)i * kPlaceThreads;
-        // a key that lands on a new position refreshes that position's co-rank sample
-        if (act[i] == 1) {
-          akeys[dst[i]] = ka[i];
-          if (vals) avals[dst[i]] = va[i];
-          if (dst[i] != e && (dst[i] & SM) == 0) smp[dst[i] / kSampleStride] = Key<KT>::ord(ka[i]);
-        } else if (act[i] == 2) {
-          keys[e] = kb[i];
-          keys[dst[i]] = ka[i];
-          if (vals) {
-            vals[e] = vb[i];
-            vals[dst[i]] = va[i];
-          }
-          if ((e & SM) == 0) smp[e / kSampleStride] = Key<KT>::ord(kb[i]);
-          if ((dst[i] & SM) == 0) smp[dst[i] / kSampleStride] = Key<KT>::ord(ka[i]);
+        const int o = t + i * T;
+        if (o < lim) {
+          kd[o] = kv[i];
+          if (vals) avals[bs + o] = vv[i];
         }
       }
+    } else if (!(staged && nr == 1 && fl0 == 0)) {
+place_general<KT>(keys, vals, akeys, avals, rs, desc, leaf_depth, r, smp, sRs, sFl, nr, staged, jc,
+                        bs, be, t);
     }
-    __syncthreads();
+    jc = jn;
+    __syncthreads();   // the run table is restaged for the next block
   }
 }
 
