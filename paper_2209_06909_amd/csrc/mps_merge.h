@@ -572,9 +572,10 @@ __device__ inline int lift_search(const O *a, const O *b, int lo, int hi) {
 // the lane's first and last output are found once per tile.  At stage st the
 // merge unit of slice s is the group of 2^st slices of its piece that contains
 // s, and the unit's bounds are read from the slice-offset table in LDS.  When
-// all E outputs lie in one unit (nearly every lane), one merge-path search and
-// an unrolled E-step merge produce them; lanes whose outputs straddle a unit
-// boundary walk unit by unit.  The key buffer carries one element of padding,
+// all E outputs lie in one unit, or run from one unit into the next, one
+// merge-path search (in the first unit; the next one starts at diagonal 0) and
+// an unrolled E-step merge produce them.  Lanes spanning more units (only when
+// a unit is shorter than E) walk unit by unit.  The key buffer carries one element of padding,
 // so reading one past a unit is harmless.
 template <typename O, int K, int TILE, int THREADS, bool HV>
 __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t *sl_off_l, int S,
@@ -606,22 +607,40 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
       ok[i] = 0;
       os[i] = 0;
     }
-    if (full && ga == gb) {
-      const int pend = sa >= s1 ? S : s1;
-      const int iM = ga + h < pend ? ga + h : pend;
-      const int iR = ga + 2 * h < pend ? ga + 2 * h : pend;
-      const int u0 = sl_off_l[ga], u1 = sl_off_l[iM], u2 = sl_off_l[iR];
+    // unit A holds the lane's first output; a lane whose outputs run on into
+    // the next unit B (it starts where A ends) takes the same path, switching
+    // to B's start mid-merge
+    const int pendA = sa >= s1 ? S : s1;
+    const int iMA = ga + h < pendA ? ga + h : pendA;
+    const int iRA = ga + 2 * h < pendA ? ga + 2 * h : pendA;
+    const int u0 = sl_off_l[ga], u1 = sl_off_l[iMA], u2 = sl_off_l[iRA];
+    const bool two = full && ga != gb && (int)sl_off_l[gb] == u2;
+    if (full && (ga == gb || two)) {
       const int nL = u1 - u0, nR = u2 - u1, diag = e0 - u0;
       int lo = diag - nR > 0 ? diag - nR : 0;
       const int hi = diag < nL ? diag : nL;
       // smallest i in [lo, hi] with ks[u0+i] > ks[u1+diag-1-i]
       lo = lift_search<O, TILE>(ks + u0, ks + u1 + diag - 1, lo, hi);
       uint32_t pa = (uint32_t)(u0 + lo) * KS, pb = (uint32_t)(u1 + diag - lo) * KS;
-      const uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
+      uint32_t ea = (uint32_t)u1 * KS, eb = (uint32_t)u2 * KS;
       O ka = *reinterpret_cast<const O *>(kb8 + pa);
       O kb = *reinterpret_cast<const O *>(kb8 + pb);
+      // B starts at output u2 - e0 (1..E-1) of the lane; it begins at
+      // diagonal 0, so its heads are the first elements of its two halves
+      const int swi = two ? u2 - e0 : E;
 #pragma unroll
       for (int i = 0; i < E; i++) {
+        if (i > 0 && i == swi) {
+          const int pendB = sb >= s1 ? S : s1;
+          const int iMB = gb + h < pendB ? gb + h : pendB;
+          const int iRB = gb + 2 * h < pendB ? gb + 2 * h : pendB;
+          pa = (uint32_t)u2 * KS;
+          pb = (uint32_t)sl_off_l[iMB] * KS;
+          ea = pb;
+          eb = (uint32_t)sl_off_l[iRB] * KS;
+          ka = *reinterpret_cast<const O *>(kb8 + pa);
+          kb = *reinterpret_cast<const O *>(kb8 + pb);
+        }
         const bool takeL = pa < ea && (pb >= eb || ka <= kb);
         ok[i] = takeL ? ka : kb;
         os[i] = takeL ? pa : pb;
@@ -754,7 +773,10 @@ constexpr int kFastClaim = 8;
 // tile i+2 and the input slices of tile i+1 are already being fetched into
 // registers, so global latency overlaps the LDS work.
 template <int KT, int K, int TILE, int THREADS, bool HV>
-__global__ __launch_bounds__(THREADS) void k_merge_fast(
+// With 4-byte keys, k <= 4 and 4 outputs per lane the kernel fits in 64
+// registers, which lets 4 workgroups of 512 threads share a CU.
+__global__ __launch_bounds__(THREADS, (sizeof(typename Key<KT>::U) == 4 && K <= 4 && TILE == 4 * THREADS) ? 8 : 1)
+void k_merge_fast(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
     Plan *__restrict__ plan, int level, const TileDesc<K> *__restrict__ desc,
