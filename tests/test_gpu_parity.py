@@ -133,6 +133,10 @@ EDGE = {
     "two_runs": np.concatenate([np.arange(3000), np.arange(3000)]).astype(np.int32),
     "one_big_one_small": np.concatenate([np.arange(100000), [5, 4]]).astype(np.int32),
     "tile_edge": np.concatenate([np.arange(2048), np.arange(2048), np.arange(1)]).astype(np.int32),
+    # runs of 8, shifted so a 2048-position block overlaps 257 of them: the
+    # placement's staged run table (256 entries) just overflows
+    "runs8_up": np.concatenate([np.arange(4), np.tile(np.arange(8), 1000)]).astype(np.int32),
+    "runs8_down": np.concatenate([np.arange(4)[::-1], np.tile(np.arange(8)[::-1], 1000)]).astype(np.int32),
 }
 
 
