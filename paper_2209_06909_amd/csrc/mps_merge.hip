@@ -29,20 +29,16 @@ __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, 
   return lo;
 }
 
-// Positions of a block that is not one ascending run: each finds its run (in
-// the staged table, else in the global one) and acts on it, in two halves of
-// kPlaceE/2 positions per thread.
+// Positions of a block that is not one ascending run: each finds its run in
+// the staged table and acts on it, in two halves of kPlaceE/2 positions per
+// thread.
 template <int KT>
 __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
-                                           uint32_t *__restrict__ vals,
-                                           typename Key<KT>::U *__restrict__ akeys,
-                                           uint32_t *__restrict__ avals,
-                                           const uint64_t *__restrict__ rs,
-                                           const uint8_t *__restrict__ desc,
-                                           const uint8_t *__restrict__ leaf_depth, uint64_t r,
-                                           uint64_t *__restrict__ smp, const uint64_t *sRs,
-                                           const uint8_t *sFl, int nr, bool staged, uint64_t jc,
-                                           uint64_t bs, uint64_t be, int t) {
+                                     uint32_t *__restrict__ vals,
+                                     typename Key<KT>::U *__restrict__ akeys,
+                                     uint32_t *__restrict__ avals, uint64_t *__restrict__ smp,
+                                     const uint64_t *sRs, const uint8_t *sFl, int nr, uint64_t bs,
+                                     uint64_t be, int t) {
   using U = typename Key<KT>::U;
   constexpr uint64_t SM = kSampleStride - 1;
   constexpr int T = kPlaceThreads;
@@ -57,23 +53,13 @@ __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
       act[i] = 0;
       dst[i] = e;
       if (e < be) {
-        uint64_t s, f;
-        int fl;
-        if (staged) {
-          int lo = 0, hi = nr - 1;   // last staged run with start <= e
-          while (hi > lo) {
-            int mid = (lo + hi + 1) >> 1;
-            if (sRs[mid] <= e) lo = mid; else hi = mid - 1;
-          }
-          s = sRs[lo];
-          f = sRs[lo + 1];
-          fl = sFl[lo];
-        } else {
-          const uint64_t j = run_of(rs, jc, r - 1, e);
-          s = rs[j];
-          f = rs[j + 1];
-          fl = (leaf_depth[j] & 1) | (desc[j] ? 2 : 0);
+        int lo = 0, hi = nr - 1;   // last staged run with start <= e
+        while (hi > lo) {
+          int mid = (lo + hi + 1) >> 1;
+          if (sRs[mid] <= e) lo = mid; else hi = mid - 1;
         }
+        const uint64_t s = sRs[lo], f = sRs[lo + 1];
+        const int fl = sFl[lo];
         if (fl & 1) {
           act[i] = 1;
           dst[i] = (fl & 2) ? s + f - 1 - e : e;
@@ -129,7 +115,8 @@ __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
 // run and what to do with it: odd-depth leaves are copied to the other buffer
 // (reversed if descending); even-depth descending runs are reversed in place
 // by the threads of their first half, each swapping with its mirror position.
-// A block overlapping more runs than staged finds them in the global table.
+// A block overlapping more than kPlaceThreads runs stages all of them (at most
+// one per position) in a second round.
 template <int KT>
 __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__restrict__ keys,
                                                          uint32_t *__restrict__ vals,
@@ -143,8 +130,10 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
   using U = typename Key<KT>::U;
   constexpr uint64_t SM = kSampleStride - 1;
   constexpr int T = kPlaceThreads;
-  __shared__ uint64_t sRs[T + 1];
-  __shared__ uint8_t sFl[T];
+  // starts and flags of the runs overlapping a block: at most kPlaceBlock
+  // (the run holding the first position, then at most one new run per position)
+  __shared__ uint64_t sRs[kPlaceBlock + 1];
+  __shared__ uint8_t sFl[kPlaceBlock];
   __shared__ uint64_t sJ;
   const uint64_t r = plan->r;
   const int t = threadIdx.x;
@@ -167,18 +156,27 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
     // runs overlapping [bs, be): jc .. jc+nr-1 (sRs[0] <= bs, so nr >= 1)
     // the values that choose the path are uniform; readfirstlane lets the
     // compiler branch on them as such
-    const int nr = __builtin_amdgcn_readfirstlane(__syncthreads_count(sRs[t] < be));
-    const bool staged = __builtin_amdgcn_readfirstlane(nr < T || sRs[T] >= be ? 1 : 0) != 0;
-    uint64_t jn = jc;
-    if (staged) {
-      jn = jc + (uint64_t)(nr - 1) + (sRs[nr] == be ? 1u : 0u);
-    } else {
-      if (t == 0) sJ = run_of(rs, jc, r - 1, be < N ? be : N - 1);
+    int nr = __builtin_amdgcn_readfirstlane(__syncthreads_count(sRs[t] < be));
+    if (__builtin_amdgcn_readfirstlane(nr == T && sRs[T] < be ? 1 : 0)) {
+      // more than T runs overlap the block: stage the rest of them too
+      for (int x = T + 1 + t; x <= (int)kPlaceBlock; x += T) {
+        const uint64_t i = jc + (uint64_t)x;
+        sRs[x] = i <= r ? rs[i] : ~0ull;
+        if (x < (int)kPlaceBlock)
+          sFl[x] = i < r ? (uint8_t)((leaf_depth[i] & 1) | (desc[i] ? 2 : 0)) : (uint8_t)0;
+      }
+      if (t == 0) sFl[T] = jc + T < r ? (uint8_t)((leaf_depth[jc + T] & 1) | (desc[jc + T] ? 2 : 0)) : (uint8_t)0;
       __syncthreads();
-      jn = sJ;
+      int lo = T, hi = (int)kPlaceBlock;   // first staged start >= be (sRs[kPlaceBlock] >= be)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sRs[mid] < be) lo = mid + 1; else hi = mid;
+      }
+      nr = __builtin_amdgcn_readfirstlane(lo);
     }
+    const uint64_t jn = jc + (uint64_t)(nr - 1) + (sRs[nr] == be ? 1u : 0u);
     const int fl0 = __builtin_amdgcn_readfirstlane((int)sFl[0]);
-    if (staged && nr == 1 && fl0 == 1) {
+    if (nr == 1 && fl0 == 1) {
       // one odd-depth ascending run: straight copy to the other buffer
       const int lim = (int)(be - bs);
       const U *ks = keys + bs;
@@ -201,9 +199,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
           if (vals) avals[bs + o] = vv[i];
         }
       }
-    } else if (!(staged && nr == 1 && fl0 == 0)) {
-place_general<KT>(keys, vals, akeys, avals, rs, desc, leaf_depth, r, smp, sRs, sFl, nr, staged, jc,
-                        bs, be, t);
+    } else if (!(nr == 1 && fl0 == 0)) {
+      place_general<KT>(keys, vals, akeys, avals, smp, sRs, sFl, nr, bs, be, t);
     }
     jc = jn;
     __syncthreads();   // the run table is restaged for the next block
