@@ -184,6 +184,29 @@ def bench_batched(args, torch, mps, workloads):
     }
 
 
+def bench_perm(args, torch, mps, workloads, tcfg):
+    """The second variant of the headline size: a uniform random permutation of
+    n int64 keys (no presortedness), index payload, same arity and tile."""
+    n = 1 << args.log2n
+    log(f"perm variant: generating a random permutation of 2^{args.log2n}")
+    kh, ph = workloads.perm_i64(n=n)
+    keys0 = torch.from_numpy(kh).cuda()
+    pay0 = torch.from_numpy(ph.view(np.int32)).cuda()
+    del kh, ph
+    keys, pay = keys0.clone(), pay0.clone()
+    tr = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, **tcfg)
+    ms, all_ms = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
+                            lambda: mps.sort(keys, pay, k=args.k, **tcfg))
+    del keys0, pay0, keys, pay
+    mps.release_workspaces()
+    torch.cuda.empty_cache()
+    return {"workload": f"perm_i64: uniform random permutation of 0..n-1 as int64 keys, n=2^{args.log2n}, "
+                        "uint32 index payload (seed 3)",
+            "ms": round(ms, 3), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 3),
+            "runs": int(tr.r), "tree_levels": int(tr.n_levels),
+            "merge_cost_per_key": round(tr.merge_cost / n, 4)}
+
+
 def bench_serving(args, torch, mps, workloads):
     """Serving: a pool of float32 requests (sizes log-uniform in [2^10, 2^26], random runs,
     ~1% duplicate keys, index payload) resident on the GPU.  (1) Closed loop: every pool
@@ -303,6 +326,7 @@ def main():
     ap.add_argument("--cpu-sample-log2n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-k-sweep", action="store_true")
+    ap.add_argument("--no-perm", action="store_true", help="skip the random-permutation variant")
     ap.add_argument("--batched-m", type=int, default=8192, help="arrays in the batched workload")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
@@ -471,6 +495,8 @@ def main():
             "merge_cost_workload": "n=10^8 int32, random runs of mean length 10^4 (Table 1)",
             "this_gpu": {"time_ratio_k4_over_k2": round(t4 / t2, 4),
                          "merge_cost_ratio_k4_over_k2": round(m4 / m2, 4)}}
+    if not args.no_perm:
+        out["perm_variant"] = bench_perm(args, torch, mps, workloads, tcfg)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(keys_h, pay_h, 1 << args.cpu_sample_log2n, args.k)
