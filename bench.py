@@ -68,12 +68,23 @@ def cpu_baseline(keys: np.ndarray, pay: np.ndarray, sample_n: int, k: int):
     import oracle
     sk, sp = keys[:sample_n].copy(), pay[:sample_n].copy()
     t0 = time.perf_counter()
-    oracle.sort(sk, sp, k=k)
+    ok_, op_, _ = oracle.sort(sk, sp, k=k)
     dt = time.perf_counter() - t0
+    # a library reference on the same sample: numpy's stable sort (a run-adaptive
+    # mergesort for 64-bit keys), one thread, keys and payload permuted together
+    rk, rp = keys[:sample_n].copy(), pay[:sample_n].copy()
+    t0 = time.perf_counter()
+    order = np.argsort(rk, kind="stable")
+    rk, rp = rk[order], rp[order]
+    dr = time.perf_counter() - t0
+    if not (np.array_equal(rk, ok_) and np.array_equal(rp, op_)):
+        raise RuntimeError("library stable sort and oracle disagree on the CPU sample")
     return {"value": round(sample_n / dt / 1e9, 6), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample_n} keys (2^{int(np.log2(sample_n))}) of the same runs_i64 input, "
                       f"single-threaded C oracle, {dt:.2f} s",
-            "host_cpu": host_cpu()}
+            "host_cpu": host_cpu(),
+            "library_reference": {"what": "numpy.argsort(kind='stable') + gather, one thread",
+                                  "value": round(sample_n / dr / 1e9, 6), "seconds": round(dr, 2)}}
 
 
 def host_cpu() -> str:
