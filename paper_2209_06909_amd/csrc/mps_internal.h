@@ -55,6 +55,7 @@ struct Plan {
   uint32_t gen_cnt[kMaxLevels];      // tiles per level that need the general merge path
   uint32_t q_fast[kMaxLevels];       // work-queue heads of the two merge kernels, per level
   uint32_t q_gen[kMaxLevels];
+  uint32_t jump_more[8];             // pointer-jumping round i left a target that is not a root
 };
 
 // Run-detection block aggregate (16384 positions per block).

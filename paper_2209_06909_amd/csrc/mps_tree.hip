@@ -276,22 +276,36 @@ __device__ inline bool is_leader(const uint8_t *P, const uint32_t *Le, uint32_t 
   return p > 0 && P[Le[i]] < p;
 }
 
+// One pointer-jumping round over the node leaders: the jump target moves to
+// the target's target and the distance adds up.  Roots point to themselves
+// with distance 0, so once every target is a root further rounds change
+// nothing; a round that finds this recorded by its predecessor only copies.
 __global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ P,
                                               const uint32_t *__restrict__ Le,
-                                              const Plan *__restrict__ plan,
+                                              Plan *__restrict__ plan, int round,
                                               const uint32_t *__restrict__ jin,
                                               const uint8_t *__restrict__ din,
                                               uint32_t *__restrict__ jout,
                                               uint8_t *__restrict__ dout) {
   const uint64_t r = plan->r;
+  const bool copy = round > 0 && plan->jump_more[round - 1] == 0;
+  bool more = false;
   for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
        ii += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t i = (uint32_t)ii;
+    if (copy) {
+      jout[i] = jin[i];
+      dout[i] = din[i];
+      continue;
+    }
     if (!is_leader(P, Le, i)) continue;
     uint32_t j = jin[i];
     dout[i] = din[i] + din[j];
-    jout[i] = jin[j];
+    const uint32_t j2 = jin[j];
+    jout[i] = j2;
+    more = more || jin[j2] != j2;
   }
+  if (__syncthreads_or(more) && threadIdx.x == 0) atomicOr(&plan->jump_more[round], 1u);
 }
 
 // Leaf depth: run j sits between boundaries j and j+1 and hangs below the
@@ -395,19 +409,20 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
   __shared__ uint32_t sw[kTreeWaves][kMaxLevels];
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const int nl = (int)plan->n_levels;   // every leader's depth is below this
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
     uint64_t i = b * kTreeThreads + t;
     bool lead = i > 0 && i < r && is_leader(P, Le, (uint32_t)i);
     int myd = lead ? dist[i] : -1;
     uint32_t rank = 0;
-    for (int d = 0; d < kMaxLevels; d++) {
+    for (int d = 0; d < nl; d++) {
       uint64_t mk = ballot64(myd == d);
       if (myd == d) rank = __popcll(mk & ((1ull << lane) - 1));
       if (lane == 0) sw[w][d] = __popcll(mk);
     }
     __syncthreads();
-    if (t < kMaxLevels) {
+    if (t < nl) {
       uint32_t acc = 0;
       for (int ww = 0; ww < kTreeWaves; ww++) {
         uint32_t c = sw[ww][t];
@@ -563,7 +578,7 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   hipLaunchKernelGGL(k_nodes, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0);
   for (int round = 0; round < 6; round++) {  // depths < 64
     bool even = (round & 1) == 0;
-    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.power, w.Le, w.plan, even ? w.jump0 : w.jump1,
+    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.power, w.Le, w.plan, round, even ? w.jump0 : w.jump1,
                        even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0, even ? w.dist1 : w.dist0);
   }
   hipLaunchKernelGGL(k_leaves, g256, b256, 0, s, w.power, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.leaf_depth);
