@@ -74,7 +74,7 @@ namespace {
 
 struct Layout {
   size_t total = 0;
-  size_t alt_keys, alt_vals, seg_off, dbits, det_agg, det_zin, det_off, run_start, run_desc,
+  size_t alt_keys, alt_vals, seg_off, seg_bits, dbits, det_agg, det_zin, det_off, run_start, run_desc,
       power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
       dist0, dist1, leaf_depth, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
       tj, samples, plan;
@@ -115,6 +115,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.alt_keys = take(c, N * ks);
   L.alt_vals = take(c, payload ? N * 4 : 0);
   L.seg_off = take(c, 16);
+  L.seg_bits = take(c, m > 1 ? nwords * 8 + 8 : 0);
   L.dbits = take(c, nwords * 8 + 8);
   L.det_agg = take(c, nblk * sizeof(DetAgg));
   L.det_zin = take(c, nblk * 8);
@@ -393,6 +394,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   w.alt_vals = payload ? at<uint32_t>(base, L.alt_vals) : nullptr;
   w.seg_off_local = at<uint64_t>(base, L.seg_off);
   w.off = d_off ? d_off : w.seg_off_local;
+  w.seg_bits = m > 1 ? at<uint64_t>(base, L.seg_bits) : nullptr;
   w.dbits = at<uint64_t>(base, L.dbits);
   w.det_agg = at<DetAgg>(base, L.det_agg);
   w.det_zin = at<uint64_t>(base, L.det_zin);

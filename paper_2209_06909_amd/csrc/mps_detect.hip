@@ -99,12 +99,34 @@ __device__ inline uint64_t dbit_at(const typename Key<KT>::U *keys, const uint64
   return Key<KT>::ord(keys[p]) < Key<KT>::ord(keys[p - 1]) ? 1 : 0;
 }
 
+// ---------------------------------------------------------------- segment starts
+// For batched calls: bit b of word w is set iff position 64w+b starts a
+// non-empty segment, so run detection reads one word per 64 positions
+// instead of searching the segment offsets.
+__global__ __launch_bounds__(256) void k_seg_zero(uint64_t *__restrict__ segb, uint64_t nwords) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    segb[i] = 0;
+}
+
+// (Offsets are checked on the device by the caller's plan check; an offset
+// past the end is not marked here, so nothing is written out of bounds.)
+__global__ __launch_bounds__(256) void k_seg_set(const uint64_t *__restrict__ off, uint64_t m,
+                                                 uint64_t nwords, uint64_t *__restrict__ segb) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t p = off[i];
+    if (off[i + 1] > p && (p >> 6) < nwords)
+      atomicOr((unsigned long long *)&segb[p >> 6], (unsigned long long)(1ull << (p & 63)));
+  }
+}
+
 // ---------------------------------------------------------------- pass 1
 template <int KT>
 __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
     const typename Key<KT>::U *__restrict__ keys, uint64_t N, const uint64_t *__restrict__ off,
-    uint64_t m, uint64_t *__restrict__ dbits, DetAgg *__restrict__ agg,
-    uint64_t *__restrict__ smp) {
+    uint64_t m, const uint64_t *__restrict__ segb, uint64_t *__restrict__ dbits,
+    DetAgg *__restrict__ agg, uint64_t *__restrict__ smp) {
   static_assert(kSampleStride % 64 == 0, "samples fall on 64-key word starts");
   using K = Key<KT>;
   using O = typename K::U;
@@ -116,7 +138,7 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const uint64_t my_word = word0 + t;
 
-  uint64_t sb_own = my_word < nwords ? seg_start_mask(off, m, my_word * 64) : 0;
+  uint64_t sb_own = my_word < nwords ? (segb ? segb[my_word] : seg_start_mask(off, m, my_word * 64)) : 0;
   uint64_t d_own = 0;
   const uint64_t wave_word0 = word0 + (uint64_t)wave * 64;
   O prev_last = 0;
@@ -283,7 +305,8 @@ __global__ __launch_bounds__(kScanThreads) void k_detect_scan(
 template <int KT>
 __global__ __launch_bounds__(kDetThreads) void k_detect_emit(
     const typename Key<KT>::U *__restrict__ keys, uint64_t N, const uint64_t *__restrict__ off,
-    uint64_t m, const uint64_t *__restrict__ dbits, const uint64_t *__restrict__ zin_blk,
+    uint64_t m, const uint64_t *__restrict__ segb, const uint64_t *__restrict__ dbits,
+    const uint64_t *__restrict__ zin_blk,
     const uint64_t *__restrict__ off_blk, uint64_t rmax, uint64_t *__restrict__ run_start,
     uint8_t *__restrict__ run_desc) {
   __shared__ uint64_t sD[kDetThreads + 1], sSB[kDetThreads];
@@ -294,7 +317,7 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_emit(
   const int t = threadIdx.x;
   const uint64_t my_word = word0 + t;
   sD[t] = my_word < nwords ? dbits[my_word] : 0;
-  sSB[t] = my_word < nwords ? seg_start_mask(off, m, my_word * 64) : 0;
+  sSB[t] = my_word < nwords ? (segb ? segb[my_word] : seg_start_mask(off, m, my_word * 64)) : 0;
   if (t == 0) {
     uint64_t nxt = word0 + kDetThreads;
     sD[kDetThreads] = nxt < nwords ? dbits[nxt] : 0;
@@ -336,17 +359,24 @@ hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s)
   uint64_t nblk = (N + kDetBlockPos - 1) / kDetBlockPos;
   if (nblk == 0) return hipSuccess;
   dim3 g((unsigned)nblk), b(kDetThreads);
+  if (w.seg_bits) {
+    const uint64_t nwords = (N + 63) / 64;
+    const unsigned gz = (unsigned)((nwords + 255) / 256 < 8192 ? (nwords + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_seg_zero, dim3(gz), dim3(256), 0, s, w.seg_bits, nwords);
+    const unsigned gs = (unsigned)((w.m + 255) / 256 < 8192 ? (w.m + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_seg_set, dim3(gs), dim3(256), 0, s, w.off, w.m, nwords, w.seg_bits);
+  }
   switch (kt) {
-    case 0: hipLaunchKernelGGL(k_detect_bits<0>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_agg, w.samples); break;
-    case 1: hipLaunchKernelGGL(k_detect_bits<1>, g, b, 0, s, (const uint64_t *)keys, N, w.off, w.m, w.dbits, w.det_agg, w.samples); break;
-    default: hipLaunchKernelGGL(k_detect_bits<2>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_agg, w.samples); break;
+    case 0: hipLaunchKernelGGL(k_detect_bits<0>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.seg_bits, w.dbits, w.det_agg, w.samples); break;
+    case 1: hipLaunchKernelGGL(k_detect_bits<1>, g, b, 0, s, (const uint64_t *)keys, N, w.off, w.m, w.seg_bits, w.dbits, w.det_agg, w.samples); break;
+    default: hipLaunchKernelGGL(k_detect_bits<2>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.seg_bits, w.dbits, w.det_agg, w.samples); break;
   }
   hipLaunchKernelGGL(k_detect_scan, dim3(1), dim3(kScanThreads), 0, s, w.det_agg, nblk, N, w.rmax,
                      w.det_zin, w.det_off, w.run_start, w.plan);
   switch (kt) {
-    case 0: hipLaunchKernelGGL(k_detect_emit<0>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_zin, w.det_off, w.rmax, w.run_start, w.run_desc); break;
-    case 1: hipLaunchKernelGGL(k_detect_emit<1>, g, b, 0, s, (const uint64_t *)keys, N, w.off, w.m, w.dbits, w.det_zin, w.det_off, w.rmax, w.run_start, w.run_desc); break;
-    default: hipLaunchKernelGGL(k_detect_emit<2>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.dbits, w.det_zin, w.det_off, w.rmax, w.run_start, w.run_desc); break;
+    case 0: hipLaunchKernelGGL(k_detect_emit<0>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.seg_bits, w.dbits, w.det_zin, w.det_off, w.rmax, w.run_start, w.run_desc); break;
+    case 1: hipLaunchKernelGGL(k_detect_emit<1>, g, b, 0, s, (const uint64_t *)keys, N, w.off, w.m, w.seg_bits, w.dbits, w.det_zin, w.det_off, w.rmax, w.run_start, w.run_desc); break;
+    default: hipLaunchKernelGGL(k_detect_emit<2>, g, b, 0, s, (const uint32_t *)keys, N, w.off, w.m, w.seg_bits, w.dbits, w.det_zin, w.det_off, w.rmax, w.run_start, w.run_desc); break;
   }
   return hipGetLastError();
 }

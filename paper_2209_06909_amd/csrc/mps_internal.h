@@ -74,6 +74,7 @@ struct Work {
   const uint64_t *off;               // segment offsets [m+1]
   uint64_t *seg_off_local;           // 2-entry offsets for single-array calls
   uint64_t *dbits;
+  uint64_t *seg_bits;                // [nwords] segment-start bits (batched calls; else null)
   DetAgg *det_agg;
   uint64_t *det_zin, *det_off;
   uint64_t *run_start;               // [rmax+1]
