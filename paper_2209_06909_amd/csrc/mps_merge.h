@@ -97,6 +97,11 @@ __device__ inline uint64_t gshfl<uint64_t>(uint64_t v, int src, int width) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ inline uint64_t gshfl_up64(uint64_t v, int o) {
+  const uint32_t lo = __shfl_up((uint32_t)v, o), hi = __shfl_up((uint32_t)(v >> 32), o);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename O, int K, typename Get>
 __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, int j, Get get) {
   uint32_t mm = 0;
@@ -369,20 +374,21 @@ struct FastSmem {
   uint32_t claim[2];   // tile indices taken from the work queue
 };
 
-// LDS of the general kernel (tiles spanning many small nodes).
+// LDS of the general kernel (tiles spanning many small nodes): one tile buffer
+// (the stages merge in place) and the piece and slice tables.
 template <typename O, int K, int TILE, int THREADS>
 struct GenSmem {
   static constexpr int kMaxSlices = TILE + 2 * K + 2;
   static constexpr int kMaxPieces = TILE / 2 + 4;
+  static constexpr int kWaves = THREADS / 64;
   static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
   static constexpr size_t kAux = kBuf > (size_t)kMaxSlices * 8 ? kBuf : (size_t)kMaxSlices * 8;
-  alignas(16) unsigned char bufA[kBuf];
-  alignas(16) unsigned char bufB[kAux];       // also holds slice global starts during setup
+  alignas(16) unsigned char bufA[kAux];   // the tile; holds the slices' global starts during setup
   uint64_t pc_out[kMaxPieces];
   uint16_t sl_off[kMaxSlices];
   uint16_t pc_loff[kMaxPieces];
   uint16_t pc_sl[kMaxPieces];
-  uint64_t scan[THREADS];
+  uint64_t wsum[kWaves];
   int misc[8];
 };
 
@@ -486,20 +492,28 @@ __device__ inline void commit_loads(const O (&kreg)[E], const uint32_t (&vreg)[E
   }
 }
 
-// log2(K) stages of pairwise merge-path merges in LDS; returns which buffer
-// holds the result (0: A, 1: B).
-template <typename O, int K, int TILE, int THREADS>
-__device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, bool has_vals,
-                                   const uint16_t *sl_off, int S, const uint16_t *pc_sl, int P,
-                                   int Tt, int t) {
+// log2(K) stages of pairwise merge-path merges of a general tile (any number
+// of pieces), in place in one LDS buffer: a lane merges its E outputs
+// [t*E, t*E+E) into registers, unit by unit, and writes them back after a
+// barrier (every read of the stage done).  A lane's outputs may come from
+// several merge units; output q of the lane is selected into register q.
+template <typename O, int K, int TILE, int THREADS, bool HV>
+__device__ inline void merge_stages_gen(O *ks, uint32_t *vs, const uint16_t *sl_off, int S,
+                                        const uint16_t *pc_sl, int P, int Tt, int t) {
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
-  O *ks = kA, *kd = kB;
-  uint32_t *vs = vA, *vd = vB;
+  const int e0 = t * E;
+  const int e1 = e0 + E < Tt ? e0 + E : Tt;
   for (int st = 1; st <= LOGK; st++) {
-    int e = t * E;
-    const int e_end = (t + 1) * E < Tt ? (t + 1) * E : Tt;
-    while (e < e_end) {
+    O ok[E];
+    uint32_t os[E];   // LDS index of each output's source
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      ok[i] = 0;
+      os[i] = 0;
+    }
+    int e = e0;
+    while (e < e1) {
       int s = ub16(sl_off, S + 1, e) - 1;
       int p = P == 1 ? 0 : ub16(pc_sl, P + 1, s) - 1;
       int s0 = pc_sl[p];
@@ -518,28 +532,43 @@ __device__ inline int merge_stages(O *kA, uint32_t *vA, O *kB, uint32_t *vB, boo
         if (ks[u0 + mid] <= ks[u1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
       }
       int ia = u0 + lo, ib = u1 + diag - lo;
-      int stop = e_end < u2 ? e_end : u2;
+      int stop = e1 < u2 ? e1 : u2;
       if (stop <= e) break;  // cannot happen with valid tables (e < u2)
       // heads kept in registers; one LDS key load per output
       O ka = ks[ia < TILE ? ia : TILE - 1];
       O kb = ks[ib < TILE ? ib : TILE - 1];
       for (; e < stop; e++) {
-        bool takeL = ib >= u2 || (ia < u1 && ka <= kb);
-        int src = takeL ? ia : ib;
-        kd[e] = takeL ? ka : kb;
-        if (has_vals) vd[e] = vs[src];
+        const bool takeL = ib >= u2 || (ia < u1 && ka <= kb);
+        const O kv = takeL ? ka : kb;
+        const uint32_t src = (uint32_t)(takeL ? ia : ib);
+        const int q = e - e0;
+#pragma unroll
+        for (int i = 0; i < E; i++) {
+          ok[i] = i == q ? kv : ok[i];
+          os[i] = i == q ? src : os[i];
+        }
         ia += takeL ? 1 : 0;
         ib += takeL ? 0 : 1;
-        int nx = takeL ? ia : ib;
-        O kn = ks[nx < TILE ? nx : TILE - 1];
+        const int nx = takeL ? ia : ib;
+        const O kn = ks[nx < TILE ? nx : TILE - 1];
         if (takeL) ka = kn; else kb = kn;
       }
     }
+    uint32_t pv[E];
+    if (HV) {
+#pragma unroll
+      for (int i = 0; i < E; i++) pv[i] = vs[os[i]];
+    }
+    lds_barrier();   // every read of this stage is done
+#pragma unroll
+    for (int i = 0; i < E; i++) {
+      if (e0 + i < e1) {
+        ks[e0 + i] = ok[i];
+        if (HV) vs[e0 + i] = pv[i];
+      }
+    }
     lds_barrier();
-    O *tk = ks; ks = kd; kd = tk;
-    uint32_t *tv = vs; vs = vd; vd = tv;
   }
-  return (LOGK & 1) ? 1 : 0;
 }
 
 // Merge-path cut of one lane: the smallest i in [lo, hi] with a[i] > b[-i],
@@ -869,7 +898,7 @@ void k_merge_fast(
 // and slice tables are built from the node records, then the same staged
 // merge runs.  Not pipelined.
 template <int KT, int K, int TILE, int THREADS, bool HV>
-__global__ __launch_bounds__(THREADS) void k_merge_general(
+__global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
     const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
@@ -886,9 +915,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_general(
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
   uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
-  O *kB = reinterpret_cast<O *>(sm.bufB);
-  uint32_t *vB = reinterpret_cast<uint32_t *>(sm.bufB + (size_t)TILE * sizeof(O));
-  uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufB);
+  uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufA);
 
   const uint32_t ngen = plan->gen_cnt[level];
   if (ngen == 0) return;
@@ -899,6 +926,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_general(
   const uint64_t L = np[le] - np0;
   const uint32_t *tjl = tj + tile_base[level];
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   uint64_t ga[E];
 
   uint32_t *queue = &plan->q_gen[level];
@@ -945,17 +973,23 @@ __global__ __launch_bounds__(THREADS) void k_merge_general(
             plen += c1[jj] - c0[jj];
           }
         }
-        uint64_t packed = ((uint64_t)pd << 32) | plen;
-        sm.scan[t] = packed;
-        __syncthreads();
-        for (int o = 1; o < THREADS; o <<= 1) {
-          uint64_t y = t >= o ? sm.scan[t - o] : 0;
-          __syncthreads();
-          sm.scan[t] += y;
-          __syncthreads();
+        // exclusive scan of (slices, length) over the pieces: within each wave
+        // by shuffles, then across the waves' totals
+        const uint64_t packed = ((uint64_t)pd << 32) | plen;
+        uint64_t incl = packed;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint64_t y = gshfl_up64(incl, o);
+          if (lane >= o) incl += y;
         }
-        uint64_t ex = sm.scan[t] - packed;
-        uint64_t tot = sm.scan[THREADS - 1];
+        if (lane == 63) sm.wsum[wave] = incl;
+        __syncthreads();
+        uint64_t ex = incl - packed, tot = 0;
+        for (int w = 0; w < SM::kWaves; w++) {
+          const uint64_t ws = sm.wsum[w];
+          ex += w < wave ? ws : 0;
+          tot += ws;
+        }
         __syncthreads();
         if (p < P && carry_len + (ex & 0xFFFFFFFFull) + plen <= (uint64_t)Tt &&
             carry_sl + (ex >> 32) + pd < (uint64_t)SM::kMaxSlices) {
@@ -988,12 +1022,12 @@ __global__ __launch_bounds__(THREADS) void k_merge_general(
         uint32_t v2[E];
         addr_search<E, THREADS>(ga, sm.sl_off, sl_g, S, Tt, t);
         issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
+        lds_barrier();   // the slice starts, kept in the tile buffer, are read
         commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, HV, Tt, t);
-        __syncthreads();
-        int res = merge_stages<O, K, TILE, THREADS>(kA, vA, kB, vB, HV, sm.sl_off, S, sm.pc_sl,
-                                                    P, Tt, t);
-        store_tile<Kt, O, E, THREADS>(res ? kB : kA, res ? vB : vA, out_keys, out_vals, HV,
-                                      sm.pc_loff, sm.pc_out, P, Tt, t, smp);
+        lds_barrier();
+        merge_stages_gen<O, K, TILE, THREADS, HV>(kA, vA, sm.sl_off, S, sm.pc_sl, P, Tt, t);
+        store_tile<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV, sm.pc_loff, sm.pc_out, P,
+                                      Tt, t, smp);
       }
     }
     if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
