@@ -388,6 +388,8 @@ struct GenSmem {
   uint16_t sl_off[kMaxSlices];
   uint16_t pc_loff[kMaxPieces];
   uint16_t pc_sl[kMaxPieces];
+  uint16_t sl_pc[kMaxSlices];             // piece of each slice
+  uint16_t pos_sl[TILE];                  // slice of each tile position
   uint64_t wsum[kWaves];
   int misc[8];
 };
@@ -439,13 +441,13 @@ __device__ inline void build_small(SmallTab<K> &T, const TileDesc<K> &D, bool ex
 // loads that follow form one straight-line block: the compiler then issues
 // all of them before the first wait instead of waiting between them.
 template <int E, int THREADS>
-__device__ inline void addr_search(uint64_t (&g)[E], const uint16_t *sl_off,
-                                   const uint64_t *sl_g, int S, int Tt, int t) {
+__device__ inline void addr_table(uint64_t (&g)[E], const uint16_t *pos_sl,
+                                  const uint16_t *sl_off, const uint64_t *sl_g, int Tt, int t) {
 #pragma unroll
   for (int i = 0; i < E; i++) {
     int e = t + i * THREADS;
     int ec = e < Tt ? e : Tt - 1;
-    int s = ub16(sl_off, S + 1, ec) - 1;
+    int s = pos_sl[ec];
     g[i] = sl_g[s] + (uint64_t)(ec - sl_off[s]);
   }
 }
@@ -498,8 +500,9 @@ __device__ inline void commit_loads(const O (&kreg)[E], const uint32_t (&vreg)[E
 // barrier (every read of the stage done).  A lane's outputs may come from
 // several merge units; output q of the lane is selected into register q.
 template <typename O, int K, int TILE, int THREADS, bool HV>
-__device__ inline void merge_stages_gen(O *ks, uint32_t *vs, const uint16_t *sl_off, int S,
-                                        const uint16_t *pc_sl, int P, int Tt, int t) {
+__device__ inline void merge_stages_gen(O *ks, uint32_t *vs, const uint16_t *sl_off,
+                                        const uint16_t *pos_sl, const uint16_t *sl_pc,
+                                        const uint16_t *pc_sl, int Tt, int t) {
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
   const int e0 = t * E;
@@ -514,8 +517,8 @@ __device__ inline void merge_stages_gen(O *ks, uint32_t *vs, const uint16_t *sl_
     }
     int e = e0;
     while (e < e1) {
-      int s = ub16(sl_off, S + 1, e) - 1;
-      int p = P == 1 ? 0 : ub16(pc_sl, P + 1, s) - 1;
+      int s = pos_sl[e];
+      int p = sl_pc[s];
       int s0 = pc_sl[p];
       int pd = pc_sl[p + 1] - s0;
       int jj = s - s0;
@@ -756,12 +759,13 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
 template <typename Kt, typename O, int E, int THREADS>
 __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
                                   uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
-                                  const uint64_t *pc_out, int P, int Tt, int t, uint64_t *smp) {
+                                  const uint64_t *pc_out, const uint16_t *pos_sl,
+                                  const uint16_t *sl_pc, int Tt, int t, uint64_t *smp) {
 #pragma unroll
   for (int i = 0; i < E; i++) {
     int e = t + i * THREADS;
     if (e < Tt) {
-      int p = P == 1 ? 0 : ub16(pc_loff, P + 1, e) - 1;
+      int p = sl_pc[pos_sl[e]];
       uint64_t g = pc_out[p] + (uint64_t)(e - pc_loff[p]);
       out_keys[g] = Kt::unord(ks[e]);
       if (has_vals) out_vals[g] = vs[e];
@@ -1001,6 +1005,7 @@ __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
           uint64_t acc = loff;
           for (int jj = 0; jj < pd; jj++) {
             sm.sl_off[sl0 + jj] = (uint16_t)acc;
+            sm.sl_pc[sl0 + jj] = (uint16_t)p;
             sl_g[sl0 + jj] = nd.c[jj] + c0[jj];
             acc += c1[jj] - c0[jj];
           }
@@ -1018,16 +1023,52 @@ __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
       }
       __syncthreads();
       if (!sm.misc[4]) {
+        // slice of every tile position: each non-empty slice marks its start,
+        // then a running maximum over the positions (thread t owns E of them)
+        const int b0 = t * E;
+#pragma unroll
+        for (int i = 0; i < E; i++)
+          if (b0 + i < Tt) sm.pos_sl[b0 + i] = 0;
+        lds_barrier();
+        for (int s2 = t; s2 < S; s2 += THREADS)
+          if (sm.sl_off[s2 + 1] > sm.sl_off[s2]) sm.pos_sl[sm.sl_off[s2]] = (uint16_t)s2;
+        lds_barrier();
+        uint32_t run = 0, rv[E];
+#pragma unroll
+        for (int i = 0; i < E; i++) {
+          const uint32_t v = b0 + i < Tt ? sm.pos_sl[b0 + i] : 0u;
+          run = v > run ? v : run;
+          rv[i] = run;
+        }
+        uint32_t incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(incl, o);
+          if (lane >= o) incl = y > incl ? y : incl;
+        }
+        if (lane == 63) sm.wsum[wave] = incl;
+        uint32_t pre = __shfl_up(incl, 1);
+        if (lane == 0) pre = 0;
+        lds_barrier();
+        for (int w = 0; w < wave; w++) {
+          const uint32_t ws = (uint32_t)sm.wsum[w];
+          pre = ws > pre ? ws : pre;
+        }
+#pragma unroll
+        for (int i = 0; i < E; i++)
+          if (b0 + i < Tt) sm.pos_sl[b0 + i] = (uint16_t)(rv[i] > pre ? rv[i] : pre);
+        lds_barrier();
         O k2[E];
         uint32_t v2[E];
-        addr_search<E, THREADS>(ga, sm.sl_off, sl_g, S, Tt, t);
+        addr_table<E, THREADS>(ga, sm.pos_sl, sm.sl_off, sl_g, Tt, t);
         issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
         lds_barrier();   // the slice starts, kept in the tile buffer, are read
         commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, HV, Tt, t);
         lds_barrier();
-        merge_stages_gen<O, K, TILE, THREADS, HV>(kA, vA, sm.sl_off, S, sm.pc_sl, P, Tt, t);
-        store_tile<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV, sm.pc_loff, sm.pc_out, P,
-                                      Tt, t, smp);
+        merge_stages_gen<O, K, TILE, THREADS, HV>(kA, vA, sm.sl_off, sm.pos_sl, sm.sl_pc,
+                                                  sm.pc_sl, Tt, t);
+        store_tile<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV, sm.pc_loff, sm.pc_out,
+                                      sm.pos_sl, sm.sl_pc, Tt, t, smp);
       }
     }
     if (t == 0 && sm.misc[4]) atomicOr(&plan->error, 16u);
