@@ -7,7 +7,8 @@ code with the GPU library.  The arithmetic lives in ``oracle.c`` (plain C,
 single-threaded); this module only marshals numpy arrays through ctypes.
 
 Each function follows the paper (arXiv 2209.06909):
-  runs()            Section 2, run definition (greedy left-to-right scan)
+  runs()            Section 2, run definition (greedy left-to-right scan);
+                    with min_run > 1, Appendix A.3's extension of short runs
   power()/powers()  Definition 3.1, run-boundary power (exact integers)
   sort()            Algorithm 2 (KwayPowerSort_k) with stable k-way merges
   kway_tree()       Algorithm 1 (KwayTree_k), independent cross-check
@@ -84,6 +85,10 @@ def lib():
         l.oracle_powers.restype = i32
         l.oracle_sort.argtypes = [P, i32, P, u64, u32, ctypes.POINTER(_Trace)]
         l.oracle_sort.restype = i32
+        l.oracle_sort_ex.argtypes = [P, i32, P, u64, u32, u32, ctypes.POINTER(_Trace)]
+        l.oracle_sort_ex.restype = i32
+        l.oracle_runs_min.argtypes = [P, i32, P, u64, u32, P, P]
+        l.oracle_runs_min.restype = u64
         l.oracle_trace_free.argtypes = [ctypes.POINTER(_Trace)]
         l.oracle_trace_free.restype = None
         l.oracle_kway_tree.argtypes = [P, u64, P, P]
@@ -156,13 +161,21 @@ def key_cmp(keys: np.ndarray, i: int, j: int) -> int:
     return int(lib().oracle_key_cmp(_ptr(keys), _kt(keys), i, j))
 
 
-def runs(keys: np.ndarray):
-    """Greedy run partition (Section 2) -> (run_start uint64[r+1], run_desc uint8[r])."""
+def runs(keys: np.ndarray, min_run: int = 1):
+    """Greedy run partition (Section 2) -> (run_start uint64[r+1], run_desc uint8[r]).
+
+    min_run > 1: runs shorter than min_run are extended (Appendix A.3); the
+    partition depends only on the input, which is not modified."""
     keys = np.ascontiguousarray(keys)
     n = keys.size
     rs = np.empty(n + 1, dtype=np.uint64)
     rd = np.empty(max(n, 1), dtype=np.uint8)
-    r = int(lib().oracle_runs(_ptr(keys), _kt(keys), n, _ptr(rs), _ptr(rd)))
+    if min_run <= 1:
+        r = int(lib().oracle_runs(_ptr(keys), _kt(keys), n, _ptr(rs), _ptr(rd)))
+    else:
+        work = keys.copy()
+        r = int(lib().oracle_runs_min(_ptr(work), _kt(work), None, n, min_run,
+                                      _ptr(rs), _ptr(rd)))
     return rs[: r + 1].copy(), rd[:r].copy()
 
 
@@ -183,15 +196,17 @@ def powers(run_start: np.ndarray, k: int) -> np.ndarray:
     return out
 
 
-def sort(keys: np.ndarray, payload: np.ndarray | None = None, k: int = 4):
-    """Stable k-way Powersort (Algorithm 2).  Returns (keys, payload, Trace); inputs are copied."""
+def sort(keys: np.ndarray, payload: np.ndarray | None = None, k: int = 4, min_run: int = 1):
+    """Stable k-way Powersort (Algorithm 2).  Returns (keys, payload, Trace); inputs are copied.
+
+    min_run > 1 extends short runs first (Appendix A.3)."""
     keys = np.array(keys, copy=True, order="C")
     pl = None if payload is None else np.array(payload, dtype=np.uint32, copy=True, order="C")
     if pl is not None and pl.size != keys.size:
         raise ValueError("payload size mismatch")
     t = _Trace()
-    rc = lib().oracle_sort(_ptr(keys), _kt(keys), None if pl is None else _ptr(pl),
-                           keys.size, k, ctypes.byref(t))
+    rc = lib().oracle_sort_ex(_ptr(keys), _kt(keys), None if pl is None else _ptr(pl),
+                              keys.size, k, max(int(min_run), 1), ctypes.byref(t))
     if rc:
         raise RuntimeError(f"oracle_sort failed ({rc})")
     return keys, pl, _take_trace(t)

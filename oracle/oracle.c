@@ -73,6 +73,72 @@ uint64_t oracle_runs(const void *keys, int kt, uint64_t n,
 
 /* Reverse elements [b, e) of keys (and payload). */
 static void reverse_range(unsigned char *keys, size_t ks, uint32_t *payload,
+                          uint64_t b, uint64_t e);
+
+/* Three-way comparison of two key values given by address. */
+static int value_cmp(int kt, const unsigned char *a, const unsigned char *b) {
+    unsigned char pair[16];
+    size_t ks = key_size(kt);
+    memcpy(pair, a, ks);
+    memcpy(pair + ks, b, ks);
+    return oracle_key_cmp(pair, kt, 0, 1);
+}
+
+/* Runs with a minimal run length (the 4-way Powersort implementation of
+ * Appendix A.3, as in Timsort).  Scanning left to right from b = 0: the
+ * natural run starting at b is found as in oracle_runs and, if strictly
+ * decreasing, reversed at once.  If it is shorter than min_run it is
+ * extended to min(n, b + min_run) elements, and the added elements are put
+ * into place one by one by a stable insertion sort (each is shifted left past
+ * the strictly larger keys only).  The next run starts where this one ends.
+ * Keys and payload are rearranged in place.  run_desc[i] is 1 iff run i is
+ * a strictly decreasing natural run that was reversed and not extended.
+ * min_run <= 1 gives exactly the natural runs (and reverses them). */
+uint64_t oracle_runs_min(void *keys_v, int kt, uint32_t *payload, uint64_t n,
+                         uint32_t min_run, uint64_t *run_start, uint8_t *run_desc) {
+    unsigned char *keys = keys_v;
+    size_t ks = key_size(kt);
+    unsigned char x[8];
+    uint64_t r = 0, b = 0;
+    while (b < n) {
+        uint64_t e = b + 1;
+        uint8_t desc = 0;
+        if (e < n && oracle_key_cmp(keys, kt, e, b) < 0) {
+            desc = 1;
+            while (e < n && oracle_key_cmp(keys, kt, e, e - 1) < 0) e++;
+        } else {
+            while (e < n && oracle_key_cmp(keys, kt, e, e - 1) >= 0) e++;
+        }
+        if (desc) reverse_range(keys, ks, payload, b, e);
+        int extended = 0;
+        if (min_run > 1 && e - b < min_run) {
+            uint64_t e2 = b + min_run < n ? b + min_run : n;
+            extended = e2 > e;
+            for (uint64_t i = e; i < e2; i++) {
+                memcpy(x, keys + i * ks, ks);
+                uint32_t xv = payload ? payload[i] : 0;
+                uint64_t j = i;
+                while (j > b && value_cmp(kt, keys + (j - 1) * ks, x) > 0) {
+                    memcpy(keys + j * ks, keys + (j - 1) * ks, ks);
+                    if (payload) payload[j] = payload[j - 1];
+                    j--;
+                }
+                memcpy(keys + j * ks, x, ks);
+                if (payload) payload[j] = xv;
+            }
+            e = e2;
+        }
+        run_start[r] = b;
+        run_desc[r] = (uint8_t)(desc && !extended);
+        r++;
+        b = e;
+    }
+    run_start[r] = n;
+    return r;
+}
+
+/* Reverse elements [b, e) of keys (and payload). */
+static void reverse_range(unsigned char *keys, size_t ks, uint32_t *payload,
                           uint64_t b, uint64_t e) {
     unsigned char tmp[8];
     while (e > b + 1) {
@@ -331,6 +397,11 @@ int oracle_tree_from_runs(const uint64_t *run_start, uint64_t r, uint32_t k,
 
 int oracle_sort(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
                 oracle_trace *trace) {
+    return oracle_sort_ex(keys, kt, payload, n, k, 1, trace);
+}
+
+int oracle_sort_ex(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
+                   uint32_t min_run, oracle_trace *trace) {
     if (k < 2 || k > 64 || (n > 0 && !keys)) return -1;
     if (kt != ORC_I32 && kt != ORC_I64 && kt != ORC_F32) return -1;
     size_t ks = key_size(kt);
@@ -345,12 +416,17 @@ int oracle_sort(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
         free(mv.tmp_payload);
         return -2;
     }
-    uint64_t r = oracle_runs(keys, kt, n, run_start, run_desc);
-    /* Strictly decreasing runs hold no equal keys, so reversing them keeps
-     * the sort stable. */
-    for (uint64_t i = 0; i < r; i++)
-        if (run_desc[i])
-            reverse_range(keys, ks, payload, run_start[i], run_start[i + 1]);
+    uint64_t r;
+    if (min_run <= 1) {
+        r = oracle_runs(keys, kt, n, run_start, run_desc);
+        /* Strictly decreasing runs hold no equal keys, so reversing them keeps
+         * the sort stable. */
+        for (uint64_t i = 0; i < r; i++)
+            if (run_desc[i])
+                reverse_range(keys, ks, payload, run_start[i], run_start[i + 1]);
+    } else {
+        r = oracle_runs_min(keys, kt, payload, n, min_run, run_start, run_desc);
+    }
 
     oracle_trace local;
     oracle_trace *tr = trace ? trace : &local;

@@ -10,7 +10,8 @@
  * "Multiway Powersort", arXiv 2209.06909) step by step:
  *   - runs:            Section 2 (maximal weakly increasing or strictly
  *                      decreasing segments, found by one left-to-right scan;
- *                      decreasing runs are reversed)
+ *                      decreasing runs are reversed); optionally extended to
+ *                      a minimal run length by insertion sort (Appendix A.3)
  *   - node power:      Definition 3.1 (run-boundary power), evaluated in
  *                      exact integer arithmetic
  *   - merge policy:    Algorithm 2 (KwayPowerSort_k, left-to-right run stack
@@ -46,6 +47,15 @@ int oracle_key_cmp(const void *keys, int kt, uint64_t i, uint64_t j);
  * run_start[r] = n.  Keys are not modified. */
 uint64_t oracle_runs(const void *keys, int kt, uint64_t n,
                      uint64_t *run_start, uint8_t *run_desc);
+
+/* Runs with a minimal run length min_run (Appendix A.3): natural runs shorter
+ * than min_run are extended to min(n, start + min_run) elements by a stable
+ * insertion sort; the next run starts where the extended one ends.  Keys and
+ * payload (nullable) are rearranged in place: every run is left ascending.
+ * run_desc[i] = 1 iff run i is a strictly decreasing natural run that was
+ * reversed whole (not extended).  min_run <= 1: the natural runs, reversed. */
+uint64_t oracle_runs_min(void *keys, int kt, uint32_t *payload, uint64_t n,
+                         uint32_t min_run, uint64_t *run_start, uint8_t *run_desc);
 
 /* Definition 3.1: k-way power of the boundary at s_cur between the run
  * [s_prev, s_cur) and the run [s_cur, s_next) of an array of length n.
@@ -92,6 +102,11 @@ typedef struct {
 int oracle_sort(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
                 oracle_trace *trace);
 void oracle_trace_free(oracle_trace *trace);
+
+/* oracle_sort with a minimal run length (oracle_runs_min); min_run <= 1 is
+ * oracle_sort itself. */
+int oracle_sort_ex(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
+                   uint32_t min_run, oracle_trace *trace);
 
 /* Algorithm 1 (KwayTree_k) over a given run partition and its powers.
  * nodes must hold r-1 entries; returns the node count (post-order:

@@ -380,3 +380,156 @@ def test_edge_cases(name, k):
         assert tr.r == keys.size // 2 and np.all(tr.run_desc == 1)
     if name in ("all_equal", "ascending"):
         assert tr.r == 1 and tr.merge_cost == 0
+
+
+# ---------------------------------------------------------------- minimal run length
+
+def check_min_runs(keys, rs, rd, m):
+    """The partition Appendix A.3's scan must produce, stated as properties of
+    the input: runs longer than m are maximal natural runs from their start;
+    runs of exactly m (or the shorter last one) are not: the natural run from
+    their start ends inside them, or exactly at their end; desc flags mark the
+    runs that are strictly decreasing as they stand in the input."""
+    n = keys.size
+    rs = rs.astype(np.int64)
+    assert rs[0] == 0 and rs[-1] == n
+    r = rs.size - 1
+    for i in range(r):
+        s, e = int(rs[i]), int(rs[i + 1])
+        L = e - s
+        assert L >= 1
+        if L < m:
+            assert e == n                          # only the tail may stay short
+        seg = keys[s:e]
+        down = L >= 2 and bool(np.all(lt(seg[1:], seg[:-1])))
+        up = not np.any(lt(seg[1:], seg[:-1]))
+        assert rd[i] == (1 if down else 0)
+        if L > m:                                  # a natural run, maximal
+            assert up or down
+            if e < n:
+                if down:
+                    assert not lt(keys[e:e + 1], keys[e - 1:e])[0]
+                else:
+                    assert lt(keys[e:e + 1], keys[e - 1:e])[0]
+        elif e < n and (up or down) and L >= 2:    # natural over [s, e): must stop at e
+            if down:
+                assert not lt(keys[e:e + 1], keys[e - 1:e])[0]
+            else:
+                assert lt(keys[e:e + 1], keys[e - 1:e])[0]
+
+
+def test_min_run_worked_example():
+    """Worked by hand, minimal run length 4 (Appendix A.3's scan):
+    5 3 | 8 9 ...: the natural run from 0 is (5, 3), decreasing, length 2 < 4,
+    so the run is [0, 4), sorted to 3 5 8 9.  From 4: 2 2 7 is weakly
+    increasing (1 breaks it), length 3 < 4: run [4, 8) = 1 2 2 7.  From 8:
+    0 4 6 6 (5 breaks it), length 4: a natural run [8, 12), not extended.
+    From 12: the single 5, which cannot be extended past the end."""
+    keys = np.array([5, 3, 8, 9, 2, 2, 7, 1, 0, 4, 6, 6, 5], np.int32)
+    rs, rd = oracle.runs(keys, min_run=4)
+    assert rs.tolist() == [0, 4, 8, 12, 13]
+    assert rd.tolist() == [0, 0, 0, 0]
+    pay = np.arange(keys.size, dtype=np.uint32)
+    sk, sp, tr = oracle.sort(keys, pay, k=4, min_run=4)
+    assert sp.tolist() == stable_order(keys).tolist()
+    assert tr.run_start.tolist() == [0, 4, 8, 12, 13]
+    # natural runs of the same input, for contrast: (5 3)(8 9)(2 2 7)(1 0)(4 6 6)(5)
+    assert oracle.runs(keys)[0].tolist() == [0, 2, 4, 7, 9, 12, 13]
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+def test_min_run_bruteforce_all_tie_patterns(n):
+    """Every tie pattern of length n, minimal run lengths 2..4 and 8: the
+    partition has the properties of Appendix A.3's scan, the output is the
+    unique stable sort and the tree over the partition keeps every Section 3
+    invariant."""
+    rows = weak_orderings(n)
+    for m in (2, 3, 4, 8):
+        for row in rows:
+            rs, rd = oracle.runs(row, min_run=m)
+            check_min_runs(row, rs, rd, m)
+            sk, sp, tr = oracle.sort(row, np.arange(n, dtype=np.uint32), k=4, min_run=m)
+            assert np.array_equal(sp, stable_order(row))
+            assert np.array_equal(tr.run_start, rs) and np.array_equal(tr.run_desc, rd)
+            check_tree_invariants(tr, 4)
+
+
+def test_min_run_random_small_alphabets():
+    """Longer inputs over 2-4 values (many ties, many short runs): the same
+    properties for minimal run lengths 2..6."""
+    rng = np.random.default_rng(14)
+    for _ in range(300):
+        n = int(rng.integers(20, 80))
+        row = rng.integers(0, int(rng.integers(2, 5)), size=n).astype(np.int32)
+        m = int(rng.integers(2, 7))
+        rs, rd = oracle.runs(row, min_run=m)
+        check_min_runs(row, rs, rd, m)
+        sk, sp, tr = oracle.sort(row, np.arange(n, dtype=np.uint32), k=4, min_run=m)
+        assert np.array_equal(sp, stable_order(row))
+        check_tree_invariants(tr, 4)
+
+
+def test_min_run_one_is_natural():
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        keys = rng.integers(0, 6, size=int(rng.integers(1, 300))).astype(np.int32)
+        rs0, rd0 = oracle.runs(keys)
+        rs1, rd1 = oracle.runs(keys, min_run=1)
+        assert np.array_equal(rs0, rs1) and np.array_equal(rd0, rd1)
+        a = oracle.sort(keys, None, k=4)
+        b = oracle.sort(keys, None, k=4, min_run=1)
+        assert np.array_equal(a[0], b[0]) and a[2].merge_cost == b[2].merge_cost
+
+
+@pytest.mark.parametrize("m", [3, 5, 24])
+def test_min_run_zigzag_closed_form(m):
+    """Every natural run of an alternating input has length 2, so every run
+    from any start is shorter than m >= 3: the runs start at 0, m, 2m, ..."""
+    keys = np.tile(np.array([1, 0], np.int32), 500)
+    rs, rd = oracle.runs(keys, min_run=m)
+    want = list(range(0, keys.size, m)) + [keys.size]
+    assert rs.tolist() == want and not rd.any()
+    rs2, rd2 = oracle.runs(keys, min_run=2)        # length-2 runs are not extended
+    assert rs2.tolist() == list(range(0, keys.size + 1, 2)) and rd2.all()
+
+
+def test_min_run_covering_everything_is_insertion_sort():
+    rng = np.random.default_rng(12)
+    for n in (1, 5, 17, 40):
+        keys = rng.integers(-3, 3, size=n).astype(np.int64)
+        pay = np.arange(n, dtype=np.uint32)
+        sk, sp, tr = oracle.sort(keys, pay, k=4, min_run=n + 3)
+        assert tr.r == 1 and tr.merge_cost == 0
+        assert np.array_equal(sp, stable_order(keys))
+
+
+def test_min_run_long_natural_runs_unchanged():
+    """Natural runs of length >= m are never extended: the partition is the
+    natural one."""
+    rng = np.random.default_rng(13)
+    m = 24
+    for _ in range(10):
+        lens = rng.integers(m, 4 * m, size=40)
+        # increasing segments in a high band, decreasing ones in a low band:
+        # every segment edge breaks the run before it, so each segment is
+        # exactly one natural run
+        parts = [10 ** 6 + np.arange(L) if j % 2 == 0 else np.arange(L, 0, -1)
+                 for j, L in enumerate(lens)]
+        keys = np.concatenate(parts).astype(np.int64)
+        nat = oracle.runs(keys)[0]
+        assert np.array_equal(nat, starts_from_lengths(lens))
+        assert np.array_equal(oracle.runs(keys, min_run=m)[0], nat)
+
+
+@pytest.mark.parametrize("name,n", [("perm_i64", 1 << 16), ("runs_i32", 1 << 17),
+                                    ("ties_i32", 1 << 17)])
+def test_min_run_matches_library_stable_sort(name, n):
+    keys, _ = getattr(workloads, name)(n=n)
+    pay = np.arange(n, dtype=np.uint32)
+    sk, sp, tr = oracle.sort(keys, pay, k=4, min_run=24)
+    assert np.array_equal(sp, stable_order(keys))
+    assert np.array_equal(sk, keys[stable_order(keys)])
+    check_tree_invariants(tr, 4)
+    if name == "perm_i64":          # natural runs have mean length ~2.5: nearly every run is 24
+        lens = np.diff(tr.run_start.astype(np.int64))
+        assert np.mean(lens[:-1] == 24) > 0.99
