@@ -69,6 +69,14 @@ typedef struct {
     uint32_t lane_slice;        /* outputs each thread merges per LDS stage (tile divided by
                                    the workgroup size): 4 or 8; 0 = 4.  Valid pairs: 1024/4,
                                    2048/8, 2048/4, 4096/8, 4096/4 */
+    uint32_t min_run;           /* minimal run length (Appendix A.3; the paper's experiments
+                                   use 24).  0 or 1: natural runs.  2..32: scanning left to
+                                   right, a natural run shorter than min_run is extended to
+                                   min(n, start + min_run) elements, which are sorted stably
+                                   (the order an insertion sort gives), and the next run
+                                   starts where it ends; powers and the merge tree are those
+                                   of the extended runs.  Single-array sorts only (batched:
+                                   MPS_E_UNSUPPORTED); above 32: MPS_E_UNSUPPORTED. */
 } mps_opts;
 
 /* What the sort did (filled when a trace pointer is passed; forces a stream

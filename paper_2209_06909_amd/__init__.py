@@ -50,13 +50,16 @@ TILE_CONFIGS = [(1024, 4), (2048, 8), (2048, 4), (4096, 8), (4096, 4)]
 class _Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
-                ("tile", ctypes.c_uint32), ("lane_slice", ctypes.c_uint32)]
+                ("tile", ctypes.c_uint32), ("lane_slice", ctypes.c_uint32),
+                ("min_run", ctypes.c_uint32)]
 
 
-def _opts(k, ws, *, time_levels=False, graph=False, tile=None, lane_slice=None) -> _Opts:
+def _opts(k, ws, *, time_levels=False, graph=False, tile=None, lane_slice=None,
+          min_run=1) -> _Opts:
     flags = (OPT_TIME_LEVELS if time_levels else 0) | (OPT_GRAPH if graph else 0)
     return _Opts(k=k, flags=flags, workspace=ws.data_ptr(), workspace_bytes=ws.numel(),
-                 tile=int(tile or 0), lane_slice=int(lane_slice or 0))
+                 tile=int(tile or 0), lane_slice=int(lane_slice or 0),
+                 min_run=int(min_run or 1))
 
 
 class _Trace(ctypes.Structure):
@@ -272,7 +275,7 @@ def _stream_ptr(device, stream):
 
 def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
          stream=None, time_levels: bool = False, graph: bool = False, tile: int | None = None,
-         lane_slice: int | None = None):
+         lane_slice: int | None = None, min_run: int = 1):
     """Stable multiway Powersort of a 1-D GPU tensor, in place.
 
     keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
@@ -280,6 +283,7 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     trace: if True, synchronise and return a Trace (runs, powers, nodes, merge cost).
     graph: capture the launch sequence in a HIP graph (replayed on identical calls).
     tile, lane_slice: merge tile configuration, one of TILE_CONFIGS (default 2048, 4).
+    min_run: minimal run length (Appendix A.3; 1 = natural runs, at most 32).
     """
     _check_tensors(keys, payload)
     kt = key_type_of(keys)
@@ -289,7 +293,8 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
-    opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice)
+    opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice,
+                 min_run=min_run)
     t = _Trace() if trace else None
     _check(lib().mps_sort_ex(ctypes.c_void_p(keys.data_ptr()), kt,
                              ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmps.so")
-SOURCES = ["mps_detect.hip", "mps_tree.hip", "mps_merge.hip", "mps_merge_1024x256.hip",
+SOURCES = ["mps_detect.hip", "mps_minrun.hip", "mps_tree.hip", "mps_merge.hip", "mps_merge_1024x256.hip",
            "mps_merge_2048x256.hip", "mps_merge_2048x512.hip", "mps_merge_4096x512.hip",
            "mps_merge_4096x1024.hip",
            "mps_api.hip", "mps_tune.hip", "mps_serve.hip"]

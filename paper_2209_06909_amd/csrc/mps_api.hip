@@ -77,7 +77,8 @@ struct Layout {
   size_t alt_keys, alt_vals, seg_off, seg_bits, dbits, det_agg, det_zin, det_off, run_start, run_desc,
       power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
       dist0, dist1, leaf_depth, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
-      tj, samples, plan;
+      tj, samples, plan, nat_start, nat_desc, mr_first, mr_nxt, mr_cnt, mr_gnxt, mr_gcnt,
+      mr_gentry, mr_goff, mr_centry, mr_coff;
   uint64_t rmax, nbb, tiles_max, tj_cap;
   int levels;
 };
@@ -150,6 +151,21 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.tile_base = take(c, (kMaxLevels + 1) * 8);
   L.tj_cap = (tiles_max + 1) * (uint64_t)levels + 64;
   L.tj = take(c, L.tj_cap * 4);
+  // single arrays may ask for a minimal run length: room for the natural runs
+  // and the chunk maps that turn them into extended runs
+  const uint64_t nch = m == 1 ? (N + kMrChunk - 1) / kMrChunk : 0;
+  const uint64_t ng = (nch + kMrGroup - 1) / kMrGroup;
+  L.nat_start = take(c, m == 1 ? (rmax + 1) * 8 : 0);
+  L.nat_desc = take(c, m == 1 ? rmax : 0);
+  L.mr_first = take(c, (nch + 1) * 4);
+  L.mr_nxt = take(c, nch * kMrCand);
+  L.mr_cnt = take(c, nch * kMrCand * 2);
+  L.mr_gnxt = take(c, ng * kMrCand);
+  L.mr_gcnt = take(c, ng * kMrCand * 4);
+  L.mr_gentry = take(c, ng);
+  L.mr_goff = take(c, ng * 4);
+  L.mr_centry = take(c, nch);
+  L.mr_coff = take(c, nch * 4);
   L.total = c + 256;
   L.rmax = rmax;
   L.nbb = nbb;
@@ -271,7 +287,16 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
   if (d_off)
     hipLaunchKernelGGL(k_check_offsets, dim3(64), dim3(256), 0, s, d_off, w.m, w.N, w.plan);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(launch_detect(kt, keys, w, s));
+  if (w.min_run > 1) {
+    // natural runs into their own arrays, then the extended runs
+    Work wn = w;
+    wn.run_start = w.nat_start;
+    wn.run_desc = w.nat_desc;
+    HIP_TRY(launch_detect(kt, keys, wn, s));
+    HIP_TRY(launch_minrun(kt, keys, payload, w, s));
+  } else {
+    HIP_TRY(launch_detect(kt, keys, w, s));
+  }
   HIP_TRY(launch_tree(w, want_cost, lvl_tot, tile_base, tj, gtree, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_place(kt, keys, payload, w, s));
@@ -297,13 +322,14 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
 // launch sequence.  Captured on a library stream (capture only records), then
 // launched on the caller's stream.
 struct GraphKey {
-  int dev, kt, k, tile, threads, want_cost;
+  int dev, kt, k, tile, threads, want_cost, min_run;
   const void *keys, *payload, *off, *base;
   uint64_t m, N;
   bool operator<(const GraphKey &o) const {
-    return std::tie(dev, kt, k, tile, threads, want_cost, keys, payload, off, base, m, N) <
-           std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.keys, o.payload, o.off,
-                    o.base, o.m, o.N);
+    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, keys, payload, off, base, m,
+                    N) <
+           std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.min_run, o.keys,
+                    o.payload, o.off, o.base, o.m, o.N);
   }
 };
 std::mutex g_graph_mu;
@@ -367,6 +393,11 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   rc = resolve_tile(opts, tile, threads);
   if (rc) return rc;
   const uint32_t flags = opts ? opts->flags : 0;
+  const uint32_t min_run = opts && opts->min_run > 1 ? opts->min_run : 1;
+  if (min_run > (uint32_t)kMrMaxMinRun)
+    return fail(MPS_E_UNSUPPORTED, "min_run above " + std::to_string(kMrMaxMinRun));
+  if (min_run > 1 && m > 1)
+    return fail(MPS_E_UNSUPPORTED, "a minimal run length applies to single-array sorts only");
   if ((flags & MPS_OPT_GRAPH) && (flags & MPS_OPT_TIME_LEVELS))
     return fail(MPS_E_INVALID, "MPS_OPT_GRAPH cannot be combined with MPS_OPT_TIME_LEVELS");
   Layout L;
@@ -401,6 +432,20 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   w.det_off = at<uint64_t>(base, L.det_off);
   w.run_start = at<uint64_t>(base, L.run_start);
   w.run_desc = at<uint8_t>(base, L.run_desc);
+  w.min_run = (int)min_run;
+  if (m == 1) {
+    w.nat_start = at<uint64_t>(base, L.nat_start);
+    w.nat_desc = at<uint8_t>(base, L.nat_desc);
+    w.mr_first = at<uint32_t>(base, L.mr_first);
+    w.mr_nxt = at<uint8_t>(base, L.mr_nxt);
+    w.mr_cnt = at<uint16_t>(base, L.mr_cnt);
+    w.mr_gnxt = at<uint8_t>(base, L.mr_gnxt);
+    w.mr_gcnt = at<uint32_t>(base, L.mr_gcnt);
+    w.mr_gentry = at<uint8_t>(base, L.mr_gentry);
+    w.mr_goff = at<uint32_t>(base, L.mr_goff);
+    w.mr_centry = at<uint8_t>(base, L.mr_centry);
+    w.mr_coff = at<uint32_t>(base, L.mr_coff);
+  }
   w.power = at<uint8_t>(base, L.power);
   w.ansv_bl = at<uint32_t>(base, L.ansv_bl);
   w.ansv_bf = at<uint32_t>(base, L.ansv_bf);
@@ -434,7 +479,8 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   HIP_TRY(hipGetDevice(&dev));
 
   if (flags & MPS_OPT_GRAPH) {
-    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, keys, payload, d_off, base, m, N};
+    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, keys, payload, d_off,
+                 base, m, N};
     rc = graph_launch(key, keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, s);
     if (rc) return rc;
   } else {

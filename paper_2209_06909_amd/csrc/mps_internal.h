@@ -56,7 +56,16 @@ struct Plan {
   uint32_t q_fast[kMaxLevels];       // work-queue heads of the two merge kernels, per level
   uint32_t q_gen[kMaxLevels];
   uint32_t jump_more[8];             // pointer-jumping round i left a target that is not a root
+  uint64_t r_nat;                    // natural runs, when a minimal run length replaced them
 };
+
+// Minimal run length (runs extended to at least min_run elements): the chain
+// of run starts is resolved in chunks of kMrChunk positions, composed over
+// groups of kMrGroup chunks; each chunk keeps kMrCand candidate entries.
+constexpr int kMrChunk = 4096;
+constexpr int kMrGroup = 256;
+constexpr int kMrMaxMinRun = 32;
+constexpr int kMrCand = kMrMaxMinRun + 1;
 
 // Run-detection block aggregate (16384 positions per block).
 struct DetAgg {
@@ -79,6 +88,16 @@ struct Work {
   uint64_t *det_zin, *det_off;
   uint64_t *run_start;               // [rmax+1]
   uint8_t *run_desc;                 // [rmax]
+  int min_run;                       // 1: natural runs; 2..kMrMaxMinRun: extended runs
+  uint64_t *nat_start;               // [rmax+1] natural runs when min_run > 1 (single arrays)
+  uint8_t *nat_desc;                 // [rmax]
+  uint32_t *mr_first;                // [nch+1] first natural run at or after each chunk start
+  uint8_t *mr_nxt;                   // [nch*kMrCand] exit candidate per chunk and entry
+  uint16_t *mr_cnt;                  // [nch*kMrCand] runs started per chunk and entry
+  uint8_t *mr_gnxt;                  // [ng*kMrCand] the same per group of chunks
+  uint32_t *mr_gcnt;                 // [ng*kMrCand]
+  uint8_t *mr_gentry, *mr_centry;    // [ng], [nch] entry of the chain
+  uint32_t *mr_goff, *mr_coff;       // [ng], [nch] index of the first run started there
   uint8_t *power;                    // [rmax+1], power[0] = power[r] = 0
   uint32_t *ansv_bl, *ansv_bf, *ansv_cl, *ansv_cr;   // [nbb * kVMax]
   uint32_t *Ls, *Rs, *Le, *Re;       // [rmax+1]
@@ -184,6 +203,10 @@ hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s)
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
                        uint32_t *tj, unsigned grid_blocks, hipStream_t s);
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
+// Replaces the natural runs (w.nat_start / w.nat_desc, plan->r) by the runs
+// extended to w.min_run (w.run_start / w.run_desc, plan->r) and sorts the
+// extended runs of keys / vals in place.
+hipError_t launch_minrun(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                         const uint64_t *tile_base, int level, hipStream_t s);
 // The merge launches of one level for one tile configuration (each defined in
