@@ -208,14 +208,28 @@ def bench_perm(args, torch, mps, workloads, tcfg):
     tr = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, **tcfg)
     ms, all_ms = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
                             lambda: mps.sort(keys, pay, k=args.k, **tcfg))
+    out = {"workload": f"perm_i64: uniform random permutation of 0..n-1 as int64 keys, n=2^{args.log2n}, "
+                       "uint32 index payload (seed 3)",
+           "ms": round(ms, 3), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 3),
+           "runs": int(tr.r), "tree_levels": int(tr.n_levels),
+           "merge_cost_per_key": round(tr.merge_cost / n, 4)}
+    if args.perm_min_run > 1:
+        # the paper's own setting: natural runs extended to a minimal length (Appendix A.3)
+        mr = args.perm_min_run
+        keys.copy_(keys0)
+        pay.copy_(pay0)
+        tm = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, min_run=mr, **tcfg)
+        ms_m, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
+                             lambda: mps.sort(keys, pay, k=args.k, min_run=mr, **tcfg))
+        out[f"min_run_{mr}"] = {
+            "ms": round(ms_m, 3), "gkeys_s": round(n / (ms_m * 1e-3) / 1e9, 3),
+            "runs": int(tm.r), "tree_levels": int(tm.n_levels),
+            "merge_cost_per_key": round(tm.merge_cost / n, 4),
+            "speedup_vs_natural_runs": round(ms / ms_m, 3)}
     del keys0, pay0, keys, pay
     mps.release_workspaces()
     torch.cuda.empty_cache()
-    return {"workload": f"perm_i64: uniform random permutation of 0..n-1 as int64 keys, n=2^{args.log2n}, "
-                        "uint32 index payload (seed 3)",
-            "ms": round(ms, 3), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 3),
-            "runs": int(tr.r), "tree_levels": int(tr.n_levels),
-            "merge_cost_per_key": round(tr.merge_cost / n, 4)}
+    return out
 
 
 def bench_serving(args, torch, mps, workloads):
@@ -338,6 +352,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-k-sweep", action="store_true")
     ap.add_argument("--no-perm", action="store_true", help="skip the random-permutation variant")
+    ap.add_argument("--perm-min-run", type=int, default=24,
+                    help="also time the permutation with this minimal run length (<= 1: skip)")
     ap.add_argument("--batched-m", type=int, default=8192, help="arrays in the batched workload")
     ap.add_argument("--batched-reps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")

@@ -26,7 +26,7 @@
 // chunk it leaves by.  These maps are composed over groups of kMrGroup chunks,
 // then over the groups from chunk 0's entry 0; each chunk finally re-walks its
 // actual entry and writes its run starts.  The runs that were extended are
-// then sorted in place by a stable rank sort in LDS.
+// then sorted in place by a stable rank sort in registers, staged through LDS.
 #include "mps_internal.h"
 
 namespace mps {
@@ -36,7 +36,7 @@ constexpr int kMrThreads = 256;
 constexpr int kMrStage = kMrChunk / 2 + 8;   // natural runs staged per chunk (>= chunk/2 + 4)
 constexpr uint8_t kMrEnd = 254;              // the chain has reached n
 constexpr uint8_t kMrBad = 255;              // unused candidate
-constexpr int kMrSortRuns = 128;             // runs per window-sort block
+constexpr int kMrSortRuns = 128;             // runs per workgroup of the run sort
 
 // Natural runs that overlap [c0 - 1, c1) of chunk c, plus the next two
 // starts, staged as 32-bit positions (n <= 2^31).
@@ -399,86 +399,130 @@ __global__ __launch_bounds__(kMrThreads) void k_mr_emit(
   }
 }
 
-// Sorts every extended run in place: runs of 2..m elements that are not
-// monotone in the input (a run left whole is weakly increasing or strictly
-// decreasing; an extended one is neither).  Each element's place is the
-// number of elements of its run that are smaller, or equal and earlier:
-// the order a stable insertion sort gives.  Written positions that carry a
-// co-rank sample refresh it.
-template <int KT>
-__global__ __launch_bounds__(kMrThreads) void k_mr_sort(typename Key<KT>::U *__restrict__ keys,
-                                                        uint32_t *__restrict__ vals,
-                                                        const uint64_t *__restrict__ rs,
-                                                        const Plan *__restrict__ plan, uint32_t m,
-                                                        uint64_t *__restrict__ smp) {
+// The stable rank sort of one run of len <= W elements held in registers
+// (the unused slots are padded with the largest key, which never precedes a
+// real key).  Runs that are monotone (a run left whole is weakly increasing or
+// strictly decreasing; an extended one is neither) are left alone.  Each
+// element's place is the number of elements that are smaller, or equal and
+// earlier: the order a stable insertion sort gives.
+template <typename U, int W, typename Load, typename Store>
+__device__ inline void rank_sort_run(uint32_t len, Load ld, Store st) {
+  U k[W];
+  uint32_t v[W];
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    k[i] = (U)~(U)0;
+    v[i] = 0;
+    if ((uint32_t)i < len) ld(i, k[i], v[i]);
+  }
+  bool up = true, dn = true;
+#pragma unroll
+  for (int i = 0; i + 1 < W; i++) {
+    if ((uint32_t)(i + 1) < len) {
+      up = up && !(k[i + 1] < k[i]);
+      dn = dn && (k[i + 1] < k[i]);
+    }
+  }
+  if (up || dn) return;
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    if ((uint32_t)i < len) {
+      uint32_t rank = 0;
+#pragma unroll
+      for (int q = 0; q < W; q++) {
+        if (q < i) rank += k[q] <= k[i];
+        else if (q > i) rank += k[q] < k[i];
+      }
+      st(rank, k[i], v[i]);
+    }
+  }
+}
+
+// Sorts the extended runs in place.  A workgroup takes kMrSortRuns
+// consecutive runs; when their span fits in LDS it is staged there with
+// coalesced loads, each thread sorts its own run between LDS and registers,
+// and the span is stored back coalesced (positions that carry a co-rank
+// sample refresh it).  A longer span (a long natural run among them) is
+// handled run by run straight from memory.
+template <int KT, int W>
+__global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__restrict__ keys,
+                                                         uint32_t *__restrict__ vals,
+                                                         const uint64_t *__restrict__ rs,
+                                                         const Plan *__restrict__ plan,
+                                                         uint32_t m, uint64_t *__restrict__ smp) {
   using U = typename Key<KT>::U;
-  constexpr int kMaxW = kMrSortRuns * kMrMaxMinRun;
-  __shared__ U sk[kMaxW];
-  __shared__ uint32_t sv[kMaxW];
-  __shared__ uint32_t s_start[kMrSortRuns + 1];
-  __shared__ int woff[kMrSortRuns + 1];
-  __shared__ int up[kMrSortRuns], dn[kMrSortRuns];
-  __shared__ int scan[kMrThreads / 64];
   constexpr uint64_t SM = kSampleStride - 1;
+  constexpr uint32_t kCap = kMrSortRuns * W;
+  __shared__ U sk[kCap];
+  __shared__ uint32_t sv[kCap];
   const int t = threadIdx.x;
   const uint64_t r = plan->r;
   for (uint64_t j0 = (uint64_t)blockIdx.x * kMrSortRuns; j0 < r;
        j0 += (uint64_t)gridDim.x * kMrSortRuns) {
-    const int nr = (int)(r - j0 < (uint64_t)kMrSortRuns ? r - j0 : kMrSortRuns);
-    int w = 0;
-    if (t < nr) {
-      const uint64_t s = rs[j0 + t], e = rs[j0 + t + 1];
-      s_start[t] = (uint32_t)s;
-      w = (e - s >= 2 && e - s <= m) ? (int)(e - s) : 0;
-      up[t] = 1;
-      dn[t] = 1;
+    const uint64_t j1 = j0 + kMrSortRuns < r ? j0 + kMrSortRuns : r;
+    const uint64_t S0 = rs[j0], span = rs[j1] - S0;
+    const uint64_t j = j0 + t;
+    uint64_t s = 0;
+    uint32_t len = 0;
+    if (j < j1) {
+      s = rs[j];
+      len = (uint32_t)(rs[j + 1] - s);
     }
-    int tot;
-    const int pre = block_excl_scan(w, scan, tot);
-    if (t < nr) woff[t] = pre;
-    if (t == 0) woff[nr] = tot;
-    __syncthreads();
-    for (int x = t; x < tot; x += kMrThreads) {
-      int lo = 0, hi = nr - 1;   // window holding x
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (woff[mid] <= x) lo = mid; else hi = mid - 1;
+    const bool mine = len >= 2 && len <= m;
+    if (span <= kCap) {
+      const uint32_t sp = (uint32_t)span;
+      for (uint32_t x = t; x < sp; x += kMrSortRuns) {
+        sk[x] = Key<KT>::ord(keys[S0 + x]);
+        if (vals) sv[x] = vals[S0 + x];
       }
-      const uint64_t p = (uint64_t)s_start[lo] + (uint64_t)(x - woff[lo]);
-      sk[x] = Key<KT>::ord(keys[p]);
-      if (vals) sv[x] = vals[p];
+      __syncthreads();
+      if (mine) {
+        const uint32_t o = (uint32_t)(s - S0);
+        rank_sort_run<U, W>(
+            len,
+            [&](int i, U &kk, uint32_t &vv) {
+              kk = sk[o + i];
+              if (vals) vv = sv[o + i];
+            },
+            [&](uint32_t rank, U kk, uint32_t vv) {
+              sk[o + rank] = kk;
+              if (vals) sv[o + rank] = vv;
+            });
+      }
+      __syncthreads();
+      for (uint32_t x = t; x < sp; x += kMrSortRuns) {
+        const U kk = sk[x];
+        keys[S0 + x] = Key<KT>::unord(kk);
+        if (vals) vals[S0 + x] = sv[x];
+        if (((S0 + x) & SM) == 0) smp[(S0 + x) / kSampleStride] = (uint64_t)kk;
+      }
+      __syncthreads();
+    } else if (mine) {
+      rank_sort_run<U, W>(
+          len,
+          [&](int i, U &kk, uint32_t &vv) {
+            kk = Key<KT>::ord(keys[s + i]);
+            if (vals) vv = vals[s + i];
+          },
+          [&](uint32_t rank, U kk, uint32_t vv) {
+            const uint64_t dst = s + rank;
+            keys[dst] = Key<KT>::unord(kk);
+            if (vals) vals[dst] = vv;
+            if ((dst & SM) == 0) smp[dst / kSampleStride] = (uint64_t)kk;
+          });
     }
-    __syncthreads();
-    for (int x = t; x < tot; x += kMrThreads) {
-      int lo = 0, hi = nr - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (woff[mid] <= x) lo = mid; else hi = mid - 1;
-      }
-      if (x + 1 < woff[lo + 1]) {
-        if (sk[x + 1] < sk[x]) up[lo] = 0;
-        if (!(sk[x + 1] < sk[x])) dn[lo] = 0;
-      }
-    }
-    __syncthreads();
-    for (int x = t; x < tot; x += kMrThreads) {
-      int lo = 0, hi = nr - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (woff[mid] <= x) lo = mid; else hi = mid - 1;
-      }
-      if (up[lo] || dn[lo]) continue;
-      const int wb = woff[lo], we = woff[lo + 1];
-      const U v = sk[x];
-      int rank = 0;
-      for (int q = wb; q < we; q++) rank += (sk[q] < v) || (sk[q] == v && q < x);
-      const uint64_t dst = (uint64_t)s_start[lo] + (uint64_t)rank;
-      keys[dst] = Key<KT>::unord(v);
-      if (vals) vals[dst] = sv[x];
-      if ((dst & SM) == 0) smp[dst / kSampleStride] = (uint64_t)v;
-    }
-    __syncthreads();
   }
+}
+
+template <int W>
+hipError_t launch_mr_sort(int kt, void *keys, uint32_t *vals, const Work &w, uint32_t m,
+                          unsigned gs, hipStream_t s) {
+  switch (kt) {
+    case 0: hipLaunchKernelGGL((k_mr_sort<0, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
+    case 1: hipLaunchKernelGGL((k_mr_sort<1, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint64_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
+    default: hipLaunchKernelGGL((k_mr_sort<2, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
+  }
+  return hipGetLastError();
 }
 
 unsigned grid_for(uint64_t items, uint64_t per, unsigned cap) {
@@ -507,13 +551,11 @@ hipError_t launch_minrun(int kt, void *keys, uint32_t *vals, const Work &w, hipS
   hipLaunchKernelGGL(k_mr_emit, dim3(grid_for(nch, 1, 8192)), dim3(kMrThreads), 0, s,
                      w.nat_start, w.nat_desc, w.plan, (uint32_t)N, m, nch, w.mr_first, w.mr_centry,
                      w.mr_coff, w.rmax, w.run_start, w.run_desc);
-  const unsigned gs = grid_for(N / 2 + 2, kMrSortRuns, 8192);
-  switch (kt) {
-    case 0: hipLaunchKernelGGL(k_mr_sort<0>, dim3(gs), dim3(kMrThreads), 0, s, (uint32_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
-    case 1: hipLaunchKernelGGL(k_mr_sort<1>, dim3(gs), dim3(kMrThreads), 0, s, (uint64_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
-    default: hipLaunchKernelGGL(k_mr_sort<2>, dim3(gs), dim3(kMrThreads), 0, s, (uint32_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
-  }
-  return hipGetLastError();
+  const unsigned gs = grid_for(N / 2 + 2, kMrSortRuns, 16384);
+  if (m <= 8) return launch_mr_sort<8>(kt, keys, vals, w, m, gs, s);
+  if (m <= 16) return launch_mr_sort<16>(kt, keys, vals, w, m, gs, s);
+  if (m <= 24) return launch_mr_sort<24>(kt, keys, vals, w, m, gs, s);
+  return launch_mr_sort<32>(kt, keys, vals, w, m, gs, s);
 }
 
 }  // namespace mps
