@@ -799,6 +799,8 @@ __device__ inline void store_tile2(const O *ks, const uint32_t *vs, O *out_keys,
 // waits for the claim's return, which also waits for all of its outstanding
 // memory operations, so claims should be rare.
 constexpr int kFastClaim = 8;
+// Tiles per claim of the general kernel (its tiles are fewer and longer).
+constexpr int kGenClaim = 4;
 
 // Descriptor tiles.  Each workgroup takes tiles from the level's work queue
 // (kFastClaim at a time, skipping those of the general path) and processes
@@ -933,11 +935,19 @@ __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
   const int lane = t & 63, wave = t >> 6;
   uint64_t ga[E];
 
+  // Tiles are claimed kGenClaim at a time: a claim's returned value makes the
+  // wave wait for all of its outstanding memory operations.
   uint32_t *queue = &plan->q_gen[level];
+  uint32_t cbase = 0;
+  int cidx = kGenClaim;
   for (;;) {
-    if (t == 0) sm.misc[5] = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    const uint32_t gi = (uint32_t)sm.misc[5];
+    if (cidx == kGenClaim) {
+      if (t == 0) sm.misc[5] = (int)atomicAdd(queue, (uint32_t)kGenClaim);
+      __syncthreads();
+      cbase = (uint32_t)sm.misc[5];
+      cidx = 0;
+    }
+    const uint32_t gi = cbase + (uint32_t)cidx++;
     if (gi >= ngen) break;
     const uint64_t tile = gen_list[gi];
     TileGeom g = tile_geom(tile, TILE, L, nlev, np, lb, np0, tjl);
