@@ -59,6 +59,26 @@ def test_argument_errors_need_no_gpu():
                                 None) == -4
 
 
+def test_min_run_argument_errors_need_no_gpu():
+    """min_run above 32, or with several arrays, is rejected before the
+    workspace or the GPU is touched; 0 and 1 both mean natural runs."""
+    lib = mps.lib()
+    fake = ctypes.c_void_p(1 << 40)                                        # never dereferenced
+    opts = mps._Opts(k=4, min_run=33)
+    assert lib.mps_sort_ex(fake, mps.KEY_I64, None, 1000, ctypes.byref(opts), None, None) == -4
+    assert b"min_run" in lib.mps_last_error()
+    opts = mps._Opts(k=4, min_run=24)
+    off = (ctypes.c_uint64 * 3)(0, 500, 1000)
+    assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 2, 1000, ctypes.byref(opts),
+                                None, None) == -4
+    assert b"single-array" in lib.mps_last_error()
+    opts = mps._Opts(k=4, min_run=24)                                      # n <= 1: a no-op
+    assert lib.mps_sort_ex(fake, mps.KEY_I64, None, 1, ctypes.byref(opts), None, None) == 0
+    # a single-array workspace has room for the natural runs and chunk maps
+    assert (lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I64, 1, 4)
+            > lib.mps_workspace_bytes(1 << 20, 2, mps.KEY_I64, 1, 4) + 8 * (1 << 19))
+
+
 def test_serve_host_selftest():
     """The request server's arena allocator and batch-formation policy (host code,
     no GPU): first-fit allocation, coalescing, accounting under random churn, and
