@@ -232,6 +232,27 @@ def bench_perm(args, torch, mps, workloads, tcfg):
     return out
 
 
+def bench_records(args, torch, mps, keys0, tcfg):
+    """16-byte records, the paper's key-and-pointer records (Section 4): the headline's
+    int64 keys with an 8-byte payload (each record's index), sorted with k = 4 and k = 2
+    (mps_sort_kv64: the merges carry a 4-byte record index, the payload is gathered once)."""
+    n = keys0.numel()
+    pay0 = torch.arange(n, dtype=torch.int64, device=keys0.device)
+    keys, pay = keys0.clone(), pay0.clone()
+    res = {"workload": f"the headline keys (runs_i64, n=2^{args.log2n}) with an int64 payload "
+                       "holding each record's index", "record_bytes": 16}
+    for kk in (4, 2):
+        t, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
+                          lambda: mps.sort(keys, pay, k=kk, **tcfg))
+        res[f"k{kk}"] = {"ms": round(t, 3), "gkeys_s": round(n / (t * 1e-3) / 1e9, 3)}
+    res["time_ratio_k4_over_k2"] = round(res["k4"]["ms"] / res["k2"]["ms"], 4)
+    res["output_checked"] = bool((keys[1:] >= keys[:-1]).all().item()) and \
+        bool((keys0[pay] == keys).all().item())
+    del pay0, keys, pay
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(args, torch, mps, workloads):
     """Serving: a pool of float32 requests (sizes log-uniform in [2^10, 2^26], random runs,
     ~1% duplicate keys, index payload) resident on the GPU.  (1) Closed loop: every pool
@@ -352,6 +373,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-k-sweep", action="store_true")
     ap.add_argument("--no-perm", action="store_true", help="skip the random-permutation variant")
+    ap.add_argument("--no-records", action="store_true",
+                    help="skip the 16-byte-record variant (8-byte payload)")
     ap.add_argument("--perm-min-run", type=int, default=24,
                     help="also time the permutation with this minimal run length (<= 1: skip)")
     ap.add_argument("--batched-m", type=int, default=8192, help="arrays in the batched workload")
@@ -522,6 +545,8 @@ def main():
             "merge_cost_workload": "n=10^8 int32, random runs of mean length 10^4 (Table 1)",
             "this_gpu": {"time_ratio_k4_over_k2": round(t4 / t2, 4),
                          "merge_cost_ratio_k4_over_k2": round(m4 / m2, 4)}}
+    if not args.no_records:
+        out["records16"] = bench_records(args, torch, mps, keys0, tcfg)
     if not args.no_perm:
         out["perm_variant"] = bench_perm(args, torch, mps, workloads, tcfg)
     if not args.no_cpu_baseline:

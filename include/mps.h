@@ -104,7 +104,9 @@ typedef struct {
 } mps_trace;
 
 /* Bytes of device workspace needed to sort n elements in m arrays with the
- * given key type, payload presence and arity.  Returns 0 on bad arguments. */
+ * given key type, payload and arity.  has_payload: 0 none, 1 a u32 payload,
+ * 2 a u64 payload (mps_sort_kv64, single arrays only).  Returns 0 on bad
+ * arguments. */
 uint64_t mps_workspace_bytes(uint64_t n, uint64_t m, mps_key_type kt, int has_payload,
                              uint32_t k);
 
@@ -121,6 +123,17 @@ int mps_sort_f32(float *keys, uint32_t *payload, uint64_t n, void *stream);
 /* mps_sort with options and an optional trace (trace may be NULL). */
 int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
                 const mps_opts *opts, mps_trace *trace, void *stream);
+
+/* Records of a key and an 8-byte payload, such as the key-and-pointer records
+ * of the paper's experiments with 16-byte records (Section 4): the stable sort
+ * of mps_sort_ex, with payload (device, n u64) permuted with the keys.  The
+ * merges carry each record's 4-byte index; the payload is gathered once after
+ * the last merge, through a buffer in the workspace (mps_workspace_bytes with
+ * has_payload = 2: 12 bytes per key more than a u32 payload).  Options, trace,
+ * limits and errors as mps_sort_ex; payload NULL or n <= 1 is mps_sort_ex
+ * without a payload. */
+int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uint64_t n,
+                  const mps_opts *opts, mps_trace *trace, void *stream);
 
 /* Batched: m independent arrays packed back to back, array i occupying
  * [offsets[i], offsets[i+1]) of keys/payload (offsets: device uint64[m+1],

@@ -29,7 +29,7 @@ _STATUS = {-1: "MPS_E_INVALID", -2: "MPS_E_NOMEM", -3: "MPS_E_HIP", -4: "MPS_E_U
 KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
 
 EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
-            "mps_sort_ex", "mps_sort_batched", "mps_autotune", "mps_trace_fetch",
+            "mps_sort_ex", "mps_sort_kv64", "mps_sort_batched", "mps_autotune", "mps_trace_fetch",
             "mps_last_level_stats", "mps_serve_create", "mps_serve_submit", "mps_serve_poll",
             "mps_serve_release", "mps_serve_stats", "mps_serve_destroy", "mps_serve_selftest",
             "mps_last_error"]
@@ -127,6 +127,8 @@ def lib() -> ctypes.CDLL:
                 getattr(l, name).restype = i32
             l.mps_sort_ex.argtypes = [P, i32, P, u64, ctypes.POINTER(_Opts), ctypes.POINTER(_Trace), P]
             l.mps_sort_ex.restype = i32
+            l.mps_sort_kv64.argtypes = [P, i32, P, u64, ctypes.POINTER(_Opts), ctypes.POINTER(_Trace), P]
+            l.mps_sort_kv64.restype = i32
             l.mps_sort_batched.argtypes = [P, i32, P, P, P, u64, u64, ctypes.POINTER(_Opts),
                                            ctypes.POINTER(_Trace), P]
             l.mps_sort_batched.restype = i32
@@ -175,7 +177,7 @@ def key_type_of(t) -> int:
     return kt
 
 
-def workspace_bytes(n: int, m: int = 1, key_type: int = KEY_I32, has_payload: bool = True,
+def workspace_bytes(n: int, m: int = 1, key_type: int = KEY_I32, has_payload: int = 1,
                     k: int = 4) -> int:
     return int(lib().mps_workspace_bytes(n, m, key_type, int(has_payload), k))
 
@@ -213,8 +215,8 @@ def _check_tensors(keys, payload):
     if not keys.is_contiguous():
         raise ValueError("keys must be contiguous")
     if payload is not None:
-        if payload.dtype not in (torch.int32, torch.uint32):
-            raise TypeError("payload must be int32 or uint32 (4 bytes per key)")
+        if payload.dtype not in (torch.int32, torch.uint32, torch.int64):
+            raise TypeError("payload must be int32/uint32 (4 bytes per key) or int64 (8 bytes)")
         if payload.device != keys.device or not payload.is_contiguous():
             raise ValueError("payload must be contiguous and on the keys' device")
         if payload.numel() != keys.numel():
@@ -279,7 +281,8 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     """Stable multiway Powersort of a 1-D GPU tensor, in place.
 
     keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
-    payload: optional int32/uint32 tensor of the same length, permuted with the keys.
+    payload: optional int32/uint32 tensor of the same length, permuted with the keys; an
+        int64 payload (8-byte records such as pointers) goes through mps_sort_kv64.
     trace: if True, synchronise and return a Trace (runs, powers, nodes, merge cost).
     graph: capture the launch sequence in a HIP graph (replayed on identical calls).
     tile, lane_slice: merge tile configuration, one of TILE_CONFIGS (default 2048, 4).
@@ -289,14 +292,16 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     kt = key_type_of(keys)
     n = keys.numel()
     dev = keys.device
-    need = workspace_bytes(max(n, 2), 1, kt, payload is not None, k)
+    wide = payload is not None and payload.element_size() == 8
+    need = workspace_bytes(max(n, 2), 1, kt, 2 if wide else int(payload is not None), k)
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
     opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice,
                  min_run=min_run)
     t = _Trace() if trace else None
-    _check(lib().mps_sort_ex(ctypes.c_void_p(keys.data_ptr()), kt,
+    entry = lib().mps_sort_kv64 if wide else lib().mps_sort_ex
+    _check(entry(ctypes.c_void_p(keys.data_ptr()), kt,
                              ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
                              n, ctypes.byref(opts), ctypes.byref(t) if t is not None else None,
                              _stream_ptr(dev, stream)))

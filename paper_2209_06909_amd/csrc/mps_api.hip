@@ -37,6 +37,26 @@ __global__ void k_init(Plan *plan, uint64_t *seg_off, uint64_t n, uint64_t m, ui
   }
 }
 
+// Records with an 8-byte payload: the sort carries the u32 index of every
+// record; the payload is gathered once at the end.
+__global__ __launch_bounds__(256) void k_iota32(uint32_t *__restrict__ idx, uint64_t n) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
+    idx[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_gather64(const uint64_t *__restrict__ src,
+                                                  const uint32_t *__restrict__ idx,
+                                                  uint64_t *__restrict__ dst, uint64_t n) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
+    dst[i] = src[idx[i]];
+}
+
+__global__ __launch_bounds__(256) void k_copy64(const uint64_t *__restrict__ src,
+                                                uint64_t *__restrict__ dst, uint64_t n) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
+    dst[i] = src[i];
+}
+
 __global__ void k_check_offsets(const uint64_t *off, uint64_t m, uint64_t total, Plan *plan) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (uint64_t)gridDim.x * blockDim.x) {
@@ -99,6 +119,10 @@ int levels_for(uint64_t n, uint32_t k) {
   }
   return p < 1 ? 1 : p;
 }
+
+// Bytes after a sort's workspace for records with an 8-byte payload: the u32
+// record indices and the gather buffer, each 256-byte aligned.
+uint64_t record_extra(uint64_t n) { return 256 + ((n * 4 + 255) & ~(uint64_t)255) + n * 8 + 256; }
 
 bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layout &L) {
   if (N == 0 || m == 0) return false;
@@ -514,9 +538,11 @@ extern "C" uint64_t mps_workspace_bytes(uint64_t n, uint64_t m, mps_key_type kt,
   if (k == 0) k = 4;
   if (k != 2 && k != 4 && k != 8) return 0;
   if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return 0;
+  if (has_payload < 0 || has_payload > 2 || (has_payload == 2 && m > 1)) return 0;
   Layout L;
   if (!make_layout(n < 2 ? 2 : n, m < 1 ? 1 : m, kt, has_payload != 0, k, L)) return 0;
-  return L.total;
+  // 8-byte payloads: the record indices and a gather buffer follow the sort's part
+  return has_payload == 2 ? L.total + record_extra(n < 2 ? 2 : n) : L.total;
 }
 
 extern "C" int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
@@ -546,6 +572,56 @@ extern "C" int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint6
     return MPS_OK;
   }
   return run_sort(keys, kt, payload, nullptr, 1, n, opts, trace, (hipStream_t)stream);
+}
+
+extern "C" int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uint64_t n,
+                             const mps_opts *opts, mps_trace *trace, void *stream) {
+  g_err.clear();
+  if (!payload || n <= 1) return mps_sort_ex(keys, kt, nullptr, n, opts, trace, stream);
+  if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
+  if (!keys) return fail(MPS_E_INVALID, "keys is NULL");
+  if (n > (1ull << 31)) return fail(MPS_E_UNSUPPORTED, "arrays longer than 2^31 are not supported");
+  uint32_t k = opts ? opts->k : 0;
+  int rc = check_k(k);
+  if (rc) return rc;
+  Layout L;
+  if (!make_layout(n, 1, kt, true, k, L)) return fail(MPS_E_INVALID, "bad sizes");
+  const uint64_t need = L.total + record_extra(n);
+  void *base = nullptr;
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < need)
+      return fail(MPS_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    base = opts->workspace;
+  } else {
+    rc = get_workspace(need, &base);
+    if (rc) return rc;
+  }
+  char *ex = static_cast<char *>(base) + L.total;
+  ex = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ex) + 255) & ~(uintptr_t)255);
+  uint32_t *idx = reinterpret_cast<uint32_t *>(ex);
+  uint64_t *tmp = reinterpret_cast<uint64_t *>(ex + ((n * 4 + 255) & ~(uint64_t)255));
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned g = (unsigned)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+  hipLaunchKernelGGL(k_iota32, dim3(g), dim3(256), 0, s, idx, n);
+  HIP_TRY(hipGetLastError());
+  mps_opts o{};
+  if (opts) o = *opts;
+  o.workspace = base;
+  o.workspace_bytes = L.total;
+  rc = run_sort(keys, kt, idx, nullptr, 1, n, &o, trace, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_gather64, dim3(g), dim3(256), 0, s, (const uint64_t *)payload,
+                     (const uint32_t *)idx, tmp, n);
+  hipLaunchKernelGGL(k_copy64, dim3(g), dim3(256), 0, s, (const uint64_t *)tmp, payload, n);
+  HIP_TRY(hipGetLastError());
+  if (!(opts && opts->workspace)) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64) {
+      g_last_base[dev] = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(base) + 255) & ~(uintptr_t)255);
+    }
+  }
+  return MPS_OK;
 }
 
 extern "C" int mps_sort(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n, void *stream) {
