@@ -85,7 +85,7 @@ def lib():
         l.oracle_powers.restype = i32
         l.oracle_sort.argtypes = [P, i32, P, u64, u32, ctypes.POINTER(_Trace)]
         l.oracle_sort.restype = i32
-        l.oracle_sort_ex.argtypes = [P, i32, P, u64, u32, u32, ctypes.POINTER(_Trace)]
+        l.oracle_sort_ex.argtypes = [P, i32, P, u64, u32, u32, i32, ctypes.POINTER(_Trace)]
         l.oracle_sort_ex.restype = i32
         l.oracle_runs_min.argtypes = [P, i32, P, u64, u32, P, P]
         l.oracle_runs_min.restype = u64
@@ -95,6 +95,8 @@ def lib():
         l.oracle_kway_tree.restype = ctypes.c_int64
         l.oracle_tree_from_runs.argtypes = [P, u64, u32, ctypes.POINTER(_Trace)]
         l.oracle_tree_from_runs.restype = i32
+        l.oracle_tree_from_runs_ex.argtypes = [P, u64, u32, i32, ctypes.POINTER(_Trace)]
+        l.oracle_tree_from_runs_ex.restype = i32
         l.oracle_sort_many.argtypes = [P, i32, P, P, u64, u32, P]
         l.oracle_sort_many.restype = i32
         l.oracle_key_cmp.argtypes = [P, i32, u64, u64]
@@ -196,27 +198,31 @@ def powers(run_start: np.ndarray, k: int) -> np.ndarray:
     return out
 
 
-def sort(keys: np.ndarray, payload: np.ndarray | None = None, k: int = 4, min_run: int = 1):
+def sort(keys: np.ndarray, payload: np.ndarray | None = None, k: int = 4, min_run: int = 1,
+         merge_down: bool = False):
     """Stable k-way Powersort (Algorithm 2).  Returns (keys, payload, Trace); inputs are copied.
 
-    min_run > 1 extends short runs first (Appendix A.3)."""
+    min_run > 1 extends short runs first (Appendix A.3); merge_down uses the
+    final phase of Appendix A.3 (s mod (k-1) entries first, then k-way)."""
     keys = np.array(keys, copy=True, order="C")
     pl = None if payload is None else np.array(payload, dtype=np.uint32, copy=True, order="C")
     if pl is not None and pl.size != keys.size:
         raise ValueError("payload size mismatch")
     t = _Trace()
     rc = lib().oracle_sort_ex(_ptr(keys), _kt(keys), None if pl is None else _ptr(pl),
-                              keys.size, k, max(int(min_run), 1), ctypes.byref(t))
+                              keys.size, k, max(int(min_run), 1), int(bool(merge_down)),
+                              ctypes.byref(t))
     if rc:
         raise RuntimeError(f"oracle_sort failed ({rc})")
     return keys, pl, _take_trace(t)
 
 
-def tree_from_runs(run_start: np.ndarray, k: int) -> Trace:
+def tree_from_runs(run_start: np.ndarray, k: int, merge_down: bool = False) -> Trace:
     """Algorithm 2's merge tree for a given run partition (no element movement)."""
     rs = np.ascontiguousarray(run_start, dtype=np.uint64)
     t = _Trace()
-    rc = lib().oracle_tree_from_runs(_ptr(rs), rs.size - 1, k, ctypes.byref(t))
+    rc = lib().oracle_tree_from_runs_ex(_ptr(rs), rs.size - 1, k, int(bool(merge_down)),
+                                        ctypes.byref(t))
     if rc:
         raise RuntimeError(f"oracle_tree_from_runs failed ({rc})")
     return _take_trace(t)

@@ -260,15 +260,14 @@ typedef struct {
     uint64_t top;               /* number of entries (the power-0 sentinel is implicit) */
     uint64_t max_stack;
     uint64_t merge_cost;
+    uint32_t k;
+    int merge_down;             /* final phase of Appendix A.3 instead of Algorithm 2's */
 } policy;
 
-/* Pops the whole group of top entries that share the top power and merges
- * them together with the current segment, as in the inner loop of
- * Algorithm 2.  The merged segment becomes the current segment. */
-static int merge_group(policy *pl, stack_entry *cur) {
-    uint32_t pw = pl->stack[pl->top - 1].power;
-    uint64_t g = 0;
-    while (g < pl->top && pl->stack[pl->top - 1 - g].power == pw) g++;
+/* Pops the top g entries and merges them together with the current segment;
+ * the merged segment becomes the current segment.  The new node records the
+ * power pw. */
+static int merge_top(policy *pl, stack_entry *cur, uint64_t g, uint32_t pw) {
     uint32_t d = (uint32_t)g + 1;
     if (d > 64) return -1;
     stack_entry parts[64];
@@ -302,6 +301,38 @@ static int merge_group(policy *pl, stack_entry *cur) {
     return 0;
 }
 
+/* Pops the whole group of top entries that share the top power and merges
+ * them together with the current segment, as in the inner loop of
+ * Algorithm 2. */
+static int merge_group(policy *pl, stack_entry *cur) {
+    uint32_t pw = pl->stack[pl->top - 1].power;
+    uint64_t g = 0;
+    while (g < pl->top && pl->stack[pl->top - 1 - g].power == pw) g++;
+    return merge_top(pl, cur, g, pw);
+}
+
+/* The final phase of the 4-way implementation in Appendix A.3 ("merge
+ * down"), for any k: with s entries left on the stack there are s + 1 runs;
+ * first the top e = s mod (k-1) entries are merged with the current segment
+ * (a 2- or 3-way merge for k = 4), so that every later merge takes k - 1
+ * entries, a k-way merge.  A node made here records the power of its first
+ * boundary (the boundary right of its first child). */
+static uint32_t first_boundary_power(const policy *pl, const stack_entry *cur, uint64_t g) {
+    uint64_t b = g >= 2 ? pl->stack[pl->top - g + 1].first_run : cur->first_run;
+    return pl->power[b - 1];
+}
+
+static int merge_down(policy *pl, stack_entry *cur) {
+    uint64_t km1 = pl->k - 1;
+    uint64_t e = pl->top % km1;
+    if (e > 0 && merge_top(pl, cur, e, first_boundary_power(pl, cur, e))) return -1;
+    while (pl->top > 0) {
+        uint64_t g = pl->top < km1 ? pl->top : km1;
+        if (merge_top(pl, cur, g, first_boundary_power(pl, cur, g))) return -1;
+    }
+    return 0;
+}
+
 static int run_policy(policy *pl) {
     uint64_t r = pl->r;
     if (r == 0) return 0;
@@ -316,6 +347,7 @@ static int run_policy(policy *pl) {
         stack_entry next = {pl->run_start[i], pl->run_start[i + 1], i, -1, 0};
         cur = next;
     }
+    if (pl->merge_down) return merge_down(pl, &cur);
     /* Final phase: keep merging whole equal-power groups, exactly as if one
      * more boundary of power 0 (below every real power) arrived. */
     while (pl->top > 0)
@@ -333,7 +365,8 @@ static void fill_depths(oracle_node *nodes, uint64_t n_nodes) {
 }
 
 static int build_trace(const uint64_t *run_start, uint64_t r, uint32_t k,
-                       const uint8_t *power_in, mover *mv, oracle_trace *tr) {
+                       const uint8_t *power_in, mover *mv, int merge_down,
+                       oracle_trace *tr) {
     memset(tr, 0, sizeof *tr);
     tr->r = r;
     tr->k = k;
@@ -373,6 +406,8 @@ static int build_trace(const uint64_t *run_start, uint64_t r, uint32_t k,
     pl.boundary_node = tr->boundary_node;
     pl.leaf_parent = leaf_parent;
     pl.stack = stack;
+    pl.k = k;
+    pl.merge_down = merge_down;
     int rc = run_policy(&pl);
     if (rc == 0) {
         tr->n_nodes = pl.n_nodes;
@@ -392,16 +427,22 @@ static int build_trace(const uint64_t *run_start, uint64_t r, uint32_t k,
 int oracle_tree_from_runs(const uint64_t *run_start, uint64_t r, uint32_t k,
                           oracle_trace *trace) {
     if (!run_start || !trace || k < 2) return -1;
-    return build_trace(run_start, r, k, NULL, NULL, trace);
+    return build_trace(run_start, r, k, NULL, NULL, 0, trace);
+}
+
+int oracle_tree_from_runs_ex(const uint64_t *run_start, uint64_t r, uint32_t k,
+                             int merge_down, oracle_trace *trace) {
+    if (!run_start || !trace || k < 2) return -1;
+    return build_trace(run_start, r, k, NULL, NULL, merge_down, trace);
 }
 
 int oracle_sort(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
                 oracle_trace *trace) {
-    return oracle_sort_ex(keys, kt, payload, n, k, 1, trace);
+    return oracle_sort_ex(keys, kt, payload, n, k, 1, 0, trace);
 }
 
 int oracle_sort_ex(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
-                   uint32_t min_run, oracle_trace *trace) {
+                   uint32_t min_run, int merge_down, oracle_trace *trace) {
     if (k < 2 || k > 64 || (n > 0 && !keys)) return -1;
     if (kt != ORC_I32 && kt != ORC_I64 && kt != ORC_F32) return -1;
     size_t ks = key_size(kt);
@@ -430,7 +471,7 @@ int oracle_sort_ex(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k
 
     oracle_trace local;
     oracle_trace *tr = trace ? trace : &local;
-    int rc = build_trace(run_start, r, k, NULL, &mv, tr);
+    int rc = build_trace(run_start, r, k, NULL, &mv, merge_down, tr);
     if (rc == 0) memcpy(tr->run_desc, run_desc, r);
     if (!trace && rc == 0) oracle_trace_free(&local);
     free(run_start);

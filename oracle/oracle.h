@@ -15,7 +15,8 @@
  *   - node power:      Definition 3.1 (run-boundary power), evaluated in
  *                      exact integer arithmetic
  *   - merge policy:    Algorithm 2 (KwayPowerSort_k, left-to-right run stack
- *                      that merges a whole group of equal powers at once)
+ *                      that merges a whole group of equal powers at once);
+ *                      optionally Appendix A.3's "merge down" final phase
  *   - merge tree:      Algorithm 1 (KwayTree_k), an independent recursive
  *                      construction used as a cross-check
  *   - merging:         Section 2.2 (stable merge of up to k runs; on equal
@@ -103,10 +104,14 @@ int oracle_sort(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
                 oracle_trace *trace);
 void oracle_trace_free(oracle_trace *trace);
 
-/* oracle_sort with a minimal run length (oracle_runs_min); min_run <= 1 is
- * oracle_sort itself. */
+/* oracle_sort with a minimal run length (oracle_runs_min; min_run <= 1: the
+ * natural runs) and, if merge_down is set, the final phase of the 4-way
+ * implementation in Appendix A.3 in place of Algorithm 2's: with s entries
+ * left on the stack, the top s mod (k-1) entries are merged with the current
+ * segment first, then k-1 entries at a time.  Such a node records the power
+ * of its first boundary. */
 int oracle_sort_ex(void *keys, int kt, uint32_t *payload, uint64_t n, uint32_t k,
-                   uint32_t min_run, oracle_trace *trace);
+                   uint32_t min_run, int merge_down, oracle_trace *trace);
 
 /* Algorithm 1 (KwayTree_k) over a given run partition and its powers.
  * nodes must hold r-1 entries; returns the node count (post-order:
@@ -119,6 +124,9 @@ int64_t oracle_kway_tree(const uint64_t *run_start, uint64_t r,
  * run_start/run_desc/power are copies of the inputs. */
 int oracle_tree_from_runs(const uint64_t *run_start, uint64_t r,
                           uint32_t k, oracle_trace *trace);
+/* The same with the merge-down final phase (see oracle_sort_ex) if set. */
+int oracle_tree_from_runs_ex(const uint64_t *run_start, uint64_t r, uint32_t k,
+                             int merge_down, oracle_trace *trace);
 
 /* Sorts each segment [offsets[i], offsets[i+1]) independently (its own n,
  * runs and tree); merge_cost (nullable) receives each segment's cost. */

@@ -533,3 +533,76 @@ def test_min_run_matches_library_stable_sort(name, n):
     if name == "perm_i64":          # natural runs have mean length ~2.5: nearly every run is 24
         lens = np.diff(tr.run_start.astype(np.int64))
         assert np.mean(lens[:-1] == 24) > 0.99
+
+
+# ---------------------------------------------------------------- merge-down final phase
+
+def spine_boundaries(power):
+    """Boundaries i (1-based) whose power is <= every power to their right."""
+    out, m = [], 10 ** 9
+    for i in range(len(power), 0, -1):
+        if power[i - 1] <= m:
+            out.append(i)
+            m = power[i - 1]
+    return out[::-1]
+
+
+def node_rows(nodes):
+    return sorted((int(v["begin"]), int(v["end"]), int(v["first_boundary"]), int(v["arity"]))
+                  for v in nodes)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 8])
+def test_merge_down_properties(k):
+    """Appendix A.3's final phase on random run partitions: the merge cost is
+    never above the pure tree's (the appendix states it can only go down);
+    nodes that do not end at n are the pure tree's; the nodes that end at n
+    split the array exactly at the weak suffix minima of the powers (the
+    boundaries left on the stack), every one of them k-way except the
+    smallest, which takes the remaining s mod (k-1) entries."""
+    rng = np.random.default_rng(100 + k)
+    lower = 0
+    for _ in range(400):
+        r = int(rng.integers(2, 120))
+        lens = rng.integers(1, int(rng.choice([3, 50, 5000])), size=r)
+        rs = starts_from_lengths(lens)
+        n = int(rs[-1])
+        pure = oracle.tree_from_runs(rs, k)
+        md = oracle.tree_from_runs(rs, k, merge_down=True)
+        assert md.merge_cost <= pure.merge_cost
+        lower += md.merge_cost < pure.merge_cost
+        off_p = [x for x in node_rows(pure.nodes) if x[1] != n]
+        off_m = [x for x in node_rows(md.nodes) if x[1] != n]
+        assert off_p == off_m
+        spine = [x for x in node_rows(md.nodes) if x[1] == n]
+        sp = spine_boundaries(pure.power.tolist())
+        s = len(sp)
+        spine_ids = {i for i, v in enumerate(md.nodes) if int(v["end"]) == n}
+        owned = [b for b in range(1, r) if int(md.boundary_node[b - 1]) in spine_ids]
+        assert owned == sp
+        arities = sorted((x[1] - x[0], x[3]) for x in spine)      # smallest span first
+        e = s % (k - 1)
+        want = ([e + 1] if e else []) + [k] * ((s - e) // (k - 1))
+        assert [a for _, a in arities] == want
+    assert lower > 0          # the variant does change some trees
+
+
+def test_merge_down_binary_is_pure():
+    """With k = 2 every merge is 2-way in both final phases: the same tree."""
+    rng = np.random.default_rng(120)
+    for _ in range(200):
+        rs = starts_from_lengths(rng.integers(1, 40, size=int(rng.integers(2, 80))))
+        a, b = oracle.tree_from_runs(rs, 2), oracle.tree_from_runs(rs, 2, merge_down=True)
+        assert node_rows(a.nodes) == node_rows(b.nodes) and a.merge_cost == b.merge_cost
+
+
+@pytest.mark.parametrize("name,n", [("runs_i32", 1 << 16), ("perm_i64", 1 << 14),
+                                    ("ties_i32", 1 << 16)])
+def test_merge_down_sort_is_stable_sort(name, n):
+    keys, _ = getattr(workloads, name)(n=n)
+    pay = np.arange(n, dtype=np.uint32)
+    for k in (2, 4, 8):
+        sk, sp, tr = oracle.sort(keys, pay, k=k, merge_down=True)
+        assert np.array_equal(sp, stable_order(keys))
+        pure = oracle.sort(keys, pay, k=k)[2]
+        assert tr.merge_cost <= pure.merge_cost
