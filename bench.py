@@ -545,6 +545,17 @@ def main():
             "merge_cost_workload": "n=10^8 int32, random runs of mean length 10^4 (Table 1)",
             "this_gpu": {"time_ratio_k4_over_k2": round(t4 / t2, 4),
                          "merge_cost_ratio_k4_over_k2": round(m4 / m2, 4)}}
+    if not args.no_k_sweep:
+        # Appendix A.3's merge-down final phase on the same input (k-way merges along the
+        # right spine): merge cost and time against the pure tree
+        keys.copy_(keys0)
+        pay.copy_(pay0)
+        trm = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, merge_down=True, **tcfg)
+        t_md, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
+                             lambda: mps.sort(keys, pay, k=args.k, merge_down=True, **tcfg))
+        out["merge_down"] = {"ms": round(t_md, 3), "merge_cost": int(trm.merge_cost),
+                             "merge_cost_pure": int(tr.merge_cost),
+                             "tree_levels": int(trm.n_levels)}
     if not args.no_records:
         out["records16"] = bench_records(args, torch, mps, keys0, tcfg)
     if not args.no_perm:

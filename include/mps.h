@@ -56,6 +56,15 @@ typedef enum { MPS_I32 = 0, MPS_I64 = 1, MPS_F32 = 2 } mps_key_type;
                                    every data-dependent quantity on the device, so new
                                    contents of keys / payload / offsets are fine.  Not with
                                    MPS_OPT_TIME_LEVELS. */
+#define MPS_OPT_MERGE_DOWN 4u   /* the final phase of the paper's 4-way implementation
+                                   (Appendix A.3) instead of Algorithm 2's: with s runs left on
+                                   the stack after the last one, the top s mod (k-1) are merged
+                                   with it first, then k-1 at a time, so every later merge is
+                                   k-way.  Only the nodes along the tree's right spine change,
+                                   and the merge cost never rises.  Each such node reports the
+                                   power of its first boundary, and so do its boundaries in the
+                                   trace.  Single arrays only (batched: MPS_E_UNSUPPORTED); a
+                                   no-op for k = 2. */
 
 /* Options.  All fields may be zero for defaults. */
 typedef struct {

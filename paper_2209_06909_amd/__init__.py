@@ -43,6 +43,7 @@ class MpsError(RuntimeError):
 
 OPT_TIME_LEVELS = 1
 OPT_GRAPH = 2
+OPT_MERGE_DOWN = 4
 # merge tile configurations: (outputs per tile, outputs per thread per LDS stage)
 TILE_CONFIGS = [(1024, 4), (2048, 8), (2048, 4), (4096, 8), (4096, 4)]
 
@@ -55,8 +56,9 @@ class _Opts(ctypes.Structure):
 
 
 def _opts(k, ws, *, time_levels=False, graph=False, tile=None, lane_slice=None,
-          min_run=1) -> _Opts:
-    flags = (OPT_TIME_LEVELS if time_levels else 0) | (OPT_GRAPH if graph else 0)
+          min_run=1, merge_down=False) -> _Opts:
+    flags = ((OPT_TIME_LEVELS if time_levels else 0) | (OPT_GRAPH if graph else 0)
+             | (OPT_MERGE_DOWN if merge_down else 0))
     return _Opts(k=k, flags=flags, workspace=ws.data_ptr(), workspace_bytes=ws.numel(),
                  tile=int(tile or 0), lane_slice=int(lane_slice or 0),
                  min_run=int(min_run or 1))
@@ -277,7 +279,7 @@ def _stream_ptr(device, stream):
 
 def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
          stream=None, time_levels: bool = False, graph: bool = False, tile: int | None = None,
-         lane_slice: int | None = None, min_run: int = 1):
+         lane_slice: int | None = None, min_run: int = 1, merge_down: bool = False):
     """Stable multiway Powersort of a 1-D GPU tensor, in place.
 
     keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
@@ -287,6 +289,8 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     graph: capture the launch sequence in a HIP graph (replayed on identical calls).
     tile, lane_slice: merge tile configuration, one of TILE_CONFIGS (default 2048, 4).
     min_run: minimal run length (Appendix A.3; 1 = natural runs, at most 32).
+    merge_down: Appendix A.3's final phase (every merge after the first on the right
+        spine is k-way) instead of Algorithm 2's equal-power groups.
     """
     _check_tensors(keys, payload)
     kt = key_type_of(keys)
@@ -298,7 +302,7 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
         raise MpsError(-4, f"unsupported arity k={k}")
     ws = _workspace(dev, need)
     opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice,
-                 min_run=min_run)
+                 min_run=min_run, merge_down=merge_down)
     t = _Trace() if trace else None
     entry = lib().mps_sort_kv64 if wide else lib().mps_sort_ex
     _check(entry(ctypes.c_void_p(keys.data_ptr()), kt,

@@ -346,14 +346,14 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
 // launch sequence.  Captured on a library stream (capture only records), then
 // launched on the caller's stream.
 struct GraphKey {
-  int dev, kt, k, tile, threads, want_cost, min_run;
+  int dev, kt, k, tile, threads, want_cost, min_run, merge_down;
   const void *keys, *payload, *off, *base;
   uint64_t m, N;
   bool operator<(const GraphKey &o) const {
-    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, keys, payload, off, base, m,
-                    N) <
-           std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.min_run, o.keys,
-                    o.payload, o.off, o.base, o.m, o.N);
+    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, merge_down, keys, payload,
+                    off, base, m, N) <
+           std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.min_run, o.merge_down,
+                    o.keys, o.payload, o.off, o.base, o.m, o.N);
   }
 };
 std::mutex g_graph_mu;
@@ -422,6 +422,8 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
     return fail(MPS_E_UNSUPPORTED, "min_run above " + std::to_string(kMrMaxMinRun));
   if (min_run > 1 && m > 1)
     return fail(MPS_E_UNSUPPORTED, "a minimal run length applies to single-array sorts only");
+  if ((flags & MPS_OPT_MERGE_DOWN) && m > 1)
+    return fail(MPS_E_UNSUPPORTED, "MPS_OPT_MERGE_DOWN applies to single-array sorts only");
   if ((flags & MPS_OPT_GRAPH) && (flags & MPS_OPT_TIME_LEVELS))
     return fail(MPS_E_INVALID, "MPS_OPT_GRAPH cannot be combined with MPS_OPT_TIME_LEVELS");
   Layout L;
@@ -457,6 +459,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   w.run_start = at<uint64_t>(base, L.run_start);
   w.run_desc = at<uint8_t>(base, L.run_desc);
   w.min_run = (int)min_run;
+  w.merge_down = (flags & MPS_OPT_MERGE_DOWN) ? 1 : 0;
   if (m == 1) {
     w.nat_start = at<uint64_t>(base, L.nat_start);
     w.nat_desc = at<uint8_t>(base, L.nat_desc);
@@ -503,8 +506,8 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   HIP_TRY(hipGetDevice(&dev));
 
   if (flags & MPS_OPT_GRAPH) {
-    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, keys, payload, d_off,
-                 base, m, N};
+    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, w.merge_down, keys,
+                 payload, d_off, base, m, N};
     rc = graph_launch(key, keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, s);
     if (rc) return rc;
   } else {

@@ -37,6 +37,7 @@ constexpr int kMrStage = kMrChunk / 2 + 8;   // natural runs staged per chunk (>
 constexpr uint8_t kMrEnd = 254;              // the chain has reached n
 constexpr uint8_t kMrBad = 255;              // unused candidate
 constexpr int kMrSortRuns = 128;             // runs per workgroup of the run sort
+constexpr uint32_t kErrMinRun = 1024u;       // plan->error bit of a failed chain check
 
 // Natural runs that overlap [c0 - 1, c1) of chunk c, plus the next two
 // starts, staged as 32-bit positions (n <= 2^31).
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kMrThreads) void k_mr_chunk(
     const uint64_t ia = c > 0 ? first[c] - 1 : 0, ib = first[c + 1];
     const int nrun = mr_stage(rs, desc, r, ia, ib, N, m, sm);
     if (nrun < 0) {
-      if (t == 0) atomicOr(&plan->error, 64u);
+      if (t == 0) atomicOr(&plan->error, kErrMinRun);
       __syncthreads();
       continue;
     }
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kMrThreads) void k_mr_chunk(
           // a jump past the next chunk's first m positions: it must end where
           // the run from c1 - 1 ends (staged run nrun - 1 holds c1 - 1)
           code = (uint8_t)m;
-          if (X != run_end_at(sm, nrun - 1, c1 - 1, N)) atomicOr(&plan->error, 64u);
+          if (X != run_end_at(sm, nrun - 1, c1 - 1, N)) atomicOr(&plan->error, kErrMinRun);
         }
       }
       nxt[c * kMrCand + t] = code;
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(64) void k_mr_top(const uint8_t *__restrict__ gnxt,
   if (lane == 0) {
     plan->r_nat = plan->r;   // the natural runs are still read by the emitting pass
     if (idx != kMrEnd || tot == 0 || tot > rmax) {
-      atomicOr(&plan->error, 64u);
+      atomicOr(&plan->error, kErrMinRun);
       tot = tot == 0 ? 1 : (tot > rmax ? rmax : tot);
     }
     plan->r = tot;
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(kMrThreads) void k_mr_emit(
     const uint64_t ia = c > 0 ? first[c] - 1 : 0, ib = first[c + 1];
     const int nrun = mr_stage(rs, desc, r, ia, ib, N, m, sm);
     if (nrun < 0) {
-      if (t == 0) atomicOr(&plan->error, 64u);
+      if (t == 0) atomicOr(&plan->error, kErrMinRun);
       __syncthreads();
       continue;
     }

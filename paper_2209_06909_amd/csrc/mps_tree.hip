@@ -218,6 +218,46 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_final(
   }
 }
 
+// ---------------------------------------------------------------- merge down
+// The final phase of the 4-way implementation in Appendix A.3 ("merge down"):
+// after the last run, the stack holds the subtrees hanging off the tree's
+// right spine, separated by the boundaries whose power is <= every power to
+// their right (the chain of nearest smaller-or-equal powers from boundary
+// r-1).  Instead of merging equal-power groups, the top s mod (k-1) entries
+// are merged first, then k-1 at a time.  The same tree comes out of the
+// power-based construction if every such group of spine boundaries gets the
+// power of its leftmost boundary: spine powers rise weakly to the right and
+// at most k-1 in a row are equal (Fact 3.2), so these values rise strictly
+// from group to group, and none exceeds a power inside the subtrees between
+// them.  One lane walks the spine (at most kMaxSpine boundaries).
+constexpr int kMaxSpine = 256;
+__global__ __launch_bounds__(64) void k_spine(uint8_t *__restrict__ P, const uint32_t *__restrict__ Le,
+                                              Plan *__restrict__ plan, int k) {
+  __shared__ uint32_t sb[kMaxSpine];
+  if (threadIdx.x != 0) return;
+  const uint64_t r = plan->r;
+  if (r < 3) return;
+  int s = 0;
+  uint32_t b = (uint32_t)(r - 1);
+  while (b > 0 && s < kMaxSpine) {
+    sb[s++] = b;
+    b = Le[b];
+  }
+  if (b > 0) {
+    atomicOr(&plan->error, 2048u);
+    return;
+  }
+  // sb[0] is the rightmost spine boundary; groups are taken from the right
+  const int km1 = k - 1;
+  int at = 0;
+  for (int len = s % km1; at < s; len = km1) {
+    if (len == 0) continue;
+    const uint8_t v = P[sb[at + len - 1]];
+    for (int t = at; t < at + len; t++) P[sb[t]] = v;
+    at += len;
+  }
+}
+
 // ---------------------------------------------------------------- nodes
 // Leader of the equal-power group containing boundary i: follow the chain of
 // nearest smaller-or-equal boundaries while the power stays equal.  A group
@@ -572,6 +612,14 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
                        uint32_t *tj, unsigned gtree, hipStream_t s) {
   const dim3 g256(1024), b256(256);
   hipLaunchKernelGGL(k_powers, g256, b256, 0, s, w.run_start, w.off, w.m, w.plan, w.logk, w.power);
+  if (w.merge_down && w.k > 2) {
+    // nearest smaller values of the true powers give the spine; its groups
+    // get their new powers, and the pass below runs on those
+    hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
+    hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
+    hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);
+    hipLaunchKernelGGL(k_spine, dim3(1), dim3(64), 0, s, w.power, w.Le, w.plan, w.k);
+  }
   hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
   hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
   hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);

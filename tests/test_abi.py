@@ -72,6 +72,10 @@ def test_min_run_argument_errors_need_no_gpu():
     assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 2, 1000, ctypes.byref(opts),
                                 None, None) == -4
     assert b"single-array" in lib.mps_last_error()
+    opts = mps._Opts(k=4, flags=mps.OPT_MERGE_DOWN)                        # merge-down: single arrays
+    assert lib.mps_sort_batched(fake, mps.KEY_I32, None, fake, off, 2, 1000, ctypes.byref(opts),
+                                None, None) == -4
+    assert b"MERGE_DOWN" in lib.mps_last_error()
     opts = mps._Opts(k=4, min_run=24)                                      # n <= 1: a no-op
     assert lib.mps_sort_ex(fake, mps.KEY_I64, None, 1, ctypes.byref(opts), None, None) == 0
     # a single-array workspace has room for the natural runs and chunk maps
