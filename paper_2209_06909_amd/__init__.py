@@ -210,13 +210,16 @@ def release_workspaces():
         _ws.clear()
 
 
-def _check_tensors(keys, payload):
+def _check_tensors(keys, payload, wide_ok=False):
+    """wide_ok: an int64 payload (8-byte records) is accepted, for sort() only."""
     torch = _torch()
     if not keys.is_cuda:
         raise ValueError("keys must be a GPU tensor")
     if not keys.is_contiguous():
         raise ValueError("keys must be contiguous")
     if payload is not None:
+        if payload.dtype == torch.int64 and not wide_ok:
+            raise TypeError("an 8-byte payload is supported by sort() only")
         if payload.dtype not in (torch.int32, torch.uint32, torch.int64):
             raise TypeError("payload must be int32/uint32 (4 bytes per key) or int64 (8 bytes)")
         if payload.device != keys.device or not payload.is_contiguous():
@@ -292,7 +295,7 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     merge_down: Appendix A.3's final phase (every merge after the first on the right
         spine is k-way) instead of Algorithm 2's equal-power groups.
     """
-    _check_tensors(keys, payload)
+    _check_tensors(keys, payload, wide_ok=True)
     kt = key_type_of(keys)
     n = keys.numel()
     dev = keys.device

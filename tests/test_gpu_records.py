@@ -90,3 +90,13 @@ def test_records_full_size():
     torch.cuda.synchronize()
     say("[gpu] records full runs_i64: checking")
     check_stable_sort_properties(keys, kd.cpu().numpy(), pd.cpu().numpy().astype(np.int64))
+
+
+def test_wide_payload_only_in_sort():
+    """An 8-byte payload goes through mps_sort_kv64 only; the batched call,
+    whose ABI takes a u32 payload, rejects it before any launch."""
+    kd = torch.arange(100, dtype=torch.int32, device="cuda:0")
+    pd = torch.arange(100, dtype=torch.int64, device="cuda:0")
+    off = torch.tensor([0, 50, 100], dtype=torch.int64, device="cuda:0")
+    with pytest.raises(TypeError):
+        mps.sort_batched(kd, pd, off)
