@@ -79,35 +79,63 @@ __device__ inline int block_excl_scan(int v, int *tmp, int &total) {
 __device__ inline int mr_stage(const uint64_t *__restrict__ rs, const uint8_t *__restrict__ desc,
                                uint64_t r, uint64_t ia, uint64_t ib, uint32_t N, uint32_t m,
                                MrSmem &sm) {
+  constexpr int kPer = (kMrStage + kMrThreads - 1) / kMrThreads;
   const int t = threadIdx.x;
   const uint64_t last = ib + 1 < r ? ib + 1 : r;
   const int ns = (int)(last - ia + 1);
   const int nrun = (int)(ib - ia);
   if (ns > kMrStage) return -1;
-  for (int j = t; j < ns; j += kMrThreads) {
-    sm.rs[j] = (uint32_t)rs[ia + j];
-    sm.d[j] = ia + j < r ? desc[ia + j] : 0;
+  // every load of a thread is issued before the first store
+  uint32_t v[kPer];
+  uint8_t dv[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    const int j = t + u * kMrThreads;
+    v[u] = 0;
+    dv[u] = 0;
+    if (j < ns) {
+      v[u] = (uint32_t)rs[ia + j];
+      if (ia + j < r) dv[u] = desc[ia + j];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    const int j = t + u * kMrThreads;
+    if (j < ns) {
+      sm.rs[j] = v[u];
+      sm.d[j] = dv[u];
+    }
   }
   __syncthreads();
-  int base = 0;
-  for (int j0 = 0; j0 < nrun; j0 += kMrThreads) {
-    const int j = j0 + t;
-    int hi = 0, hp = 0;
+  // thread t lists the jump sources of runs [t*kPer, t*kPer + kPer) in order;
+  // one scan gives every thread its place in the list
+  const int j0 = t * kPer;
+  uint32_t fl = 0;   // bit 2u: interval of run j0+u, bit 2u+1: its end point
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    const int j = j0 + u;
     if (j < nrun) {
       const uint32_t s = sm.rs[j], e = sm.rs[j + 1];
-      hi = e - s > m;
+      const bool hi = e - s > m;
+      bool hp = false;
       if (e < N) {
         const uint8_t against = sm.d[j] ^ 1;
         hp = sm.d[j + 1] == against && sm.rs[j + 2] - e >= m;
       }
+      fl |= (hi ? 1u : 0u) << (2 * u);
+      fl |= (hp ? 1u : 0u) << (2 * u + 1);
+      c += (int)hi + (int)hp;
     }
-    int tot;
-    const int pos = base + block_excl_scan(hi + hp, sm.scan, tot);
-    if (hi) sm.seg[pos] = (uint16_t)(2 * j);
-    if (hp) sm.seg[pos + hi] = (uint16_t)(2 * j + 1);
-    base += tot;
   }
-  if (t == 0) sm.misc[0] = base;
+  int tot;
+  int pos = block_excl_scan(c, sm.scan, tot);
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    if (fl >> (2 * u) & 1u) sm.seg[pos++] = (uint16_t)(2 * (j0 + u));
+    if (fl >> (2 * u + 1) & 1u) sm.seg[pos++] = (uint16_t)(2 * (j0 + u) + 1);
+  }
+  if (t == 0) sm.misc[0] = tot;
   __syncthreads();
   return nrun;
 }
@@ -135,16 +163,29 @@ __device__ inline uint32_t run_end_at(const MrSmem &sm, int j, uint32_t q, uint3
 
 // Follows the chain from b through the chunk ending at c1; counts the runs it
 // starts (and records their starts if rec is set).  Returns where it leaves.
+// Between jump sources the chain is an arithmetic progression of step m, so
+// it is advanced to the next jump source (or the chunk end) in one step.
 __device__ inline uint32_t mr_walk(const MrSmem &sm, int nseg, uint32_t b, uint32_t c1,
                                    uint32_t N, uint32_t m, int &cnt, uint32_t *rec) {
   int j = 0;
   cnt = 0;
   while (b < c1) {
     while (j < nseg && seg_hi(sm, sm.seg[j], m) < b) j++;
-    if (rec) rec[cnt] = b;
-    if (j < nseg && seg_lo(sm, sm.seg[j], m) <= b) b = seg_tgt(sm, sm.seg[j]);
-    else b = N - b > m ? b + m : N;
-    cnt++;
+    if (j < nseg && seg_lo(sm, sm.seg[j], m) <= b) {
+      if (rec) rec[cnt] = b;
+      b = seg_tgt(sm, sm.seg[j]);
+      cnt++;
+      continue;
+    }
+    // no jump source holds b: runs of m start at b, b+m, ... up to the first
+    // position at or past the next jump source's start (or c1)
+    uint32_t lim = j < nseg ? seg_lo(sm, sm.seg[j], m) : c1;
+    lim = lim < c1 ? lim : c1;
+    const uint32_t steps = (lim - b + m - 1) / m;
+    if (rec)
+      for (uint32_t q = 0; q < steps; q++) rec[cnt + (int)q] = b + q * m;
+    cnt += (int)steps;
+    b = N - b > steps * m ? b + steps * m : N;
   }
   return b;
 }
