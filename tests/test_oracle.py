@@ -606,3 +606,35 @@ def test_merge_down_sort_is_stable_sort(name, n):
         assert np.array_equal(sp, stable_order(keys))
         pure = oracle.sort(keys, pay, k=k)[2]
         assert tr.merge_cost <= pure.merge_cost
+
+
+@pytest.mark.parametrize("k", [3, 4, 8])
+def test_merge_down_is_kway_tree_of_regrouped_powers(k):
+    """An independent construction of the merge-down tree: Algorithm 1 over
+    the powers in which every group of spine boundaries (taken from the right,
+    s mod (k-1) first, then k-1 at a time) carries the power of its leftmost
+    boundary.  Spine powers rise weakly to the right with at most k-1 equal in
+    a row (Fact 3.2), so these groups are exactly Algorithm 1's equal-power
+    groups; it must give the stack's merge-down tree node for node."""
+    rng = np.random.default_rng(130 + k)
+    for _ in range(300):
+        r = int(rng.integers(2, 150))
+        lens = rng.integers(1, int(rng.choice([3, 40, 4000])), size=r)
+        rs = starts_from_lengths(lens)
+        pw = oracle.tree_from_runs(rs, k).power.tolist()
+        sp = spine_boundaries(pw)[::-1]                 # rightmost first
+        v = list(pw)
+        at, length = 0, len(sp) % (k - 1)
+        while at < len(sp):
+            if length:
+                lead = pw[sp[at + length - 1] - 1]
+                for b in sp[at:at + length]:
+                    v[b - 1] = lead
+                at += length
+            length = k - 1
+        alg1 = oracle.kway_tree(rs, np.array(v, dtype=np.uint8))
+        md = oracle.tree_from_runs(rs, k, merge_down=True)
+        rows = lambda nodes: sorted((int(x["begin"]), int(x["end"]), int(x["first_boundary"]),
+                                     int(x["arity"]), int(x["power"]), int(x["depth"]))
+                                    for x in nodes)
+        assert rows(alg1) == rows(md.nodes)
