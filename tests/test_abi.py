@@ -88,3 +88,14 @@ def test_serve_host_selftest():
     no GPU): first-fit allocation, coalescing, accounting under random churn, and
     arrival-order batches split by key type, count and memory."""
     assert mps.serve_selftest() == 0
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asked for more it exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
