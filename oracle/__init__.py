@@ -10,7 +10,8 @@ Each function follows the paper (arXiv 2209.06909):
   runs()            Section 2, run definition (greedy left-to-right scan);
                     with min_run > 1, Appendix A.3's extension of short runs
   power()/powers()  Definition 3.1, run-boundary power (exact integers)
-  sort()            Algorithm 2 (KwayPowerSort_k) with stable k-way merges
+  sort()            Algorithm 2 (KwayPowerSort_k) with stable k-way merges;
+                    merge_down: the final phase of Appendix A.3
   kway_tree()       Algorithm 1 (KwayTree_k), independent cross-check
   tree_from_runs()  Algorithm 2's tree without moving elements
 """
