@@ -138,7 +138,7 @@ def bench_batched(args, torch, mps, workloads):
     reps = args.batched_reps
 
     def batched(**c):
-        return lambda: mps.sort_batched(keys, pay, off_d, graph=True, **c)
+        return lambda: mps.sort_batched(keys, pay, off_d, graph=True, check=False, **c)
 
     restore()
     mps.sort_batched(keys, pay, off_d, graph=True, **cfg)          # warm-up + capture
@@ -207,7 +207,7 @@ def bench_perm(args, torch, mps, workloads, tcfg):
     keys, pay = keys0.clone(), pay0.clone()
     tr = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, **tcfg)
     ms, all_ms = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
-                            lambda: mps.sort(keys, pay, k=args.k, **tcfg))
+                            lambda: mps.sort(keys, pay, k=args.k, check=False, **tcfg))
     out = {"workload": f"perm_i64: uniform random permutation of 0..n-1 as int64 keys, n=2^{args.log2n}, "
                        "uint32 index payload (seed 3)",
            "ms": round(ms, 3), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 3),
@@ -220,7 +220,7 @@ def bench_perm(args, torch, mps, workloads, tcfg):
         pay.copy_(pay0)
         tm = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, min_run=mr, **tcfg)
         ms_m, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
-                             lambda: mps.sort(keys, pay, k=args.k, min_run=mr, **tcfg))
+                             lambda: mps.sort(keys, pay, k=args.k, min_run=mr, check=False, **tcfg))
         out[f"min_run_{mr}"] = {
             "ms": round(ms_m, 3), "gkeys_s": round(n / (ms_m * 1e-3) / 1e9, 3),
             "runs": int(tm.r), "tree_levels": int(tm.n_levels),
@@ -243,7 +243,7 @@ def bench_records(args, torch, mps, keys0, tcfg):
                        "holding each record's index", "record_bytes": 16}
     for kk in (4, 2):
         t, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
-                          lambda: mps.sort(keys, pay, k=kk, **tcfg))
+                          lambda: mps.sort(keys, pay, k=kk, check=False, **tcfg))
         res[f"k{kk}"] = {"ms": round(t, 3), "gkeys_s": round(n / (t * 1e-3) / 1e9, 3)}
     res["time_ratio_k4_over_k2"] = round(res["k4"]["ms"] / res["k2"]["ms"], 4)
     res["output_checked"] = bool((keys[1:] >= keys[:-1]).all().item()) and \
@@ -439,7 +439,7 @@ def main():
         keys.copy_(keys0)
         pay.copy_(pay0)
         ev[i][0].record()
-        mps.sort(keys, pay, k=args.k, time_levels=True, **tcfg)
+        mps.sort(keys, pay, k=args.k, time_levels=True, check=False, **tcfg)
         ev[i][1].record()
         elems, cms, mms = mps.level_stats()
         live = elems > 0
@@ -453,6 +453,7 @@ def main():
             f"{float(mms[live].sum()):.3f} ms, co-rank {float(cms[live].sum()):.3f} ms")
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
+    mps.check_last(dev)     # the last timed sort passed every device-side check
     sort_ms = np.array([a.elapsed_time(b) for a, b in ev])
     ms = float(sort_ms.mean())
     gkeys = n / (ms * 1e-3) / 1e9
@@ -525,7 +526,7 @@ def main():
             pay.copy_(pay0)
             trk = mps.sort(keys, pay, k=kk, trace=True, trace_arrays=False, **tcfg)
             t_k, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
-                                lambda: mps.sort(keys, pay, k=kk, **tcfg))
+                                lambda: mps.sort(keys, pay, k=kk, check=False, **tcfg))
             sweep.append({"k": kk, "ms": round(t_k, 3), "gkeys_s": round(n / (t_k * 1e-3) / 1e9, 3),
                           "merge_cost": int(trk.merge_cost),
                           "merge_cost_per_key": round(trk.merge_cost / n, 4),
@@ -552,7 +553,7 @@ def main():
         pay.copy_(pay0)
         trm = mps.sort(keys, pay, k=args.k, trace=True, trace_arrays=False, merge_down=True, **tcfg)
         t_md, _ = _time_reps(torch, 3, lambda: (keys.copy_(keys0), pay.copy_(pay0)),
-                             lambda: mps.sort(keys, pay, k=args.k, merge_down=True, **tcfg))
+                             lambda: mps.sort(keys, pay, k=args.k, merge_down=True, check=False, **tcfg))
         out["merge_down"] = {"ms": round(t_md, 3), "merge_cost": int(trm.merge_cost),
                              "merge_cost_pure": int(tr.merge_cost),
                              "tree_levels": int(trm.n_levels)}

@@ -21,9 +21,24 @@
  *  - Keys are int32, int64 or float32.  float32 keys are ordered by the
  *    IEEE-754 total order (-0 before +0, NaNs by bit pattern).  The payload
  *    is an optional uint32 per key that moves with its key (NULL: keys only).
- *  - Errors are returned as negative mps_status codes before any work is
- *    enqueued; mps_last_error() gives a message for the calling thread.
- *    Device faults surface at the caller's next synchronisation.
+ *  - Errors found on the host are returned as negative mps_status codes
+ *    before any work is enqueued; mps_last_error() gives a message for the
+ *    calling thread.  The kernels also check the consistency of what they
+ *    build (run table, merge tree, co-ranks, tile descriptors) and record a
+ *    failed check in the sort's device-side error word, whose output must
+ *    then not be trusted.  That word reaches the caller in three ways: a
+ *    trace request (the call returns MPS_E_DEVICE), mps_sort_status() after
+ *    the sort (it synchronises), or mps_opts.error_out (a device word the
+ *    sort ORs its error bits into, without synchronising).  HIP runtime
+ *    faults surface at the caller's next synchronisation.
+ *  - Workspace: every sort needs device scratch memory
+ *    (mps_workspace_bytes).  Either the caller passes it in
+ *    mps_opts.workspace -- one workspace must not be used by two sorts that
+ *    can run at the same time, e.g. on two streams -- or the library keeps
+ *    one per (device, stream), allocated on first use and kept until
+ *    mps_free_workspaces().  Growing a library-managed workspace
+ *    synchronises its stream and frees the old allocation, so a call that
+ *    needs a larger one is not asynchronous.
  */
 #ifndef MPS_H
 #define MPS_H
@@ -65,13 +80,16 @@ typedef enum { MPS_I32 = 0, MPS_I64 = 1, MPS_F32 = 2 } mps_key_type;
                                    power of its first boundary, and so do its boundaries in the
                                    trace.  Single arrays only (batched: MPS_E_UNSUPPORTED); a
                                    no-op for k = 2. */
+#define MPS_OPT_TEST_DEVICE_ERROR 8u /* testing only: the sort runs normally but reports a
+                                   failed device-side check (bit 30 of the error word), to
+                                   exercise the caller's error path */
 
 /* Options.  All fields may be zero for defaults. */
 typedef struct {
     uint32_t k;                 /* merge arity: 2, 4 (default, the paper's 4-way) or 8 */
     uint32_t flags;             /* MPS_OPT_* bits */
     void *workspace;            /* device memory of >= mps_workspace_bytes(); NULL: the
-                                   library allocates and caches one per device */
+                                   library allocates and caches one per (device, stream) */
     uint64_t workspace_bytes;
     uint32_t tile;              /* merge tile, outputs per workgroup task: 1024, 2048
                                    (default) or 4096 */
@@ -86,6 +104,10 @@ typedef struct {
                                    starts where it ends; powers and the merge tree are those
                                    of the extended runs.  Single-array sorts only (batched:
                                    MPS_E_UNSUPPORTED); above 32: MPS_E_UNSUPPORTED. */
+    uint32_t *error_out;        /* device uint32 or NULL: after the sort, a last kernel on the
+                                   stream ORs the sort's device-side error bits into it (0:
+                                   every check passed).  The caller clears it; it is sticky
+                                   across sorts, and works with MPS_OPT_GRAPH. */
 } mps_opts;
 
 /* What the sort did (filled when a trace pointer is passed; forces a stream
@@ -174,6 +196,21 @@ int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload, const uint6
 int mps_autotune(const void *keys, mps_key_type kt, const uint32_t *payload,
                  const uint64_t *h_offsets, uint64_t m, uint64_t sample_cap, uint32_t flags,
                  mps_opts *best, float *cand_ms, void *stream);
+
+/* Outcome of the device-side checks of the most recent sort that used
+ * `workspace` (the opts->workspace of that call; NULL: the library-managed
+ * workspace of the current device and `stream`).  Synchronises `stream`
+ * first.  MPS_OK if every check passed, MPS_E_DEVICE if one failed (that
+ * sort's output must not be trusted; the message gives the error word),
+ * MPS_E_NOTFOUND if no sort has used the library-managed workspace of this
+ * device and stream.  The error word is reset by the next sort that uses
+ * the same workspace. */
+int mps_sort_status(const void *workspace, void *stream);
+
+/* Synchronises every device that holds a library-managed workspace and frees
+ * them all (the next sort on a stream allocates a new one).  Traces and level
+ * timings of sorts that used them can no longer be fetched. */
+int mps_free_workspaces(void);
 
 /* Fills trace (counters and every array the caller supplies) from the most
  * recent sort that used `workspace` (the opts->workspace pointer of that

@@ -29,7 +29,8 @@ _STATUS = {-1: "MPS_E_INVALID", -2: "MPS_E_NOMEM", -3: "MPS_E_HIP", -4: "MPS_E_U
 KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
 
 EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
-            "mps_sort_ex", "mps_sort_kv64", "mps_sort_batched", "mps_autotune", "mps_trace_fetch",
+            "mps_sort_ex", "mps_sort_kv64", "mps_sort_batched", "mps_autotune", "mps_sort_status",
+            "mps_free_workspaces", "mps_trace_fetch",
             "mps_last_level_stats", "mps_serve_create", "mps_serve_submit", "mps_serve_poll",
             "mps_serve_release", "mps_serve_stats", "mps_serve_destroy", "mps_serve_selftest",
             "mps_last_error"]
@@ -44,6 +45,7 @@ class MpsError(RuntimeError):
 OPT_TIME_LEVELS = 1
 OPT_GRAPH = 2
 OPT_MERGE_DOWN = 4
+OPT_TEST_DEVICE_ERROR = 8
 # merge tile configurations: (outputs per tile, outputs per thread per LDS stage)
 TILE_CONFIGS = [(1024, 4), (2048, 8), (2048, 4), (4096, 8), (4096, 4)]
 
@@ -52,16 +54,18 @@ class _Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("tile", ctypes.c_uint32), ("lane_slice", ctypes.c_uint32),
-                ("min_run", ctypes.c_uint32)]
+                ("min_run", ctypes.c_uint32), ("error_out", ctypes.c_void_p)]
 
 
 def _opts(k, ws, *, time_levels=False, graph=False, tile=None, lane_slice=None,
-          min_run=1, merge_down=False) -> _Opts:
+          min_run=1, merge_down=False, error_out=None, test_device_error=False) -> _Opts:
     flags = ((OPT_TIME_LEVELS if time_levels else 0) | (OPT_GRAPH if graph else 0)
-             | (OPT_MERGE_DOWN if merge_down else 0))
+             | (OPT_MERGE_DOWN if merge_down else 0)
+             | (OPT_TEST_DEVICE_ERROR if test_device_error else 0))
     return _Opts(k=k, flags=flags, workspace=ws.data_ptr(), workspace_bytes=ws.numel(),
                  tile=int(tile or 0), lane_slice=int(lane_slice or 0),
-                 min_run=int(min_run or 1))
+                 min_run=int(min_run or 1),
+                 error_out=error_out.data_ptr() if error_out is not None else None)
 
 
 class _Trace(ctypes.Structure):
@@ -136,6 +140,10 @@ def lib() -> ctypes.CDLL:
             l.mps_sort_batched.restype = i32
             l.mps_autotune.argtypes = [P, i32, P, P, u64, u64, u32, ctypes.POINTER(_Opts), P, P]
             l.mps_autotune.restype = i32
+            l.mps_sort_status.argtypes = [P, P]
+            l.mps_sort_status.restype = i32
+            l.mps_free_workspaces.argtypes = []
+            l.mps_free_workspaces.restype = i32
             l.mps_trace_fetch.argtypes = [P, ctypes.POINTER(_Trace)]
             l.mps_trace_fetch.restype = i32
             l.mps_last_level_stats.argtypes = [u32, P, P, P, P]
@@ -188,10 +196,16 @@ _ws = {}
 _ws_lock = threading.Lock()
 
 
-def _workspace(device, nbytes: int):
-    """A cached torch uint8 buffer of at least nbytes on `device`."""
+def _workspace(device, stream, nbytes: int):
+    """A cached torch uint8 workspace of at least nbytes for sorts on `stream`.
+
+    One buffer per (device, stream): sorts on one stream run one after another, so
+    they may share it, while sorts on two streams never do.  The buffer is allocated
+    with `stream` current, so torch's caching allocator ties it to that stream: when
+    a larger one replaces it, its memory is handed out again only in that stream's
+    order, after the sorts already enqueued there."""
     torch = _torch()
-    key = (device.type, device.index)
+    key = (device.type, device.index, stream.cuda_stream)
     with _ws_lock:
         buf = _ws.get(key)
         if buf is None or buf.numel() < nbytes:
@@ -199,15 +213,19 @@ def _workspace(device, nbytes: int):
             # reused for the larger one
             buf = None
             _ws.pop(key, None)
-            buf = torch.empty(int(nbytes * 1.05) + 4096, dtype=torch.uint8, device=device)
+            with torch.cuda.stream(stream):
+                buf = torch.empty(int(nbytes * 1.05) + 4096, dtype=torch.uint8, device=device)
             _ws[key] = buf
         return buf
 
 
 def release_workspaces():
-    """Drop the cached torch workspaces (they are reallocated on the next call)."""
+    """Drop the cached torch workspaces (they are reallocated on the next call) and
+    free the library-managed ones (mps_free_workspaces)."""
     with _ws_lock:
         _ws.clear()
+    if os.path.exists(LIB_PATH) and _lib is not None:
+        _check(lib().mps_free_workspaces())
 
 
 def _check_tensors(keys, payload, wide_ok=False):
@@ -274,15 +292,39 @@ def _fetch_trace(ws_ptr, t: _Trace, arrays: bool) -> Trace:
     return tr
 
 
-def _stream_ptr(device, stream):
+def _stream_of(device, stream):
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream(device)
-    return ctypes.c_void_p(s.cuda_stream)
+    return stream if stream is not None else torch.cuda.current_stream(device)
+
+
+def _stream_ptr(device, stream):
+    return ctypes.c_void_p(_stream_of(device, stream).cuda_stream)
+
+
+def status(ws_ptr, stream_ptr):
+    """mps_sort_status: synchronise the stream and raise MpsError(MPS_E_DEVICE) if the
+    last sort that used the workspace failed a device-side check."""
+    _check(lib().mps_sort_status(ws_ptr, stream_ptr))
+
+
+def check_last(device=None, stream=None):
+    """After sorts run with check=False: synchronise `stream` (default: the current
+    stream of `device`) and raise MpsError if the last sort() / sort_batched() on it
+    failed a device-side check."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = _stream_of(dev, stream)
+    with _ws_lock:
+        buf = _ws.get((dev.type, dev.index, st.cuda_stream))
+    if buf is None:
+        raise MpsError(-5, "no sort has run on this stream")
+    status(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(st.cuda_stream))
 
 
 def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
          stream=None, time_levels: bool = False, graph: bool = False, tile: int | None = None,
-         lane_slice: int | None = None, min_run: int = 1, merge_down: bool = False):
+         lane_slice: int | None = None, min_run: int = 1, merge_down: bool = False,
+         check: bool = True, error_out=None, test_device_error: bool = False):
     """Stable multiway Powersort of a 1-D GPU tensor, in place.
 
     keys: int32 / int64 / float32 (float32 by the IEEE-754 total order).
@@ -294,6 +336,11 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     min_run: minimal run length (Appendix A.3; 1 = natural runs, at most 32).
     merge_down: Appendix A.3's final phase (every merge after the first on the right
         spine is k-way) instead of Algorithm 2's equal-power groups.
+    check: synchronise the stream after the sort and raise MpsError (MPS_E_DEVICE) if
+        a device-side check failed.  check=False keeps the call asynchronous; the
+        device error word then reaches the caller through `error_out` (a GPU int32
+        tensor of one element that the sort ORs its error bits into) or status().
+    test_device_error: testing only -- the sort runs normally but reports a failed check.
     """
     _check_tensors(keys, payload, wide_ok=True)
     kt = key_type_of(keys)
@@ -303,16 +350,21 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
     need = workspace_bytes(max(n, 2), 1, kt, 2 if wide else int(payload is not None), k)
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
-    ws = _workspace(dev, need)
+    st = _stream_of(dev, stream)
+    ws = _workspace(dev, st, need)
     opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice,
-                 min_run=min_run, merge_down=merge_down)
+                 min_run=min_run, merge_down=merge_down, error_out=error_out,
+                 test_device_error=test_device_error)
     t = _Trace() if trace else None
     entry = lib().mps_sort_kv64 if wide else lib().mps_sort_ex
+    sp = ctypes.c_void_p(st.cuda_stream)
     _check(entry(ctypes.c_void_p(keys.data_ptr()), kt,
                              ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
                              n, ctypes.byref(opts), ctypes.byref(t) if t is not None else None,
-                             _stream_ptr(dev, stream)))
+                             sp))
     if t is None:
+        if check and n > 1:
+            status(ctypes.c_void_p(ws.data_ptr()), sp)
         return None
     if n <= 1:
         tr = Trace(r=n, n_nodes=0, merge_cost=0, n_levels=0, k=k)
@@ -333,12 +385,13 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
 def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
                  trace_arrays: bool = True, stream=None, host_offsets=None,
                  time_levels: bool = False, graph: bool = False, tile: int | None = None,
-                 lane_slice: int | None = None):
+                 lane_slice: int | None = None, check: bool = True, error_out=None,
+                 test_device_error: bool = False):
     """Sort m independent arrays packed back to back in `keys` (and `payload`).
 
     offsets: GPU int64/uint64 tensor of m+1 entries (offsets[0] = 0, offsets[m] = len(keys)).
     Every array is sorted exactly as sort() would sort it alone.  graph / tile /
-    lane_slice as for sort().
+    lane_slice / check / error_out as for sort().
     """
     torch = _torch()
     _check_tensors(keys, payload)
@@ -356,17 +409,22 @@ def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,
     need = workspace_bytes(max(n, 2), max(m, 1), kt, payload is not None, k)
     if need == 0:
         raise MpsError(-4, f"unsupported arity k={k}")
-    ws = _workspace(dev, need)
-    opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice)
+    st = _stream_of(dev, stream)
+    ws = _workspace(dev, st, need)
+    opts = _opts(k, ws, time_levels=time_levels, graph=graph, tile=tile, lane_slice=lane_slice,
+                 error_out=error_out, test_device_error=test_device_error)
     t = _Trace() if trace else None
+    sp = ctypes.c_void_p(st.cuda_stream)
     _check(lib().mps_sort_batched(
         ctypes.c_void_p(keys.data_ptr()), kt,
         ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
         ctypes.c_void_p(offsets.data_ptr()),
         hoff.ctypes.data_as(ctypes.c_void_p) if hoff is not None else None,
         max(m, 0), n, ctypes.byref(opts), ctypes.byref(t) if t is not None else None,
-        _stream_ptr(dev, stream)))
+        sp))
     if t is None:
+        if check and m > 0 and n > 0:
+            status(ctypes.c_void_p(ws.data_ptr()), sp)
         return None
     return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)
 

@@ -7,10 +7,11 @@
 // graph).  Levels are launched for every depth the powers allow; levels
 // deeper than the actual tree find zero tiles and return at once.
 #include <mutex>
-#include <string>
 #include <tuple>
 #include <vector>
 #include <map>
+#include <cstdarg>
+#include <cstdio>
 #include <cstring>
 
 #include "mps.h"
@@ -19,8 +20,10 @@
 namespace mps {
 
 // Zero the plan and (for single-array calls) write the 2-entry offsets.
+// init_error presets the plan's error word (testing: a reported device error
+// on a sort that otherwise runs normally).
 __global__ void k_init(Plan *plan, uint64_t *seg_off, uint64_t n, uint64_t m, uint32_t kt,
-                       uint32_t has_payload, uint32_t k, int single) {
+                       uint32_t has_payload, uint32_t k, int single, uint32_t init_error) {
   uint64_t *p = reinterpret_cast<uint64_t *>(plan);
   for (size_t i = threadIdx.x; i < sizeof(Plan) / 8; i += blockDim.x) p[i] = 0;
   __syncthreads();
@@ -30,11 +33,18 @@ __global__ void k_init(Plan *plan, uint64_t *seg_off, uint64_t n, uint64_t m, ui
     plan->kt = kt;
     plan->has_payload = has_payload;
     plan->k = k;
+    plan->error = init_error;
     if (single) {
       seg_off[0] = 0;
       seg_off[1] = n;
     }
   }
+}
+
+// The last launch of a sort that was given an error word: ORs the plan's
+// device-side check results into it (sticky across sorts).
+__global__ void k_report(const Plan *plan, uint32_t *error_out) {
+  if (threadIdx.x == 0 && plan->error) atomicOr(error_out, plan->error);
 }
 
 // Records with an 8-byte payload: the sort carries the u32 index of every
@@ -71,21 +81,30 @@ __global__ void k_check_offsets(const uint64_t *off, uint64_t m, uint64_t total,
 using namespace mps;
 
 // ---------------------------------------------------------------- errors
-static thread_local std::string g_err;
+// The calling thread's last message, in a fixed buffer: reporting an error
+// allocates nothing.
+static thread_local char g_err[512];
 
-static int fail(int code, const std::string &msg) {
-  g_err = msg;
+static int fail(int code, const char *msg) {
+  snprintf(g_err, sizeof g_err, "%s", msg);
+  return code;
+}
+
+__attribute__((format(printf, 2, 3))) static int failf(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
   return code;
 }
 
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
     hipError_t _e = (expr);                                                        \
-    if (_e != hipSuccess)                                                          \
-      return fail(MPS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+    if (_e != hipSuccess) return failf(MPS_E_HIP, "%s: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
 
-extern "C" const char *mps_last_error(void) { return g_err.c_str(); }
+extern "C" const char *mps_last_error(void) { return g_err; }
 
 int mps::fail_msg(int code, const char *msg) { return fail(code, msg); }
 
@@ -205,18 +224,26 @@ int check_k(uint32_t &k) {
   return MPS_OK;
 }
 
-// Library-managed workspace, one per device, grown on demand.
+// Library-managed workspaces, one per (device, stream), grown on demand.  A
+// stream runs its sorts one after another, so sorts on one stream never share
+// a workspace with sorts still running on another.  Growing waits for the
+// stream (its earlier sorts may still use the old allocation) before freeing.
+struct WsKey {
+  int dev;
+  hipStream_t s;
+  bool operator<(const WsKey &o) const { return std::tie(dev, s) < std::tie(o.dev, o.s); }
+};
 std::mutex g_ws_mu;
-std::map<int, std::pair<void *, size_t>> g_ws;
+std::map<WsKey, std::pair<void *, size_t>> g_ws;
 
-int get_workspace(size_t need, void **out) {
+int get_workspace(size_t need, hipStream_t s, void **out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  auto &e = g_ws[dev];
+  auto &e = g_ws[WsKey{dev, s}];
   if (e.second < need) {
     if (e.first) {
-      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipStreamSynchronize(s));
       HIP_TRY(hipFree(e.first));
       e.first = nullptr;
       e.second = 0;
@@ -230,6 +257,16 @@ int get_workspace(size_t need, void **out) {
   return MPS_OK;
 }
 
+// The library-managed workspace of (current device, s), or nullptr.
+void *find_workspace(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_ws.find(WsKey{dev, s});
+  if (it == g_ws.end() || !it->second.first) return nullptr;
+  return reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(it->second.first) + 255) & ~(uintptr_t)255);
+}
+
 template <typename T> T *at(void *base, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
@@ -240,7 +277,7 @@ int fill_trace(void *base, mps_trace *tr) {
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
   if (plan.error)
-    return fail(MPS_E_DEVICE, "device-side consistency check failed (code " + std::to_string(plan.error) + ")");
+    return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", plan.error);
   tr->r = plan.r;
   tr->n_nodes = plan.n_nodes;
   tr->merge_cost = plan.merge_cost;
@@ -255,7 +292,7 @@ int fill_trace(void *base, mps_trace *tr) {
                     tr->node_power || tr->node_depth;
   if (!want_runs && !want_nodes) return MPS_OK;
   if (tr->r_cap < r + 1)
-    return fail(MPS_E_NOMEM, "trace r_cap too small (need r+1 = " + std::to_string(r + 1) + ")");
+    return failf(MPS_E_NOMEM, "trace r_cap too small (need r+1 = %llu)", (unsigned long long)(r + 1));
   std::vector<uint64_t> rs(r + 1);
   HIP_TRY(hipMemcpy(rs.data(), at<uint64_t>(base, L.run_start), (r + 1) * 8, hipMemcpyDeviceToHost));
   std::vector<uint8_t> P(r + 1);
@@ -304,10 +341,11 @@ LevelTiming g_time[64];
 // The launch sequence of one sort on stream s (also what a graph captures).
 int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, const Work &w,
                  const Layout &L, uint64_t *lvl_tot, uint64_t *tile_base, uint32_t *tj,
-                 int want_cost, LevelTiming *tm, hipStream_t s) {
+                 int want_cost, LevelTiming *tm, uint32_t init_error, uint32_t *error_out,
+                 hipStream_t s) {
   const unsigned gtree = (unsigned)(L.nbb < 4096 ? L.nbb : 4096);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.plan, w.seg_off_local, w.N, w.m,
-                     (uint32_t)kt, payload ? 1u : 0u, (uint32_t)w.k, d_off ? 0 : 1);
+                     (uint32_t)kt, payload ? 1u : 0u, (uint32_t)w.k, d_off ? 0 : 1, init_error);
   if (d_off)
     hipLaunchKernelGGL(k_check_offsets, dim3(64), dim3(256), 0, s, d_off, w.m, w.N, w.plan);
   HIP_TRY(hipGetLastError());
@@ -338,6 +376,10 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
       HIP_TRY(launch_level(kt, a, w, tj, tile_base, d, s));
     }
   }
+  if (error_out) {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, (const Plan *)w.plan, error_out);
+    HIP_TRY(hipGetLastError());
+  }
   return MPS_OK;
 }
 
@@ -347,13 +389,14 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
 // launched on the caller's stream.
 struct GraphKey {
   int dev, kt, k, tile, threads, want_cost, min_run, merge_down;
-  const void *keys, *payload, *off, *base;
+  uint32_t init_error;
+  const void *keys, *payload, *off, *base, *error_out;
   uint64_t m, N;
   bool operator<(const GraphKey &o) const {
-    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, merge_down, keys, payload,
-                    off, base, m, N) <
+    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, merge_down, init_error, keys,
+                    payload, off, base, error_out, m, N) <
            std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.min_run, o.merge_down,
-                    o.keys, o.payload, o.off, o.base, o.m, o.N);
+                    o.init_error, o.keys, o.payload, o.off, o.base, o.error_out, o.m, o.N);
   }
 };
 std::mutex g_graph_mu;
@@ -376,18 +419,18 @@ int graph_launch(const GraphKey &key, void *keys, int kt, uint32_t *payload,
     }
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
     int rc = enqueue_sort(keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, key.want_cost,
-                          nullptr, cs);
+                          nullptr, key.init_error, (uint32_t *)key.error_out, cs);
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(cs, &g);
     if (rc != MPS_OK) {
       if (g) (void)hipGraphDestroy(g);
       return rc;
     }
-    if (ec != hipSuccess) return fail(MPS_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    if (ec != hipSuccess) return failf(MPS_E_HIP, "graph capture: %s", hipGetErrorString(ec));
     hipGraphExec_t ge = nullptr;
     hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (ei != hipSuccess) return fail(MPS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    if (ei != hipSuccess) return failf(MPS_E_HIP, "graph instantiate: %s", hipGetErrorString(ei));
     it = g_graphs.emplace(key, ge).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, s));
@@ -419,7 +462,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   const uint32_t flags = opts ? opts->flags : 0;
   const uint32_t min_run = opts && opts->min_run > 1 ? opts->min_run : 1;
   if (min_run > (uint32_t)kMrMaxMinRun)
-    return fail(MPS_E_UNSUPPORTED, "min_run above " + std::to_string(kMrMaxMinRun));
+    return failf(MPS_E_UNSUPPORTED, "min_run above %d", kMrMaxMinRun);
   if (min_run > 1 && m > 1)
     return fail(MPS_E_UNSUPPORTED, "a minimal run length applies to single-array sorts only");
   if ((flags & MPS_OPT_MERGE_DOWN) && m > 1)
@@ -431,10 +474,10 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   void *base = nullptr;
   if (opts && opts->workspace) {
     if (opts->workspace_bytes < L.total)
-      return fail(MPS_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+      return failf(MPS_E_NOMEM, "workspace too small: need %llu bytes", (unsigned long long)L.total);
     base = opts->workspace;
   } else {
-    rc = get_workspace(L.total, &base);
+    rc = get_workspace(L.total, s, &base);
     if (rc) return rc;
   }
   base = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(base) + 255) & ~(uintptr_t)255);
@@ -502,12 +545,14 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   uint64_t *tile_base = at<uint64_t>(base, L.tile_base);
   uint32_t *tj = at<uint32_t>(base, L.tj);
   const int want_cost = trace ? 1 : 0;
+  const uint32_t init_error = (flags & MPS_OPT_TEST_DEVICE_ERROR) ? kErrTestForced : 0u;
+  uint32_t *error_out = opts ? opts->error_out : nullptr;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
 
   if (flags & MPS_OPT_GRAPH) {
-    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, w.merge_down, keys,
-                 payload, d_off, base, m, N};
+    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, w.merge_down, init_error,
+                 keys, payload, d_off, base, error_out, m, N};
     rc = graph_launch(key, keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, s);
     if (rc) return rc;
   } else {
@@ -525,7 +570,8 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
       tm->levels = L.levels;
       tm->base = base;
     }
-    rc = enqueue_sort(keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, want_cost, tm, s);
+    rc = enqueue_sort(keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, want_cost, tm,
+                      init_error, error_out, s);
     if (rc) return rc;
   }
   if (!(opts && opts->workspace) && dev >= 0 && dev < 64) g_last_base[dev] = base;
@@ -550,7 +596,7 @@ extern "C" uint64_t mps_workspace_bytes(uint64_t n, uint64_t m, mps_key_type kt,
 
 extern "C" int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
                            const mps_opts *opts, mps_trace *trace, void *stream) {
-  g_err.clear();
+  g_err[0] = 0;
   if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
   if (n > 0 && !keys) return fail(MPS_E_INVALID, "keys is NULL");
   if (n > (1ull << 31)) return fail(MPS_E_UNSUPPORTED, "arrays longer than 2^31 are not supported");
@@ -579,7 +625,7 @@ extern "C" int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint6
 
 extern "C" int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uint64_t n,
                              const mps_opts *opts, mps_trace *trace, void *stream) {
-  g_err.clear();
+  g_err[0] = 0;
   if (!payload || n <= 1) return mps_sort_ex(keys, kt, nullptr, n, opts, trace, stream);
   if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
   if (!keys) return fail(MPS_E_INVALID, "keys is NULL");
@@ -593,10 +639,10 @@ extern "C" int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uin
   void *base = nullptr;
   if (opts && opts->workspace) {
     if (opts->workspace_bytes < need)
-      return fail(MPS_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+      return failf(MPS_E_NOMEM, "workspace too small: need %llu bytes", (unsigned long long)need);
     base = opts->workspace;
   } else {
-    rc = get_workspace(need, &base);
+    rc = get_workspace(need, (hipStream_t)stream, &base);
     if (rc) return rc;
   }
   char *ex = static_cast<char *>(base) + L.total;
@@ -644,7 +690,7 @@ extern "C" int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload,
                                 const uint64_t *offsets, const uint64_t *h_offsets, uint64_t m,
                                 uint64_t total_n, const mps_opts *opts, mps_trace *trace,
                                 void *stream) {
-  g_err.clear();
+  g_err[0] = 0;
   if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
   if (m == 0 || total_n == 0) {
     if (trace) memset(trace, 0, offsetof(mps_trace, r_cap));
@@ -662,8 +708,52 @@ extern "C" int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload,
   return run_sort(keys, kt, payload, offsets, m, total_n, opts, trace, (hipStream_t)stream);
 }
 
+extern "C" int mps_sort_status(const void *workspace, void *stream) {
+  g_err[0] = 0;
+  hipStream_t s = (hipStream_t)stream;
+  void *base = workspace ? reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(workspace) + 255) &
+                                                    ~(uintptr_t)255)
+                         : find_workspace(s);
+  if (!base)
+    return fail(MPS_E_NOTFOUND, "no sort has used the library-managed workspace of this device and stream");
+  HIP_TRY(hipStreamSynchronize(s));
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, static_cast<char *>(base) + offsetof(Plan, error), 4, hipMemcpyDeviceToHost));
+  if (err) return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", err);
+  return MPS_OK;
+}
+
+extern "C" int mps_free_workspaces(void) {
+  g_err[0] = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (g_ws.empty()) return MPS_OK;
+  }
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto &e : g_ws) {
+      if (!e.second.first) continue;
+      HIP_TRY(hipSetDevice(e.first.dev));
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(e.second.first));
+      e.second.first = nullptr;
+      e.second.second = 0;
+    }
+    g_ws.clear();
+    for (auto &b : g_last_base) b = nullptr;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    for (auto &t : g_time) t.base = nullptr;
+  }
+  HIP_TRY(hipSetDevice(cur));
+  return MPS_OK;
+}
+
 extern "C" int mps_trace_fetch(const void *workspace, mps_trace *trace) {
-  g_err.clear();
+  g_err[0] = 0;
   if (!trace) return fail(MPS_E_INVALID, "trace is NULL");
   void *base = nullptr;
   if (workspace) {
@@ -679,7 +769,7 @@ extern "C" int mps_trace_fetch(const void *workspace, mps_trace *trace) {
 
 extern "C" int mps_last_level_stats(uint32_t cap, uint32_t *n_levels, uint64_t *level_elems,
                                     float *corank_ms, float *merge_ms) {
-  g_err.clear();
+  g_err[0] = 0;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");

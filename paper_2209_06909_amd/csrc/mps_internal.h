@@ -14,6 +14,9 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxLevels = 64;       // bound on merge-tree depth (powers fit in a byte)
 constexpr int kVMax = 40;            // powers are < kVMax (k=2: P <= ceil(log2(2n)) <= 33)
 constexpr uint32_t kNone32 = 0xFFFFFFFFu;
+// Error-word bit set by the host-requested test of the error path
+// (MPS_OPT_TEST_DEVICE_ERROR); the device checks use the low bits.
+constexpr uint32_t kErrTestForced = 1u << 30;
 constexpr uint64_t kNone64 = ~0ull;
 
 // Key traits: storage type U and the order-preserving map to unsigned O.

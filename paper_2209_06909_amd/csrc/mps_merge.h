@@ -13,7 +13,6 @@
 // with coalesced stores.  Workgroups take tiles from a per-level work queue
 // (an atomic counter in the plan).
 #pragma once
-#include <map>
 #include <mutex>
 
 #include "mps_internal.h"
@@ -1088,21 +1087,30 @@ __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
 
 // ---------------------------------------------------------------- host side
 // Workgroups that fill the device once (CUs x resident workgroups per CU) for
-// a queue-driven kernel; computed once per kernel.
+// a queue-driven kernel; computed once per kernel and device.  The cache is a
+// fixed table, so a launch allocates no host memory (a full table only means
+// recomputing).
 inline unsigned fill_grid(const void *kernel, int threads, unsigned fallback) {
+  struct Entry {
+    const void *kernel;
+    int dev;
+    unsigned grid;
+  };
+  constexpr int kSlots = 512;
   static std::mutex mu;
-  static std::map<const void *, unsigned> cache;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(kernel);
-  if (it != cache.end()) return it->second;
+  static Entry tab[kSlots];
+  static int used = 0;
   int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  if (hipGetDevice(&dev) != hipSuccess) return fallback;
+  std::lock_guard<std::mutex> lk(mu);
+  for (int i = 0; i < used; i++)
+    if (tab[i].kernel == kernel && tab[i].dev == dev) return tab[i].grid;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
       cus <= 0 || per_cu <= 0)
     return fallback;
-  unsigned g = (unsigned)(cus * per_cu);
-  cache[kernel] = g;
+  const unsigned g = (unsigned)(cus * per_cu);
+  if (used < kSlots) tab[used++] = Entry{kernel, dev, g};
   return g;
 }
 

@@ -252,3 +252,25 @@ def test_batched_full_size():
     del kin, pin, kd, pd
     mps.release_workspaces()
     torch.cuda.empty_cache()
+
+
+def test_batched_large_arrays_vs_oracle():
+    """Arrays of 2^23 to 2^26 keys in one batch (with small ones between them):
+    every array equals the oracle's sort of it alone, keys and payload."""
+    say("[gpu] batched large arrays vs oracle")
+    big, pb, ob = workloads.batch_i32(m=3, seed=62, lo_exp=23.0, hi_exp=26.0)
+    small, ps, os_ = workloads.batch_i32(m=5, seed=63, lo_exp=8.0, hi_exp=12.0)
+    keys = np.concatenate([small[: int(os_[2])], big, small[int(os_[2]):]])
+    pay = np.concatenate([ps[: int(os_[2])], pb, ps[int(os_[2]):]])
+    sizes = np.concatenate([np.diff(os_)[:2], np.diff(ob), np.diff(os_)[2:]]).astype(np.uint64)
+    off = np.zeros(sizes.size + 1, np.uint64)
+    off[1:] = np.cumsum(sizes)
+    assert int(off[-1]) == keys.size and int(np.diff(ob).max()) >= 1 << 23
+    kd = torch.from_numpy(keys).to(DEV)
+    pd = torch.from_numpy(pay.view(np.int32)).to(DEV)
+    od = torch.from_numpy(off.view(np.int64)).to(DEV)
+    mps.sort_batched(kd, pd, od, host_offsets=off)
+    gk, gp = kd.cpu().numpy(), pd.cpu().numpy().view(np.uint32)
+    ok, op, _ = oracle.sort_many(keys, pay, off, k=4)
+    assert np.array_equal(gk, ok)
+    assert np.array_equal(gp, op)

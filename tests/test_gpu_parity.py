@@ -262,3 +262,25 @@ def test_full_size(name, n):
     assert np.array_equal(gt.node_first.astype(np.int64), nodes["first_boundary"].astype(np.int64))
     assert np.array_equal(gt.node_depth.astype(np.int64), nodes["depth"].astype(np.int64))
     assert np.array_equal(gt.node_arity.astype(np.int64), nodes["arity"].astype(np.int64))
+
+
+ZIGZAG_BIG = [
+    # strictly alternating: every pair type changes, so the odd-streak rule's carry runs
+    # through the whole array and across every iteration of the run-detection block scan
+    ("zigzag_i32", np.tile(np.array([5, 3], np.int32), (1 << 24) + 1)),
+    ("zigzag_i32_odd", np.concatenate([np.tile(np.array([5, 3], np.int32), 1 << 24),
+                                       np.array([9, 1, 2], np.int32)])),
+    ("zigzag_i64_shifted", np.concatenate([np.array([7], np.int64),
+                                           np.tile(np.array([2, 8], np.int64), (1 << 24) + 7)])),
+]
+
+
+@pytest.mark.parametrize("name,keys", ZIGZAG_BIG, ids=[z[0] for z in ZIGZAG_BIG])
+def test_zigzag_crosses_detect_blocks(name, keys):
+    """Zig-zag inputs of more than 2^25 keys (Section 2's runs: every run is a
+    strictly descending pair, or the pair it starts is ascending): runs,
+    directions, powers, tree and output equal the oracle's."""
+    say(f"[gpu] zigzag {name} n={keys.size}")
+    assert keys.size > 1 << 25
+    pay = np.arange(keys.size, dtype=np.uint32)
+    check_vs_oracle(keys, pay, 4)

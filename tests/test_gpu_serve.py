@@ -176,3 +176,34 @@ def test_serve_destroy_drains():
         ok_, op_, _ = oracle.sort(k0, p0, k=4)
         assert np.array_equal(k.cpu().numpy(), ok_)
         assert np.array_equal(p.cpu().numpy().view(np.uint32), op_)
+
+
+def test_serve_large_f32_alone_vs_mix():
+    """Served float32 requests from the top of the serving size range (2^22 to 2^26
+    keys, normal values with about 1% duplicated keys, random runs) mixed with
+    small ones: every result equals the request sorted alone, and the large ones
+    equal the oracle bit for bit (keys and payload permutation)."""
+    say("[gpu] serve large f32 alone vs mix")
+    rng = np.random.default_rng(61)
+    sizes = [1 << 22, int(2 ** 23.4), int(2 ** 24.7), 1 << 26, 1500, 9000, 70000, 1 << 14]
+    host = [workloads.serve_request_f32(s, rng) for s in sizes]
+    reqs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(p.view(np.int32)).to(DEV)) for x, p in host]
+    outs = [(torch.empty_like(k), torch.empty_like(p)) for k, p in reqs]
+    with mps.Server(hbm_budget_bytes=16 << 30, n_streams=3, max_batch=4) as srv:
+        ids = []
+        for i, ((k, p), (ko, po)) in enumerate(zip(reqs, outs)):
+            ids.append(srv.submit(k, p, ko, po))
+            if i % 3 == 2:
+                time.sleep(0.002)                 # later requests arrive while batches run
+        for i in ids:
+            srv.wait(i, timeout=120)
+    for (k, p), (ko, po) in zip(reqs, outs):
+        ak, ap = alone(k, p)
+        assert np.array_equal(ko.cpu().numpy().view(np.uint8), ak.view(np.uint8))
+        assert np.array_equal(po.cpu().numpy(), ap)
+    for idx in range(4):
+        x, p = host[idx]
+        ok_, op_, _ = oracle.sort(x, p, k=4)
+        say(f"[gpu]   oracle check of request {idx} ({x.size} keys)")
+        assert np.array_equal(outs[idx][0].cpu().numpy().view(np.uint8), ok_.view(np.uint8))
+        assert np.array_equal(outs[idx][1].cpu().numpy().view(np.uint32), op_)
