@@ -155,6 +155,30 @@ int mps_sort_f32(float *keys, uint32_t *payload, uint64_t n, void *stream);
 int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
                 const mps_opts *opts, mps_trace *trace, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the sort of
+ * mps_sort_ex (same result, same options) with its workspace in a fixed
+ * device array of the library, mps_noalloc_scratch_bytes() = 64 MiB, that
+ * every device the library runs on holds from the first such call until the
+ * process ends.  The call allocates nothing: no hipMalloc / hipFree, no HIP
+ * events, streams or graphs, no host memory.
+ *  - Limit: mps_workspace_bytes(n, 1, kt, payload != NULL, k) must not exceed
+ *    the scratch (about 1.38M int64 or 1.5M int32/float32 keys with a u32
+ *    payload at k = 4); larger sorts return MPS_E_NOMEM before any work is
+ *    enqueued.
+ *  - opts may be NULL.  opts->workspace must be NULL (MPS_E_INVALID);
+ *    MPS_OPT_GRAPH and MPS_OPT_TIME_LEVELS give MPS_E_UNSUPPORTED (they create
+ *    HIP objects).  There is no trace; device-side check results reach the
+ *    caller through opts->error_out.
+ *  - Every call on a device shares that device's scratch, which keeps the last
+ *    call's contents (the sort clears what it needs cleared itself).  Calls
+ *    that can overlap on one device -- on two streams, or from two threads --
+ *    race on it and must be serialised by the caller.
+ * Errors otherwise as mps_sort_ex. */
+int mps_sort_noalloc(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
+                     const mps_opts *opts, void *stream);
+uint64_t mps_noalloc_scratch_bytes(void);
+
 /* Records of a key and an 8-byte payload, such as the key-and-pointer records
  * of the paper's experiments with 16-byte records (Section 4): the stable sort
  * of mps_sort_ex, with payload (device, n u64) permuted with the keys.  The

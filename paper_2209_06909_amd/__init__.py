@@ -29,7 +29,8 @@ _STATUS = {-1: "MPS_E_INVALID", -2: "MPS_E_NOMEM", -3: "MPS_E_HIP", -4: "MPS_E_U
 KEY_I32, KEY_I64, KEY_F32 = 0, 1, 2
 
 EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "mps_sort_f32",
-            "mps_sort_ex", "mps_sort_kv64", "mps_sort_batched", "mps_autotune", "mps_sort_status",
+            "mps_sort_ex", "mps_sort_noalloc", "mps_noalloc_scratch_bytes", "mps_sort_kv64",
+            "mps_sort_batched", "mps_autotune", "mps_sort_status",
             "mps_free_workspaces", "mps_trace_fetch",
             "mps_last_level_stats", "mps_serve_create", "mps_serve_submit", "mps_serve_poll",
             "mps_serve_release", "mps_serve_stats", "mps_serve_destroy", "mps_serve_selftest",
@@ -133,6 +134,10 @@ def lib() -> ctypes.CDLL:
                 getattr(l, name).restype = i32
             l.mps_sort_ex.argtypes = [P, i32, P, u64, ctypes.POINTER(_Opts), ctypes.POINTER(_Trace), P]
             l.mps_sort_ex.restype = i32
+            l.mps_sort_noalloc.argtypes = [P, i32, P, u64, ctypes.POINTER(_Opts), P]
+            l.mps_sort_noalloc.restype = i32
+            l.mps_noalloc_scratch_bytes.argtypes = []
+            l.mps_noalloc_scratch_bytes.restype = u64
             l.mps_sort_kv64.argtypes = [P, i32, P, u64, ctypes.POINTER(_Opts), ctypes.POINTER(_Trace), P]
             l.mps_sort_kv64.restype = i32
             l.mps_sort_batched.argtypes = [P, i32, P, P, P, u64, u64, ctypes.POINTER(_Opts),
@@ -380,6 +385,32 @@ def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: b
                 setattr(tr, name, np.zeros(0, np.uint8))
         return tr
     return _fetch_trace(ctypes.c_void_p(ws.data_ptr()), t, trace_arrays)
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the fixed device scratch behind sort_noalloc (mps_noalloc_scratch_bytes)."""
+    return int(lib().mps_noalloc_scratch_bytes())
+
+
+def sort_noalloc(keys, payload=None, *, k: int = 4, stream=None, tile: int | None = None,
+                 lane_slice: int | None = None, min_run: int = 1, merge_down: bool = False,
+                 error_out=None):
+    """sort() through mps_sort_noalloc: the workspace is the library's fixed device
+    scratch, so the call allocates nothing (neither here nor in the library).  Only
+    for arrays whose workspace fits that scratch (MpsError MPS_E_NOMEM otherwise).
+    Asynchronous on `stream`; device-side check results go to `error_out` (a GPU
+    int32 tensor of one element) if given.  Calls that can overlap on one device
+    share the scratch and must not be issued concurrently."""
+    _check_tensors(keys, payload)
+    kt = key_type_of(keys)
+    st = _stream_of(keys.device, stream)
+    opts = _Opts(k=k, flags=(OPT_MERGE_DOWN if merge_down else 0), workspace=None,
+                 workspace_bytes=0, tile=int(tile or 0), lane_slice=int(lane_slice or 0),
+                 min_run=int(min_run or 1),
+                 error_out=error_out.data_ptr() if error_out is not None else None)
+    _check(lib().mps_sort_noalloc(ctypes.c_void_p(keys.data_ptr()), kt,
+                                  ctypes.c_void_p(payload.data_ptr()) if payload is not None else None,
+                                  keys.numel(), ctypes.byref(opts), ctypes.c_void_p(st.cuda_stream)))
 
 
 def sort_batched(keys, payload, offsets, *, k: int = 4, trace: bool = False,

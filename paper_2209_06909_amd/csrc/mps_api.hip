@@ -673,6 +673,70 @@ extern "C" int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uin
   return MPS_OK;
 }
 
+// ---------------------------------------------------------------- fixed scratch
+// The allocation-free entry point keeps a sort's whole workspace in this
+// file-scope device array.  Every device the library runs on holds its own
+// copy until the process ends.  In host code the name `scratch` is only a
+// stand-in for the symbol: the device address of a device's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever passed to a kernel.
+namespace {
+constexpr uint64_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];   // per device; set by the first call on that device
+
+int scratch_of_current_device(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MPS_E_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MPS_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPS_OK;
+}
+}  // namespace
+
+extern "C" uint64_t mps_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" int mps_sort_noalloc(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
+                                const mps_opts *opts, void *stream) {
+  g_err[0] = 0;
+  if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
+  if (n > 0 && !keys) return fail(MPS_E_INVALID, "keys is NULL");
+  if (n > (1ull << 31)) return fail(MPS_E_UNSUPPORTED, "arrays longer than 2^31 are not supported");
+  if (n <= 1) return MPS_OK;
+  mps_opts o{};
+  if (opts) o = *opts;
+  if (o.workspace)
+    return fail(MPS_E_INVALID, "mps_sort_noalloc uses the library's fixed scratch; opts->workspace must be NULL");
+  if (o.flags & (MPS_OPT_GRAPH | MPS_OPT_TIME_LEVELS))
+    return fail(MPS_E_UNSUPPORTED,
+                "MPS_OPT_GRAPH and MPS_OPT_TIME_LEVELS create HIP objects; not with mps_sort_noalloc");
+  uint32_t k = o.k;
+  int rc = check_k(k);
+  if (rc) return rc;
+  Layout L;
+  if (!make_layout(n, 1, kt, payload != nullptr, k, L)) return fail(MPS_E_INVALID, "bad sizes");
+  if (L.total > kScratchBytes)
+    return failf(MPS_E_NOMEM,
+                 "this sort needs %llu bytes of workspace; the fixed scratch of mps_sort_noalloc "
+                 "holds %llu (use mps_sort_ex for larger arrays)",
+                 (unsigned long long)L.total, (unsigned long long)kScratchBytes);
+  void *base = nullptr;
+  rc = scratch_of_current_device(&base);
+  if (rc) return rc;
+  o.workspace = base;
+  o.workspace_bytes = kScratchBytes;
+  return run_sort(keys, kt, payload, nullptr, 1, n, &o, nullptr, (hipStream_t)stream);
+}
+
 extern "C" int mps_sort(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n, void *stream) {
   return mps_sort_ex(keys, kt, payload, n, nullptr, nullptr, stream);
 }

@@ -99,3 +99,29 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode != 0
     assert "one GPU" in (p.stdout + p.stderr)
+
+
+def test_noalloc_argument_errors_need_no_gpu():
+    """mps_sort_noalloc checks its arguments and the fixed scratch's limit on the
+    host, before it looks up the scratch or enqueues anything."""
+    lib = mps.lib()
+    fake = ctypes.c_void_p(1 << 40)                                        # never dereferenced
+    scratch = lib.mps_noalloc_scratch_bytes()
+    assert scratch == 64 << 20
+    assert lib.mps_sort_noalloc(None, mps.KEY_I32, None, 10, None, None) == -1
+    assert lib.mps_sort_noalloc(fake, 9, None, 10, None, None) == -1
+    assert lib.mps_sort_noalloc(fake, mps.KEY_I32, None, 1, None, None) == 0   # no-op
+    assert lib.mps_sort_noalloc(fake, mps.KEY_I32, None, (1 << 31) + 1, None, None) == -4
+    o = mps._Opts(k=4, workspace=1 << 40, workspace_bytes=1 << 30)
+    assert lib.mps_sort_noalloc(fake, mps.KEY_I32, fake, 1000, ctypes.byref(o), None) == -1
+    for flag in (mps.OPT_GRAPH, mps.OPT_TIME_LEVELS):
+        o = mps._Opts(k=4, flags=flag)
+        assert lib.mps_sort_noalloc(fake, mps.KEY_I32, fake, 1000, ctypes.byref(o), None) == -4
+    o = mps._Opts(k=3)
+    assert lib.mps_sort_noalloc(fake, mps.KEY_I32, fake, 1000, ctypes.byref(o), None) == -4
+    # the largest fitting size and one past it, by the workspace formula
+    n = 1
+    while lib.mps_workspace_bytes(2 * n, 1, mps.KEY_I64, 1, 4) <= scratch:
+        n *= 2
+    assert lib.mps_sort_noalloc(fake, mps.KEY_I64, fake, 2 * n, None, None) == -2
+    assert b"fixed scratch" in lib.mps_last_error()
