@@ -84,7 +84,11 @@ typedef enum { MPS_I32 = 0, MPS_I64 = 1, MPS_F32 = 2 } mps_key_type;
                                    failed device-side check (bit 30 of the error word), to
                                    exercise the caller's error path */
 
-/* Options.  All fields may be zero for defaults. */
+/* Options.  All fields may be zero for defaults.  The defaults of k, tile and
+ * lane_slice can be set per process from the environment: MPS_K (2, 4 or 8),
+ * MPS_TILE (1024, 2048 or 4096) and MPS_LANE_SLICE (4 or 8), read once at the
+ * first call; unsupported values are ignored, and a lane slice that does not
+ * pair with the tile falls back to 4. */
 typedef struct {
     uint32_t k;                 /* merge arity: 2, 4 (default, the paper's 4-way) or 8 */
     uint32_t flags;             /* MPS_OPT_* bits */
@@ -213,7 +217,12 @@ int mps_sort_batched(void *keys, mps_key_type kt, uint32_t *payload, const uint6
  * using MPS_OPT_GRAPH will run).  cand_ms (nullable, 15 floats) receives every
  * candidate's mean time in ms.  The choice is cached per device, key type,
  * payload presence, log2(total keys) and log2(mean array size); a cached
- * choice is returned without timing unless cand_ms is requested.  Allocates
+ * choice is returned without timing unless cand_ms is requested.  If the
+ * environment variable MPS_AUTOTUNE_CACHE names a file, choices persist there
+ * across processes (one JSON object per line: GPU architecture name, key type,
+ * payload presence, both size buckets, graph flag, k, tile, lane_slice); the
+ * file is read at the first call on each device and every new choice is
+ * appended.  Allocates
  * tuner memory (about twice the sample plus a workspace) for the duration of
  * the call and synchronises `stream`.  Note that k changes the merge tree
  * (powers are base-k), never the sorted result. */

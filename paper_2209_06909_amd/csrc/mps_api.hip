@@ -12,6 +12,7 @@
 #include <map>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "mps.h"
@@ -217,8 +218,34 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   return true;
 }
 
+// Defaults of the zero-valued option fields, overridable from the environment:
+// MPS_K (2, 4 or 8), MPS_TILE (1024, 2048 or 4096) and MPS_LANE_SLICE (4 or 8).
+// Read once; an unparsable or unsupported value is ignored.
+struct EnvDefaults {
+  uint32_t k = 4, tile = (uint32_t)kTileDefault, lane_slice = 4;
+  EnvDefaults() {
+    auto num = [](const char *name) -> long {
+      const char *v = getenv(name);
+      if (!v || !*v) return -1;
+      char *end = nullptr;
+      long x = strtol(v, &end, 10);
+      return (end && *end == 0) ? x : -1;
+    };
+    long x = num("MPS_K");
+    if (x == 2 || x == 4 || x == 8) k = (uint32_t)x;
+    x = num("MPS_TILE");
+    if (x == 1024 || x == 2048 || x == 4096) tile = (uint32_t)x;
+    x = num("MPS_LANE_SLICE");
+    if (x == 4 || x == 8) lane_slice = (uint32_t)x;
+  }
+};
+const EnvDefaults &env_defaults() {
+  static const EnvDefaults d;
+  return d;
+}
+
 int check_k(uint32_t &k) {
-  if (k == 0) k = 4;
+  if (k == 0) k = env_defaults().k;
   if (k != 2 && k != 4 && k != 8)
     return fail(MPS_E_UNSUPPORTED, "k must be 2, 4 or 8");
   return MPS_OK;
@@ -438,9 +465,14 @@ int graph_launch(const GraphKey &key, void *keys, int kt, uint32_t *payload,
 }
 
 int resolve_tile(const mps_opts *opts, int &tile, int &threads) {
-  uint32_t t = opts && opts->tile ? opts->tile : (uint32_t)kTileDefault;
+  const EnvDefaults &ed = env_defaults();
+  uint32_t t = opts && opts->tile ? opts->tile : ed.tile;
   uint32_t e = opts ? opts->lane_slice : 0;
-  if (e == 0) e = 4;
+  if (e == 0) e = opts && opts->tile ? 4 : ed.lane_slice;
+  if (!tile_config_ok((int)t, (int)(t / e))) {
+    // an environment default that does not pair with the tile falls back to 4
+    if (!(opts && opts->lane_slice)) e = 4;
+  }
   if (t != 1024 && t != 2048 && t != 4096) return fail(MPS_E_UNSUPPORTED, "tile must be 1024, 2048 or 4096");
   if (e != 4 && e != 8) return fail(MPS_E_UNSUPPORTED, "lane_slice must be 4 or 8");
   if (!tile_config_ok((int)t, (int)(t / e)))

@@ -7,7 +7,17 @@
 // it, timed with HIP events on the caller's stream.  Results are cached per
 // (device, key type, payload presence, log2 of the total size, log2 of the
 // mean array size), so later batches of the same shape skip the timing.
+//
+// If the environment names a file in MPS_AUTOTUNE_CACHE, choices also persist
+// across processes: the file holds one JSON object per line (the GPU
+// architecture name, key type, payload presence, the two size buckets, graph
+// replay, and the chosen k, tile and lane slice).  It is read once, at the
+// first tuning call; every new choice is appended to it.  Lines of another
+// architecture, or that do not parse, are ignored.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -31,6 +41,58 @@ struct TuneVal {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
+bool g_file_loaded[64];
+
+// Architecture name of a device (e.g. "gfx950:sramecc+:xnack-"); "" on failure.
+std::string arch_of(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return std::string();
+  return std::string(p.gcnArchName);
+}
+
+const char *cache_path() {
+  const char *p = getenv("MPS_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+// Loads the persisted choices of this device's architecture (call with g_tune_mu held).
+void load_cache_file(int dev, const std::string &arch) {
+  if (dev < 0 || dev >= 64 || g_file_loaded[dev]) return;
+  g_file_loaded[dev] = true;
+  const char *path = cache_path();
+  if (!path || arch.empty()) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  char line[512], a[128];
+  while (fgets(line, sizeof line, f)) {
+    int kt, pay, lt, lm, gr;
+    unsigned k, tile, ls;
+    if (sscanf(line,
+               " {\"arch\": \"%127[^\"]\", \"kt\": %d, \"payload\": %d, \"lg_total\": %d, "
+               "\"lg_mean\": %d, \"graph\": %d, \"k\": %u, \"tile\": %u, \"lane_slice\": %u}",
+               a, &kt, &pay, &lt, &lm, &gr, &k, &tile, &ls) != 9)
+      continue;
+    if (arch != a) continue;
+    if ((k != 2 && k != 4 && k != 8) || (tile != 1024 && tile != 2048 && tile != 4096) ||
+        (ls != 4 && ls != 8))
+      continue;
+    g_tune_cache[TuneKey{dev, kt, pay, lt, lm, gr}] = TuneVal{k, tile, ls};
+  }
+  fclose(f);
+}
+
+void append_cache_file(const std::string &arch, const TuneKey &key, const TuneVal &v) {
+  const char *path = cache_path();
+  if (!path || arch.empty()) return;
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f,
+          "{\"arch\": \"%s\", \"kt\": %d, \"payload\": %d, \"lg_total\": %d, \"lg_mean\": %d, "
+          "\"graph\": %d, \"k\": %u, \"tile\": %u, \"lane_slice\": %u}\n",
+          arch.c_str(), key.kt, key.has_payload, key.lg_total, key.lg_mean, key.graph, v.k, v.tile,
+          v.lane_slice);
+  fclose(f);
+}
 
 // Candidates: arity x tile configuration.
 const uint32_t kArities[3] = {4, 2, 8};
@@ -69,8 +131,10 @@ extern "C" int mps_autotune(const void *keys, mps_key_type kt, const uint32_t *p
   if (hipGetDevice(&dev) != hipSuccess) return mps::fail_msg(MPS_E_HIP, "hipGetDevice failed");
   const TuneKey key{dev, (int)kt, payload ? 1 : 0, ilog2(total ? total : 1),
                     ilog2(total / m ? total / m : 1), (flags & MPS_OPT_GRAPH) ? 1 : 0};
+  const std::string arch = cache_path() ? arch_of(dev) : std::string();
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_file(dev, arch);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end() && !cand_ms) {
       best->k = it->second.k;
@@ -164,6 +228,7 @@ extern "C" int mps_autotune(const void *keys, mps_key_type kt, const uint32_t *p
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = TuneVal{bk, bt, bl};
+    append_cache_file(arch, key, TuneVal{bk, bt, bl});
   }
   best->k = bk;
   best->tile = bt;
