@@ -192,7 +192,7 @@ constexpr int kTileMin = 1024;
 // level merge).  A multiple of 64.
 constexpr uint64_t kSampleStride = 64;
 constexpr int kTileDefault = 2048;
-constexpr int kTileDescBytes = 256;  // >= sizeof(TileDesc<8>)
+constexpr int kTileDescBytes = 256;  // >= sizeof(TileTab<8>), the per-tile merge table
 
 inline bool tile_config_ok(int tile, int threads) {
   return (tile == 1024 && threads == 256) || (tile == 2048 && threads == 256) ||

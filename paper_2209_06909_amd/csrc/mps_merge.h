@@ -270,21 +270,29 @@ __device__ inline TileGeom tile_geom(uint64_t tile, int tsize, uint64_t L, uint6
   return g;
 }
 
-// Per-tile descriptor for tiles that touch at most two nodes (the common case
-// once nodes are larger than a tile): global start and length of every input
-// slice and the output start of every piece, so that the merge kernel does not
-// chase node records through dependent global loads.
+// Tables of a tile that touches at most two nodes (the common case once
+// nodes are larger than a tile), built by the descriptor kernel for the merge
+// kernel, which copies them to LDS word by word: the tile's input slices are
+// staged back to back in LDS; slice s starts at LDS position sl_off[s], and
+// the global index of LDS position e of slice s is delta[s] + e.  Piece p (a
+// node's part of the tile) starts at LDS position pc_loff[p] and slice
+// pc_sl[p], and its first output goes to global index pc_out[p].  kind says
+// which merge path takes the tile (kTabFast: this table; kTabGeneral: the
+// general kernel; kTabBad: an inconsistent cut).
+enum { kTabNone = 0, kTabFast = 1, kTabGeneral = 2, kTabBad = 3 };
+
 template <int K>
-struct TileDesc {
-  uint64_t out[2];
-  uint64_t src[2][K];
-  uint32_t len[2][K];
-  uint32_t d[2];
-  uint32_t npieces;   // 1 or 2: use this descriptor; 0: general setup; kBadTile: inconsistent
-  uint32_t total;
+struct TileTab {
+  uint64_t delta[2 * K];
+  uint64_t pc_out[2];
+  uint16_t sl_off[2 * K + 2];
+  uint16_t pc_loff[3];
+  uint16_t pc_sl[3];
+  int32_t S, P, Tt, kind;
 };
-constexpr uint32_t kBadTile = 0xFFFFFFFFu;
-static_assert(sizeof(TileDesc<8>) <= kTileDescBytes, "tile descriptor slot too small");
+static_assert(sizeof(TileTab<8>) <= kTileDescBytes, "tile table slot too small");
+static_assert(sizeof(TileTab<8>) % 4 == 0 && sizeof(TileTab<8>) / 4 <= 64,
+              "a tile table is copied by the lanes of one wave, a word each");
 
 template <int K>
 __global__ __launch_bounds__(256) void k_tile_desc(
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(256) void k_tile_desc(
     const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
     const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
     const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level, int tsize,
-    const uint32_t *__restrict__ cr, TileDesc<K> *__restrict__ desc,
+    const uint32_t *__restrict__ cr, TileTab<K> *__restrict__ desc,
     uint32_t *__restrict__ gen_list) {
   const uint64_t tiles = plan->lvl_tiles[level];
   if (tiles == 0) return;
@@ -305,71 +313,67 @@ __global__ __launch_bounds__(256) void k_tile_desc(
   const uint32_t *tjl = tj + tile_base[level];
   for (uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; tile < tiles;
        tile += (uint64_t)gridDim.x * blockDim.x) {
-    TileDesc<K> D;
+    TileTab<K> X;
+    for (int s = 0; s < 2 * K; s++) X.delta[s] = 0;
+    for (int s = 0; s < 2 * K + 2; s++) X.sl_off[s] = 0;
+    for (int p = 0; p < 3; p++) { X.pc_loff[p] = 0; X.pc_sl[p] = 0; }
+    X.pc_out[0] = X.pc_out[1] = 0;
+    X.S = 0;
+    X.P = 0;
     TileGeom g = tile_geom(tile, tsize, L, nlev, np, lb, np0, tjl);
-    D.total = (uint32_t)(g.Q1 - g.Q0);
-    D.npieces = 0;
-    for (int p = 0; p < 2; p++) {
-      D.out[p] = 0;
-      D.d[p] = 0;
-      for (int j = 0; j < K; j++) { D.src[p][j] = 0; D.len[p][j] = 0; }
-    }
+    X.Tt = (int32_t)(g.Q1 - g.Q0);
     if (!g.ok) {
-      D.npieces = kBadTile;
+      X.kind = kTabBad;
     } else if (g.j1 - g.j0 + 1 <= 2) {
       const int P = (int)(g.j1 - g.j0 + 1);
-      uint64_t sum = 0;
+      int off = 0, s = 0;
       bool bad = false;
       for (int p = 0; p < P && !bad; p++) {
         uint64_t j = g.j0 + p;
         NodeIn nd;
         if (!load_node<K>(list[lb + j], r, rs, Ls, Rs, mem, arity, nd)) { bad = true; break; }
-        bool first = p == 0;
-        bool cut_end = p == P - 1 && g.Q1 < np[lb + j + 1] - np0;
-        D.d[p] = (uint32_t)nd.d;
-        D.out[p] = nd.c[0] + (first ? g.Q0 - (np[lb + j] - np0) : 0);
+        const bool first = p == 0;
+        const bool cut_end = p == P - 1 && g.Q1 < np[lb + j + 1] - np0;
+        X.pc_loff[p] = (uint16_t)off;
+        X.pc_sl[p] = (uint16_t)s;
+        X.pc_out[p] = nd.c[0] + (first ? g.Q0 - (np[lb + j] - np0) : 0);
         for (int jj = 0; jj < nd.d; jj++) {
-          uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
-          uint32_t c0 = first ? cr[tile * K + jj] : 0;
-          uint32_t c1 = cut_end ? cr[(tile + 1) * K + jj] : len;
-          if (c1 > len || c0 > c1) { bad = true; break; }
-          D.src[p][jj] = nd.c[jj] + c0;
-          D.len[p][jj] = c1 - c0;
-          sum += c1 - c0;
+          const uint32_t len = (uint32_t)(nd.c[jj + 1] - nd.c[jj]);
+          const uint32_t c0 = first ? cr[tile * K + jj] : 0;
+          const uint32_t c1 = cut_end ? cr[(tile + 1) * K + jj] : len;
+          if (c1 > len || c0 > c1 || off + (int)(c1 - c0) > X.Tt) { bad = true; break; }
+          X.sl_off[s] = (uint16_t)off;
+          X.delta[s] = nd.c[jj] + c0 - (uint64_t)off;
+          off += (int)(c1 - c0);
+          s++;
         }
       }
-      D.npieces = (bad || sum != D.total) ? kBadTile : (uint32_t)P;
+      X.pc_loff[P] = (uint16_t)off;
+      X.pc_sl[P] = (uint16_t)s;
+      X.sl_off[s] = (uint16_t)off;
+      X.S = s;
+      X.P = P;
+      X.kind = (bad || off != X.Tt) ? kTabBad : kTabFast;
     } else {
+      X.kind = kTabGeneral;
       gen_list[atomicAdd(&plan->gen_cnt[level], 1u)] = (uint32_t)tile;
     }
-    desc[tile] = D;
+    desc[tile] = X;
   }
 }
 
-// Small tables of one descriptor-described tile (double-buffered: the next
-// tile's tables are built while the current tile is merged).
-enum { kTabNone = 0, kTabFast = 1, kTabGeneral = 2, kTabBad = 3 };
-
-template <int K>
-struct SmallTab {
-  uint64_t delta[2 * K];   // sl_g[s] - sl_off[s]: global index of LDS position e is delta[s] + e
-  uint64_t sl_g[2 * K];
-  uint64_t pc_out[2];
-  uint16_t sl_off[2 * K + 2];
-  uint16_t pc_loff[3];
-  uint16_t pc_sl[3];
-  int S, P, Tt, kind;
-};
-
 // LDS of the descriptor-tile kernel: one stage buffer (the stages merge in
-// place through registers) and the small tables.
+// place through registers) and the tables of the current and the next tile.
+// The keys have 16 bytes of padding in front and behind: a lane's outputs are
+// written back 16 bytes at a time, and a search probe of an empty range may
+// read one element before or after the keys.
 template <typename O, int K, int TILE>
 struct FastSmem {
-  static constexpr size_t kBuf = (size_t)(TILE + 2) * sizeof(O) + (size_t)TILE * 4;
-  static constexpr int kDescWords = (int)(sizeof(TileDesc<K>) / 4);
+  static constexpr size_t kKeyBytes = (size_t)(TILE + 4) * 8;
+  static constexpr size_t kBuf = kKeyBytes + (size_t)TILE * 4;
+  static constexpr int kTabWords = (int)(sizeof(TileTab<K>) / 4);
   alignas(16) unsigned char bufA[kBuf];
-  SmallTab<K> tab[2];
-  alignas(16) uint32_t raw[kDescWords];
+  TileTab<K> tab[2];
   uint32_t claim[2];   // tile indices taken from the work queue
 };
 
@@ -404,37 +408,6 @@ __device__ inline int ub16(const uint16_t *a, int n, T x) {
   return lo;
 }
 
-// Thread 0: build a small table from the raw descriptor words in LDS.
-template <int K>
-__device__ inline void build_small(SmallTab<K> &T, const TileDesc<K> &D, bool exists) {
-  if (!exists) { T.kind = kTabNone; return; }
-  uint32_t np = D.npieces;
-  T.Tt = (int)D.total;
-  if (np == kBadTile || np > 2) { T.kind = kTabBad; return; }
-  if (np == 0) { T.kind = kTabGeneral; return; }
-  int s = 0, off = 0;
-  for (int p = 0; p < (int)np; p++) {
-    T.pc_loff[p] = (uint16_t)off;
-    T.pc_sl[p] = (uint16_t)s;
-    T.pc_out[p] = D.out[p];
-    int d = (int)D.d[p];
-    if (d > K) d = K;
-    for (int j = 0; j < d; j++) {
-      T.sl_off[s] = (uint16_t)off;
-      T.sl_g[s] = D.src[p][j];
-      T.delta[s] = D.src[p][j] - (uint64_t)off;
-      off += (int)D.len[p][j];
-      s++;
-    }
-  }
-  T.pc_loff[np] = (uint16_t)off;
-  T.pc_sl[np] = (uint16_t)s;
-  T.sl_off[s] = (uint16_t)off;
-  T.S = s;
-  T.P = (int)np;
-  T.kind = off == T.Tt ? kTabFast : kTabBad;
-}
-
 // Global addresses of a thread's E positions (t + i*THREADS).  Positions past
 // the tile end are clamped to its last element (loaded, never used), so the
 // loads that follow form one straight-line block: the compiler then issues
@@ -451,22 +424,30 @@ __device__ inline void addr_table(uint64_t (&g)[E], const uint16_t *pos_sl,
   }
 }
 
-// Same for a descriptor tile: the slice of position e is the number of slice
-// starts (after the first) at or below e; its global index is delta[s] + e.
-template <int E, int THREADS, int MAXS>
-__device__ inline void addr_desc(uint64_t (&g)[E], const uint16_t *sl_off, const uint64_t *delta,
-                                 int S, int Tt, int t) {
-  int so[MAXS];
-#pragma unroll
-  for (int j = 1; j < MAXS; j++) so[j] = j < S ? (int)sl_off[j] : 0x7FFFFFFF;
+// Same for a descriptor tile: the global index of LDS position e in slice s
+// is delta[s] + e.  A wave's 64 consecutive positions t + i*THREADS usually
+// lie in one slice, found with one ballot over the slice starts (lane j holds
+// the start of slice j); only a wave whose positions cross a slice start
+// compares per lane.
+template <int E, int THREADS, int K>
+__device__ inline void addr_desc(uint64_t (&g)[E], const TileTab<K> &T, int t) {
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int S = T.S, Tt = T.Tt;
+  const int so = (lane >= 1 && lane < S) ? (int)T.sl_off[lane] : 0x7FFFFFFF;
 #pragma unroll
   for (int i = 0; i < E; i++) {
-    int e = t + i * THREADS;
-    int ec = e < Tt ? e : Tt - 1;
-    int s = 0;
-#pragma unroll
-    for (int j = 1; j < MAXS; j++) s += so[j] <= ec ? 1 : 0;
-    g[i] = delta[s] + (uint64_t)ec;
+    const int x0 = (w + i * (THREADS / 64)) * 64;
+    const int e = x0 + lane;
+    const int ec = e < Tt ? e : Tt - 1;
+    const int x1 = x0 + 63 < Tt - 1 ? x0 + 63 : Tt - 1;
+    const int s0 = __builtin_popcountll(__ballot(so <= x0));
+    const int s1 = __builtin_popcountll(__ballot(so <= x1));
+    int s = s0;
+    if (s1 != s0) {
+      for (int j = s0 + 1; j <= s1; j++) s += (int)T.sl_off[j] <= ec ? 1 : 0;
+    }
+    g[i] = T.delta[s] + (uint64_t)ec;
   }
 }
 
@@ -618,10 +599,23 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
   const int e0 = t * E;
   const int e1 = e0 + E < Tt ? e0 + E : Tt;
   const bool full = e1 - e0 == E;
+  // slices of the lane's first and last output.  8-byte keys: counts of the
+  // slice starts at or below them (the starts are the same for the whole
+  // workgroup); 4-byte keys: binary searches in the LDS table, which keeps
+  // that kernel within 64 registers
   int sa = 0, sb = 0;
   if (e0 < e1) {
-    sa = ub16(sl_off_l, S + 1, e0) - 1;
-    sb = ub16(sl_off_l, S + 1, e1 - 1) - 1;
+    if constexpr (sizeof(O) == 8) {
+#pragma unroll
+      for (int j = 1; j < 2 * K; j++) {
+        const int so = __builtin_amdgcn_readfirstlane(j < S ? (int)sl_off_l[j] : 0x7FFFFFFF);
+        sa += so <= e0 ? 1 : 0;
+        sb += so <= e1 - 1 ? 1 : 0;
+      }
+    } else {
+      sa = ub16(sl_off_l, S + 1, e0) - 1;
+      sb = ub16(sl_off_l, S + 1, e1 - 1) - 1;
+    }
   }
   const char *kb8 = reinterpret_cast<const char *>(ks);
 #pragma unroll
@@ -661,16 +655,20 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
       const int swi = two ? u2 - e0 : E;
 #pragma unroll
       for (int i = 0; i < E; i++) {
-        if (i > 0 && i == swi) {
-          const int pendB = sb >= s1 ? S : s1;
-          const int iMB = gb + h < pendB ? gb + h : pendB;
-          const int iRB = gb + 2 * h < pendB ? gb + 2 * h : pendB;
-          pa = (uint32_t)u2 * KS;
-          pb = (uint32_t)sl_off_l[iMB] * KS;
-          ea = pb;
-          eb = (uint32_t)sl_off_l[iRB] * KS;
-          ka = *reinterpret_cast<const O *>(kb8 + pa);
-          kb = *reinterpret_cast<const O *>(kb8 + pb);
+        // few waves hold a lane that switches units: a wave vote skips the
+        // switch for the others
+        if (i > 0 && __any(i == swi)) {
+          if (i == swi) {
+            const int pendB = sb >= s1 ? S : s1;
+            const int iMB = gb + h < pendB ? gb + h : pendB;
+            const int iRB = gb + 2 * h < pendB ? gb + 2 * h : pendB;
+            pa = (uint32_t)u2 * KS;
+            pb = (uint32_t)sl_off_l[iMB] * KS;
+            ea = pb;
+            eb = (uint32_t)sl_off_l[iRB] * KS;
+            ka = *reinterpret_cast<const O *>(kb8 + pa);
+            kb = *reinterpret_cast<const O *>(kb8 + pb);
+          }
         }
         const bool takeL = pa < ea && (pb >= eb || ka <= kb);
         ok[i] = takeL ? ka : kb;
@@ -734,11 +732,31 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
     }
     lds_barrier();   // every read of this stage is done
     if (full) {
+      // 8-byte keys: 16 bytes per LDS write (ks + e0 and vs + e0 are 16-byte
+      // aligned); 4-byte keys: one element per write, which keeps that kernel
+      // within 64 registers
+      if constexpr (sizeof(O) == 8) {
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-      for (int i = 0; i < E; i++) ks[e0 + i] = ok[i];
-      if (HV) {
+        for (int i = 0; i < E / 2; i++) {
+          u64x2 v;
+          v.x = ok[2 * i];
+          v.y = ok[2 * i + 1];
+          reinterpret_cast<u64x2 *>(ks + e0)[i] = v;
+        }
+        if (HV) {
 #pragma unroll
-        for (int i = 0; i < E; i++) vs[e0 + i] = pv[i];
+          for (int i = 0; i < E / 4; i++)
+            reinterpret_cast<uint4 *>(vs + e0)[i] =
+                make_uint4(pv[4 * i], pv[4 * i + 1], pv[4 * i + 2], pv[4 * i + 3]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; i++) ks[e0 + i] = ok[i];
+        if (HV) {
+#pragma unroll
+          for (int i = 0; i < E; i++) vs[e0 + i] = pv[i];
+        }
       }
     } else {
 #pragma unroll
@@ -773,24 +791,46 @@ __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
   }
 }
 
-// store_tile for a descriptor tile (one or two pieces): the output index of
-// position e is base0 + e before the second piece and base1 + e from it on.
+// Coalesced stores of a descriptor tile (one or two pieces): the output index
+// of position e is base0 + e before the second piece and base1 + e from it on.
+// The base is chosen once per wave unless the piece split falls among the
+// wave's 64 positions.
 template <typename Kt, typename O, int E, int THREADS>
-__device__ inline void store_tile2(const O *ks, const uint32_t *vs, O *out_keys,
-                                   uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
-                                   const uint64_t *pc_out, int P, int Tt, int t, uint64_t *smp) {
+__device__ inline void store_fast(const O *ks, const uint32_t *vs, O *out_keys, uint32_t *out_vals,
+                                  bool has_vals, const uint16_t *pc_loff, const uint64_t *pc_out,
+                                  int P, int Tt, int t) {
   const int split = P == 2 ? (int)pc_loff[1] : Tt;
   const uint64_t base0 = pc_out[0] - (uint64_t)pc_loff[0];
   const uint64_t base1 = P == 2 ? pc_out[1] - (uint64_t)pc_loff[1] : base0;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
 #pragma unroll
   for (int i = 0; i < E; i++) {
-    int e = t + i * THREADS;
+    const int x0 = (w + i * (THREADS / 64)) * 64;
+    const int e = x0 + lane;
+    uint64_t base;
+    if (x0 + 63 < split) base = base0;
+    else if (x0 >= split) base = base1;
+    else base = e < split ? base0 : base1;
     if (e < Tt) {
-      uint64_t g = (e < split ? base0 : base1) + (uint64_t)e;
+      const uint64_t g = base + (uint64_t)e;
       out_keys[g] = Kt::unord(ks[e]);
       if (has_vals) out_vals[g] = vs[e];
-      if ((g & (kSampleStride - 1)) == 0) smp[g / kSampleStride] = (uint64_t)ks[e];
     }
+  }
+}
+
+// The co-rank samples among a descriptor tile's outputs (every
+// kSampleStride-th global position), written by the lanes of one wave.
+template <typename O>
+__device__ inline void store_samples(const O *ks, const uint16_t *pc_loff, const uint64_t *pc_out,
+                                     int P, int Tt, int lane, uint64_t *smp) {
+  for (int p = 0; p < P && p < 2; p++) {
+    const int l0 = pc_loff[p], l1 = p + 1 < P ? (int)pc_loff[p + 1] : Tt;
+    const uint64_t g0 = pc_out[p], g1 = g0 + (uint64_t)(l1 - l0);
+    const uint64_t q0 = (g0 + kSampleStride - 1) / kSampleStride;
+    for (uint64_t q = q0 + (uint64_t)lane; q * kSampleStride < g1; q += 64)
+      smp[q] = (uint64_t)ks[l0 + (int)(q * kSampleStride - g0)];
   }
 }
 
@@ -803,9 +843,10 @@ constexpr int kGenClaim = 4;
 
 // Descriptor tiles.  Each workgroup takes tiles from the level's work queue
 // (kFastClaim at a time, skipping those of the general path) and processes
-// them software-pipelined: while tile i is merged in LDS, the descriptor of
-// tile i+2 and the input slices of tile i+1 are already being fetched into
-// registers, so global latency overlaps the LDS work.
+// them software-pipelined: while tile i is merged in LDS, the table of tile
+// i+2 and the input slices of tile i+1 are already being fetched into
+// registers, so global latency overlaps the LDS work.  A tile's table is
+// copied to LDS by the lanes of the first wave, one word each.
 template <int KT, int K, int TILE, int THREADS, bool HV>
 // With 4-byte keys, k <= 4 and 4 outputs per lane the kernel fits in 64
 // registers, which lets 4 workgroups of 512 threads share a CU.
@@ -813,24 +854,23 @@ __global__ __launch_bounds__(THREADS, (sizeof(typename Key<KT>::U) == 4 && K <= 
 void k_merge_fast(
     const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
-    Plan *__restrict__ plan, int level, const TileDesc<K> *__restrict__ desc,
+    Plan *__restrict__ plan, int level, const TileTab<K> *__restrict__ desc,
     uint64_t *__restrict__ smp) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
   using SM = FastSmem<O, K, TILE>;
   constexpr int E = TILE / THREADS;
-  constexpr int NW = SM::kDescWords;
-  constexpr int DW = (int)(sizeof(TileDesc<K>) / 4);
-  constexpr int MAXS = 2 * K;
+  constexpr int NW = SM::kTabWords;
   __shared__ SM sm;
-  O *kA = reinterpret_cast<O *>(sm.bufA);
-  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)(TILE + 2) * sizeof(O));
+  O *kA = reinterpret_cast<O *>(sm.bufA + 16);
+  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + SM::kKeyBytes);
   const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
 
   const uint64_t tiles = plan->lvl_tiles[level];
   if (tiles == 0) return;
   uint32_t *queue = &plan->q_fast[level];
   const int t = threadIdx.x;
+  const int lane = t & 63;
 
   if (t == 0) sm.claim[0] = atomicAdd(queue, (uint32_t)kFastClaim);
   __syncthreads();
@@ -843,17 +883,15 @@ void k_merge_fast(
   O kreg[E];
   uint32_t vreg[E];
   uint64_t ga[E];
-  uint32_t dreg = 0;   // one word of a prefetched descriptor (lanes 0..NW-1)
+  uint32_t dreg = 0;   // one word of a prefetched table (lanes 0..NW-1)
 
-  // prologue: tables of the first tile, descriptor of the second, loads of the first
-  if (t < NW) sm.raw[t] = descw[tile * DW + t];
+  // prologue: table of the first tile, then the loads of the first tile and
+  // the table of the second
+  if (t < NW) reinterpret_cast<uint32_t *>(&sm.tab[0])[t] = descw[tile * NW + t];
   lds_barrier();
-  if (t == 0) build_small<K>(sm.tab[0], *reinterpret_cast<const TileDesc<K> *>(sm.raw), true);
-  lds_barrier();
-  if (t < NW && nxt < tiles) dreg = descw[nxt * DW + t];
+  if (t < NW && nxt < tiles) dreg = descw[nxt * NW + t];
   if (sm.tab[0].kind == kTabFast) {
-    addr_desc<E, THREADS, MAXS>(ga, sm.tab[0].sl_off, sm.tab[0].delta, sm.tab[0].S,
-                                sm.tab[0].Tt, t);
+    addr_desc<E, THREADS, K>(ga, sm.tab[0], t);
     issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
   }
   int cur = 0;
@@ -863,32 +901,29 @@ void k_merge_fast(
     const bool reclaim = cidx == kFastClaim;
     uint32_t claimed = 0;
     if (reclaim && t == 0) claimed = atomicAdd(queue, (uint32_t)kFastClaim);
-    SmallTab<K> &T = sm.tab[cur];
-    SmallTab<K> &N = sm.tab[cur ^ 1];
+    TileTab<K> &T = sm.tab[cur];
+    TileTab<K> &N = sm.tab[cur ^ 1];
     const int kind = T.kind;
     if (kind == kTabFast) commit_loads<Kt, O, E, THREADS>(kreg, vreg, kA, vA, HV, T.Tt, t);
-    // next tile's tables from its prefetched descriptor; then fetch ahead
-    if (t < NW) sm.raw[t] = dreg;
-    lds_barrier();
-    if (t == 0) {
-      build_small<K>(N, *reinterpret_cast<const TileDesc<K> *>(sm.raw), nxt < tiles);
-      if (reclaim) sm.claim[1] = claimed;
-    }
+    // next tile's table from its prefetched words (kTabNone past the end)
+    if (t < NW) reinterpret_cast<uint32_t *>(&N)[t] = nxt < tiles ? dreg : 0u;
+    if (t == 0 && reclaim) sm.claim[1] = claimed;
     lds_barrier();
     if (reclaim) {
       cbase = sm.claim[1];
       cidx = 0;
     }
     const uint64_t after = cbase + (uint64_t)cidx++;
-    if (t < NW && after < tiles) dreg = descw[after * DW + t];
+    if (t < NW && after < tiles) dreg = descw[after * NW + t];
     if (N.kind == kTabFast) {
-      addr_desc<E, THREADS, MAXS>(ga, N.sl_off, N.delta, N.S, N.Tt, t);
+      addr_desc<E, THREADS, K>(ga, N, t);
       issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
     }
     if (kind == kTabFast) {
       merge_stages_inplace<O, K, TILE, THREADS, HV>(kA, vA, T.sl_off, T.S, T.pc_sl, T.P, T.Tt, t);
-      store_tile2<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV,
-                                    T.pc_loff, T.pc_out, T.P, T.Tt, t, smp);
+      store_fast<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV, T.pc_loff, T.pc_out, T.P,
+                                    T.Tt, t);
+      if (t >= THREADS - 64) store_samples<O>(kA, T.pc_loff, T.pc_out, T.P, T.Tt, lane, smp);
     } else if (kind == kTabBad) {
       if (t == 0) atomicOr(&plan->error, 32u);
     }
@@ -1120,7 +1155,7 @@ template <int KT, int K, int TILE, int THREADS>
 void launch_merges_kt(const LevelArgs &a, const Work &w, const uint32_t *tj,
                       const uint64_t *tile_base, int level, hipStream_t s) {
   using U = typename Key<KT>::U;
-  const TileDesc<K> *desc = reinterpret_cast<const TileDesc<K> *>(w.tile_desc);
+  const TileTab<K> *desc = reinterpret_cast<const TileTab<K> *>(w.tile_desc);
   if (a.in_vals) {
     auto kf = k_merge_fast<KT, K, TILE, THREADS, true>;
     auto kg = k_merge_general<KT, K, TILE, THREADS, true>;
