@@ -116,7 +116,7 @@ struct Layout {
   size_t total = 0;
   size_t alt_keys, alt_vals, seg_off, seg_bits, dbits, det_agg, det_zin, det_off, run_start, run_desc,
       power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
-      dist0, dist1, leaf_depth, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
+      dist0, dist1, leaf_depth, sflag, cfirst, croot, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
       tj, samples, plan, nat_start, nat_desc, mr_first, mr_nxt, mr_cnt, mr_gnxt, mr_gcnt,
       mr_gentry, mr_goff, mr_centry, mr_coff;
   uint64_t rmax, nbb, tiles_max, tj_cap;
@@ -183,6 +183,9 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.dist0 = take(c, rmax + 1);
   L.dist1 = take(c, rmax + 1);
   L.leaf_depth = take(c, rmax);
+  L.sflag = take(c, rmax + 1);
+  L.cfirst = take(c, (N / kLeafChunk + 2) * 4);
+  L.croot = take(c, (N / kLeafChunk + 2) * kChunkRec * 4);
   L.lvl_cnt = take(c, nbb * kMaxLevels * 4);
   L.lvl_tot = take(c, kMaxLevels * 8);
   L.lvl_list = take(c, rmax * 4);
@@ -327,8 +330,10 @@ int fill_trace(void *base, mps_trace *tr) {
   if (tr->run_start) memcpy(tr->run_start, rs.data(), (r + 1) * 8);
   if (tr->run_desc && r) HIP_TRY(hipMemcpy(tr->run_desc, at<uint8_t>(base, L.run_desc), r, hipMemcpyDeviceToHost));
   if (tr->power && r > 1) memcpy(tr->power, P.data() + 1, r - 1);
-  if (tr->leaf_depth && r)
+  if (tr->leaf_depth && r) {
     HIP_TRY(hipMemcpy(tr->leaf_depth, at<uint8_t>(base, L.leaf_depth), r, hipMemcpyDeviceToHost));
+    for (uint64_t j = 0; j < r; j++) tr->leaf_depth[j] &= (uint8_t)~kLeafInSmall;
+  }
   if (want_nodes && r > 1) {
     std::vector<uint32_t> Ls(r + 1), Rs(r + 1), Le(r + 1);
     std::vector<uint8_t> ar(r + 1), dep(r + 1);
@@ -389,6 +394,7 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
   HIP_TRY(launch_tree(w, want_cost, lvl_tot, tile_base, tj, gtree, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_place(kt, keys, payload, w, s));
+  HIP_TRY(launch_leaf(kt, keys, payload, w, s));
   for (int d = L.levels - 1; d >= 0; d--) {
     LevelArgs a;
     bool out_user = (d & 1) == 0;
@@ -564,6 +570,9 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   w.dist0 = at<uint8_t>(base, L.dist0);
   w.dist1 = at<uint8_t>(base, L.dist1);
   w.leaf_depth = at<uint8_t>(base, L.leaf_depth);
+  w.sflag = at<uint8_t>(base, L.sflag);
+  w.cfirst = at<uint32_t>(base, L.cfirst);
+  w.croot = at<uint32_t>(base, L.croot);
   w.lvl_cnt = at<uint32_t>(base, L.lvl_cnt);
   w.lvl_list = at<uint32_t>(base, L.lvl_list);
   w.lvl_np = at<uint64_t>(base, L.lvl_np);

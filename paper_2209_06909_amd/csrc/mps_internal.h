@@ -60,7 +60,33 @@ struct Plan {
   uint32_t q_gen[kMaxLevels];
   uint32_t jump_more[8];             // pointer-jumping round i left a target that is not a root
   uint64_t r_nat;                    // natural runs, when a minimal run length replaced them
+  uint64_t n_small;                  // nodes of span <= kSmallSpan (merged by the small-subtree pass)
+  uint32_t small_depth_end;          // 1 + deepest depth of such a node (0: none)
+  uint32_t pad2;
 };
+
+// Small subtrees: a node whose span is at most kSmallSpan elements is
+// finished, with its whole subtree, by one workgroup in LDS (the small-subtree
+// pass); the level merges handle only the larger nodes.  The pass takes the
+// array in chunks of kLeafChunk positions: a chunk's workgroup sorts the
+// maximal small subtrees whose spans start in it, which end within kLeafCap
+// positions of the chunk start.
+constexpr int kSmallSpan = 1024;
+constexpr int kLeafChunk = 1024;
+constexpr int kLeafCap = kLeafChunk + kSmallSpan;
+// Work::sflag, per boundary: kSmallNode on the leader (first boundary) of a
+// node of span <= kSmallSpan, plus kSmallRoot if its parent is larger or it
+// has none; 0 on every other boundary.
+constexpr uint8_t kSmallNode = 0x80;
+constexpr uint8_t kSmallRoot = 0x40;
+// Per chunk, kChunkRec words: the number of small roots whose spans start in
+// the chunk, then the first kChunkRec - 1 of them to be recorded (start -
+// chunk start | end - chunk start << 11 | depth parity << 23).  With more
+// roots the pass finds them from the boundaries instead.
+constexpr int kChunkRec = 8;
+static_assert(kLeafChunk <= 2048 && kLeafCap <= 4096, "root records pack 11 + 12 bits");
+// leaf_depth bit 7: the run's parent node is small (the small-subtree pass reads it)
+constexpr uint8_t kLeafInSmall = 0x80;
 
 // Minimal run length (runs extended to at least min_run elements): the chain
 // of run starts is resolved in chunks of kMrChunk positions, composed over
@@ -109,7 +135,10 @@ struct Work {
   uint32_t *nd_mem;                  // [(rmax+1)*(k-1)]
   uint32_t *jump0, *jump1;           // [rmax+1]
   uint8_t *dist0, *dist1;            // [rmax+1]
-  uint8_t *leaf_depth;               // [rmax]
+  uint8_t *leaf_depth;               // [rmax] depth of every run; bit 7: kLeafInSmall
+  uint8_t *sflag;                    // [rmax+1] small-node flags per boundary
+  uint32_t *cfirst;                  // [N/kLeafChunk + 2] run holding each chunk's first position
+  uint32_t *croot;                   // [(N/kLeafChunk + 2) * kChunkRec] small roots starting in each chunk
   uint32_t *lvl_cnt;                 // [nbb * kMaxLevels]
   uint32_t *lvl_list;                // [rmax]
   uint64_t *lvl_np;                  // [rmax+1] exclusive prefix of node sizes
@@ -207,6 +236,10 @@ hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s)
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
                        uint32_t *tj, unsigned grid_blocks, hipStream_t s);
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
+// The small-subtree pass: every maximal subtree of span <= kSmallSpan is merged
+// in LDS, from the runs in keys / vals (buffer 0) to the buffer of its root's
+// depth parity.
+hipError_t launch_leaf(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 // Replaces the natural runs (w.nat_start / w.nat_desc, plan->r) by the runs
 // extended to w.min_run (w.run_start / w.run_desc, plan->r) and sorts the
 // extended runs of keys / vals in place.

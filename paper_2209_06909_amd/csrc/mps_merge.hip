@@ -20,6 +20,13 @@ constexpr int kPlaceThreads = 256;
 constexpr int kPlaceE = 8;                                   // positions per thread
 constexpr uint64_t kPlaceBlock = (uint64_t)kPlaceThreads * kPlaceE;
 
+// Placement flags of a run: bit 0 odd depth, bit 1 strictly descending.  A run
+// whose parent is a small node is left to the small-subtree pass (flags 0).
+__device__ inline uint8_t place_flags(uint8_t leaf_depth, uint8_t desc) {
+  if (leaf_depth & kLeafInSmall) return 0;
+  return (uint8_t)((leaf_depth & 1) | (desc ? 2 : 0));
+}
+
 __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, uint64_t e) {
   // last j in [lo, hi] with rs[j] <= e
   while (hi > lo) {
@@ -150,7 +157,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
     {
       const uint64_t i = jc + (uint64_t)t;
       sRs[t] = i <= r ? rs[i] : ~0ull;   // rs[r] = N
-      sFl[t] = i < r ? (uint8_t)((leaf_depth[i] & 1) | (desc[i] ? 2 : 0)) : (uint8_t)0;
+      sFl[t] = i < r ? place_flags(leaf_depth[i], desc[i]) : (uint8_t)0;
       if (t == 0) sRs[T] = jc + T <= r ? rs[jc + T] : ~0ull;
     }
     // runs overlapping [bs, be): jc .. jc+nr-1 (sRs[0] <= bs, so nr >= 1)
@@ -163,9 +170,9 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
         const uint64_t i = jc + (uint64_t)x;
         sRs[x] = i <= r ? rs[i] : ~0ull;
         if (x < (int)kPlaceBlock)
-          sFl[x] = i < r ? (uint8_t)((leaf_depth[i] & 1) | (desc[i] ? 2 : 0)) : (uint8_t)0;
+          sFl[x] = i < r ? place_flags(leaf_depth[i], desc[i]) : (uint8_t)0;
       }
-      if (t == 0) sFl[T] = jc + T < r ? (uint8_t)((leaf_depth[jc + T] & 1) | (desc[jc + T] ? 2 : 0)) : (uint8_t)0;
+      if (t == 0) sFl[T] = jc + T < r ? place_flags(leaf_depth[jc + T], desc[jc + T]) : (uint8_t)0;
       __syncthreads();
       int lo = T, hi = (int)kPlaceBlock;   // first staged start >= be (sRs[kPlaceBlock] >= be)
       while (lo < hi) {

@@ -273,42 +273,64 @@ __device__ inline uint32_t group_leader(const uint8_t *P, const uint32_t *Le, ui
   return j;
 }
 
+// Node records, one boundary at a time: the leader (first boundary) of a
+// group gets its parent's leader and distance 1, or itself and 0 for a root.
+// Small nodes (span <= kSmallSpan elements) are flagged at their leader
+// (sflag: kSmallNode, plus kSmallRoot when the parent is not small or there
+// is none); every other boundary gets sflag 0.
 __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
                                                const uint32_t *__restrict__ Ls,
                                                const uint32_t *__restrict__ Rs,
                                                const uint32_t *__restrict__ Le,
-                                               const uint32_t *__restrict__ Re, Plan *plan, int k,
+                                               const uint32_t *__restrict__ Re,
+                                               const uint64_t *__restrict__ rs, Plan *plan, int k,
                                                uint32_t *__restrict__ mem,
                                                uint8_t *__restrict__ arity,
                                                uint32_t *__restrict__ jump,
-                                               uint8_t *__restrict__ dist) {
+                                               uint8_t *__restrict__ dist,
+                                               uint8_t *__restrict__ sflag) {
   const uint64_t r = plan->r;
+  uint32_t n_small = 0;
   for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
        ii += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t i = (uint32_t)ii;
     uint32_t p = P[i];
-    if (p == 0) continue;
-    uint32_t slot;
-    uint32_t lead = group_leader(P, Le, i, &slot);
-    if ((int)slot > k - 2) {
-      atomicOr(&plan->error, 1u);
-      continue;
-    }
-    mem[(uint64_t)lead * (k - 1) + slot] = i;
-    if (P[Re[i]] < p) arity[lead] = (uint8_t)(slot + 2);
-    if (slot == 0) {
-      uint32_t l = Ls[i], rr = Rs[i];
-      uint32_t pb = P[l] >= P[rr] ? l : rr;
-      if (P[pb] == 0) {
-        jump[i] = i;
-        dist[i] = 0;
+    uint8_t f = 0;
+    if (p > 0) {
+      uint32_t slot;
+      uint32_t lead = group_leader(P, Le, i, &slot);
+      if ((int)slot > k - 2) {
+        atomicOr(&plan->error, 1u);
       } else {
-        uint32_t s2;
-        jump[i] = group_leader(P, Le, pb, &s2);
-        dist[i] = 1;
+        mem[(uint64_t)lead * (k - 1) + slot] = i;
+        if (P[Re[i]] < p) arity[lead] = (uint8_t)(slot + 2);
+        if (slot == 0) {
+          uint32_t l = Ls[i], rr = Rs[i];
+          uint32_t pb = P[l] >= P[rr] ? l : rr;
+          const bool small = rs[rr] - rs[l] <= (uint64_t)kSmallSpan;
+          bool parent_small = false;
+          if (P[pb] == 0) {
+            jump[i] = i;
+            dist[i] = 0;
+          } else {
+            uint32_t s2;
+            const uint32_t pl = group_leader(P, Le, pb, &s2);
+            jump[i] = pl;
+            dist[i] = 1;
+            if (small) parent_small = rs[Rs[pl]] - rs[Ls[pl]] <= (uint64_t)kSmallSpan;
+          }
+          if (small) {
+            f = (uint8_t)(kSmallNode | (parent_small ? 0 : kSmallRoot));
+            n_small++;
+          }
+        }
       }
     }
+    sflag[i] = f;
   }
+  for (int o = 32; o > 0; o >>= 1) n_small += __shfl_down(n_small, o);
+  if ((threadIdx.x & 63) == 0 && n_small)
+    atomicAdd((unsigned long long *)&plan->n_small, (unsigned long long)n_small);
 }
 
 __device__ inline bool is_leader(const uint8_t *P, const uint32_t *Le, uint32_t i) {
@@ -350,26 +372,39 @@ __global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ P,
 
 // Leaf depth: run j sits between boundaries j and j+1 and hangs below the
 // node owning the larger of their powers (the leaf-depth identity in the
-// proof of Theorem 3.3); both 0 means the run is a whole segment.
+// proof of Theorem 3.3); both 0 means the run is a whole segment.  Bit 7
+// (kLeafInSmall) marks a run whose parent is a small node: the small-subtree
+// pass, not placement, reads it.
 __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
                                                 const uint32_t *__restrict__ Le,
                                                 const uint8_t *__restrict__ dist,
                                                 const uint64_t *__restrict__ rs, Plan *plan,
-                                                int want_cost, uint8_t *__restrict__ leaf_depth) {
+                                                int want_cost, const uint8_t *__restrict__ sflag,
+                                                uint8_t *__restrict__ leaf_depth) {
   const uint64_t r = plan->r;
   uint64_t cost = 0;
+  uint32_t dend = 0;
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < r;
        j += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t pa = P[j], pb = P[j + 1];
     uint32_t b = pa >= pb ? (uint32_t)j : (uint32_t)(j + 1);
-    uint8_t d = 0;
+    uint8_t d = 0, in_small = 0;
     if (P[b] > 0) {
       uint32_t s;
-      d = (uint8_t)(dist[group_leader(P, Le, b, &s)] + 1);
+      const uint32_t lead = group_leader(P, Le, b, &s);
+      d = (uint8_t)(dist[lead] + 1);
+      in_small = (sflag[lead] & kSmallNode) ? kLeafInSmall : 0;
     }
-    leaf_depth[j] = d;
+    leaf_depth[j] = d | in_small;
+    if (in_small && d > dend) dend = d;
     if (want_cost) cost += (uint64_t)d * (rs[j + 1] - rs[j]);
   }
+  // the deepest small node sits just above the deepest leaf of a small subtree
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t y = __shfl_down(dend, o);
+    dend = y > dend ? y : dend;
+  }
+  if ((threadIdx.x & 63) == 0 && dend) atomicMax(&plan->small_depth_end, dend);
   if (want_cost) {
     for (int o = 32; o > 0; o >>= 1) cost += __shfl_down(cost, o);
     if ((threadIdx.x & 63) == 0 && cost) atomicAdd((unsigned long long *)&plan->merge_cost, (unsigned long long)cost);
@@ -381,6 +416,7 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
 __global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__restrict__ P,
                                                             const uint32_t *__restrict__ Le,
                                                             const uint8_t *__restrict__ dist,
+                                                            const uint8_t *__restrict__ sflag,
                                                             const Plan *__restrict__ plan,
                                                             uint32_t *__restrict__ cnt) {
   __shared__ uint32_t sc[kMaxLevels];
@@ -391,7 +427,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__res
     if (t < kMaxLevels) sc[t] = 0;
     __syncthreads();
     uint64_t i = b * kTreeThreads + t;
-    if (i > 0 && i < r && is_leader(P, Le, (uint32_t)i)) atomicAdd(&sc[dist[i]], 1u);
+    if (i > 0 && i < r && is_leader(P, Le, (uint32_t)i) && !(sflag[i] & kSmallNode))
+      atomicAdd(&sc[dist[i]], 1u);
     __syncthreads();
     if (t < kMaxLevels) cnt[b * kMaxLevels + t] = sc[t];
     __syncthreads();
@@ -438,14 +475,17 @@ __global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals) {
     if (totals[d]) nl = d + 1;
   }
   plan->lvl_begin[kMaxLevels] = acc;
-  plan->n_nodes = acc;
-  plan->n_levels = nl;
+  // the level lists hold the nodes above the small subtrees; the small ones
+  // count towards the tree's size and depth all the same
+  plan->n_nodes = acc + plan->n_small;
+  plan->n_levels = nl > plan->small_depth_end ? nl : plan->small_depth_end;
 }
 
 __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
     const uint8_t *__restrict__ P, const uint32_t *__restrict__ Le,
-    const uint8_t *__restrict__ dist, const Plan *__restrict__ plan,
-    const uint32_t *__restrict__ cnt, uint32_t *__restrict__ list) {
+    const uint8_t *__restrict__ dist, const uint8_t *__restrict__ sflag,
+    const Plan *__restrict__ plan, const uint32_t *__restrict__ cnt,
+    uint32_t *__restrict__ list) {
   __shared__ uint32_t sw[kTreeWaves][kMaxLevels];
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
@@ -453,7 +493,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
     uint64_t i = b * kTreeThreads + t;
-    bool lead = i > 0 && i < r && is_leader(P, Le, (uint32_t)i);
+    bool lead = i > 0 && i < r && is_leader(P, Le, (uint32_t)i) && !(sflag[i] & kSmallNode);
     int myd = lead ? dist[i] : -1;
     uint32_t rank = 0;
     for (int d = 0; d < nl; d++) {
@@ -486,7 +526,7 @@ __global__ __launch_bounds__(256) void k_node_sizes(const uint32_t *__restrict__
                                                     const uint64_t *__restrict__ rs,
                                                     const Plan *__restrict__ plan,
                                                     uint64_t *__restrict__ np) {
-  const uint64_t nn = plan->n_nodes;
+  const uint64_t nn = plan->lvl_begin[kMaxLevels];   // nodes in the level lists
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nn;
        j += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t v = list[j];
@@ -495,7 +535,7 @@ __global__ __launch_bounds__(256) void k_node_sizes(const uint32_t *__restrict__
 }
 
 // ---------------------------------------------------------------- u64 exclusive scan
-// In place over a[0..n) with n = plan->n_nodes; a[n] receives the total.
+// In place over a[0..n) with n = the level lists' length; a[n] receives the total.
 constexpr int kScanBlk = 1024;
 
 __device__ inline uint64_t blk_incl_sum(uint64_t v, uint64_t *s) {
@@ -517,7 +557,7 @@ __global__ __launch_bounds__(kScanBlk) void k_scan_sums(const uint64_t *__restri
                                                         const Plan *__restrict__ plan,
                                                         uint64_t *__restrict__ bsum) {
   __shared__ uint64_t s[kScanBlk];
-  const uint64_t n = plan->n_nodes;
+  const uint64_t n = plan->lvl_begin[kMaxLevels];   // nodes in the level lists
   const uint64_t nb = (n + kScanBlk - 1) / kScanBlk;
   for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     uint64_t i = b * kScanBlk + threadIdx.x;
@@ -530,7 +570,7 @@ __global__ __launch_bounds__(kScanBlk) void k_scan_top(uint64_t *__restrict__ bs
                                                        const Plan *__restrict__ plan) {
   __shared__ uint64_t s[kScanBlk];
   __shared__ uint64_t carry;
-  const uint64_t n = plan->n_nodes;
+  const uint64_t n = plan->lvl_begin[kMaxLevels];   // nodes in the level lists
   const uint64_t nb = (n + kScanBlk - 1) / kScanBlk;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
@@ -550,7 +590,7 @@ __global__ __launch_bounds__(kScanBlk) void k_scan_apply(uint64_t *__restrict__ 
                                                          const Plan *__restrict__ plan,
                                                          const uint64_t *__restrict__ bsum) {
   __shared__ uint64_t s[kScanBlk];
-  const uint64_t n = plan->n_nodes;
+  const uint64_t n = plan->lvl_begin[kMaxLevels];   // nodes in the level lists
   const uint64_t nb = (n + kScanBlk - 1) / kScanBlk;
   for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     uint64_t i = b * kScanBlk + threadIdx.x;
@@ -623,17 +663,17 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
   hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
   hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);
-  hipLaunchKernelGGL(k_nodes, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0);
+  hipLaunchKernelGGL(k_nodes, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
   for (int round = 0; round < 6; round++) {  // depths < 64
     bool even = (round & 1) == 0;
     hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.power, w.Le, w.plan, round, even ? w.jump0 : w.jump1,
                        even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0, even ? w.dist1 : w.dist0);
   }
-  hipLaunchKernelGGL(k_leaves, g256, b256, 0, s, w.power, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.leaf_depth);
-  hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.plan, w.lvl_cnt);
+  hipLaunchKernelGGL(k_leaves, g256, b256, 0, s, w.power, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
+  hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.sflag, w.plan, w.lvl_cnt);
   hipLaunchKernelGGL(k_lvl_scan, dim3(kMaxLevels), dim3(kTreeThreads), 0, s, w.lvl_cnt, w.plan, lvl_tot);
   hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot);
-  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.plan, w.lvl_cnt, w.lvl_list);
+  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_list);
   hipLaunchKernelGGL(k_node_sizes, g256, b256, 0, s, w.lvl_list, w.Ls, w.Rs, w.run_start, w.plan, w.lvl_np);
   hipLaunchKernelGGL(k_scan_sums, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
