@@ -64,27 +64,99 @@ def committed_traffic(tag: str):
             "ratio_to_algorithmic": float(kv["ratio_to_algorithmic"])}
 
 
-def cpu_baseline(keys: np.ndarray, pay: np.ndarray, sample_n: int, k: int):
+def _timed(fn):
+    t0 = time.perf_counter()
+    out = fn()
+    return out, time.perf_counter() - t0
+
+
+def cpu_baseline(keys: np.ndarray, pay: np.ndarray, sample_n: int, k: int, full: bool = False):
+    """The oracle (single-threaded C multiway Powersort) on the host cores, beside a
+    library stable sort (C++ std::stable_sort of (key, payload) records, one thread),
+    on a bounded sample of the headline input; with full=True also every config at
+    its own size (see cpu_full_configs)."""
     import oracle
     sk, sp = keys[:sample_n].copy(), pay[:sample_n].copy()
-    t0 = time.perf_counter()
-    ok_, op_, _ = oracle.sort(sk, sp, k=k)
-    dt = time.perf_counter() - t0
-    # a library reference on the same sample: numpy's stable sort (a run-adaptive
-    # mergesort for 64-bit keys), one thread, keys and payload permuted together
-    rk, rp = keys[:sample_n].copy(), pay[:sample_n].copy()
-    t0 = time.perf_counter()
-    order = np.argsort(rk, kind="stable")
-    rk, rp = rk[order], rp[order]
-    dr = time.perf_counter() - t0
+    (ok_, op_, _), dt = _timed(lambda: oracle.sort(sk, sp, k=k))
+    (rk, rp), dr = _timed(lambda: oracle.stable_sort_ref(sk, sp))
     if not (np.array_equal(rk, ok_) and np.array_equal(rp, op_)):
-        raise RuntimeError("library stable sort and oracle disagree on the CPU sample")
-    return {"value": round(sample_n / dt / 1e9, 6), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_n} keys (2^{int(np.log2(sample_n))}) of the same runs_i64 input, "
-                      f"single-threaded C oracle, {dt:.2f} s",
-            "host_cpu": host_cpu(),
-            "library_reference": {"what": "numpy.argsort(kind='stable') + gather, one thread",
-                                  "value": round(sample_n / dr / 1e9, 6), "seconds": round(dr, 2)}}
+        raise RuntimeError("std::stable_sort and the oracle disagree on the CPU sample")
+
+    def npref():
+        order = np.argsort(sk, kind="stable")
+        return sk[order], sp[order]
+    _, dn = _timed(npref)
+    out = {"value": round(sample_n / dt / 1e9, 6), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {sample_n} keys (2^{int(np.log2(sample_n))}) of the same runs_i64 input, "
+                     f"single-threaded C oracle, {dt:.2f} s",
+           "host_cpu": host_cpu(), "nproc": os.cpu_count(),
+           "cores_available": len(os.sched_getaffinity(0)),
+           "library_reference": {"what": "C++ std::stable_sort of (int64 key, u32 payload) records, "
+                                         "one thread, g++ -O2",
+                                 "value": round(sample_n / dr / 1e9, 6), "seconds": round(dr, 2)},
+           "numpy_reference": {"what": "numpy.argsort(kind='stable') + gather, one thread",
+                               "value": round(sample_n / dn / 1e9, 6), "seconds": round(dn, 2)}}
+    if full:
+        out["per_config"] = cpu_full_configs(k)
+    return out
+
+
+def cpu_full_configs(k: int):
+    """The oracle and std::stable_sort, one thread each, on every config at its full
+    size (configs 1, 2a, 2b, 3); config 4 on a size-stratified sample of its arrays
+    (the rate extrapolated to all of them); config 5 per request over a size-stratified
+    sample of the request pool (the distribution of the oracle's per-request time)."""
+    import math
+    import oracle
+    import workloads
+    res = []
+    for cfg, name, n in (("1", "runs_i32", 1 << 20), ("2a", "runs_i64", 1 << 28),
+                         ("2b", "perm_i64", 1 << 28), ("3", "ties_i32", 1 << 27)):
+        log(f"cpu baseline: config {cfg} ({name}, n={n}) at full size")
+        kh, ph = workloads.WORKLOADS[name](n=n)
+        (ok_, op_, _), dt = _timed(lambda: oracle.sort(kh, ph, k=k))
+        (rk, rp), dr = _timed(lambda: oracle.stable_sort_ref(kh, ph))
+        same = bool(np.array_equal(rk, ok_) and np.array_equal(rp, op_))
+        res.append({"config": cfg, "workload": name, "n": n,
+                    "oracle_s": round(dt, 2), "oracle_gkeys_s": round(n / dt / 1e9, 5),
+                    "std_stable_sort_s": round(dr, 2), "std_stable_sort_gkeys_s": round(n / dr / 1e9, 5),
+                    "outputs_equal": same})
+        del kh, ph, ok_, op_, rk, rp
+    # config 4: m = 8192 int32 arrays, sizes floor(2^U), U ~ U[8, 22] (seed 5); every
+    # 128th array in size order, each generated with the recipe of the batched workload
+    sizes = workloads.serve_sizes(8192, seed=5, lo_exp=8.0, hi_exp=22.0)
+    pick = np.sort(sizes)[64::128]
+    rng = np.random.default_rng(55)
+    t_or = t_ref = 0.0
+    for sz in pick.tolist():
+        mr = max(1, int(2 * math.isqrt(sz)))
+        kh, ph, _ = workloads.batch_i32(m=1, seed=int(rng.integers(1 << 30)), lo_exp=math.log2(sz),
+                                        hi_exp=math.log2(sz) + 1e-12)
+        t_or += _timed(lambda: oracle.sort(kh, ph, k=k))[1]
+        t_ref += _timed(lambda: oracle.stable_sort_ref(kh, ph))[1]
+    keys_s = float(pick.sum())
+    res.append({"config": "4", "workload": "batch_i32 (m=8192)",
+                "sample": f"{pick.size} arrays, every 128th by size (sizes {int(pick.min())}.."
+                          f"{int(pick.max())})",
+                "oracle_gkeys_s": round(keys_s / t_or / 1e9, 5),
+                "std_stable_sort_gkeys_s": round(keys_s / t_ref / 1e9, 5),
+                "oracle_s_all_8192_extrapolated": round(float(sizes.sum()) / (keys_s / t_or), 1)})
+    # config 5: the request pool (512 sizes floor(2^U), U ~ U[10, 26], seed 6); every 8th
+    # request in size order, float32 keys generated by the serving recipe
+    psz = workloads.serve_sizes(512, seed=6)
+    pick = np.sort(psz)[4::8]
+    rng = np.random.default_rng(66)
+    per = []
+    for sz in pick.tolist():
+        x, p = workloads.serve_request_f32(int(sz), rng)
+        per.append(_timed(lambda: oracle.sort(x, p, k=k))[1] * 1e3)
+    per = np.array(per)
+    res.append({"config": "5", "workload": "serve pool (512 float32 requests)",
+                "sample": f"{pick.size} requests, every 8th by size",
+                "oracle_ms_per_request_p50_p99": [round(float(np.percentile(per, q)), 3) for q in (50, 99)],
+                "oracle_ms_per_request_mean": round(float(per.mean()), 3),
+                "oracle_gkeys_s": round(float(pick.sum()) / (per.sum() * 1e-3) / 1e9, 5)})
+    return res
 
 
 def host_cpu() -> str:
@@ -371,6 +443,9 @@ def main():
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-sample-log2n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle and std::stable_sort on every config at full size "
+                         "(several minutes of CPU work)")
     ap.add_argument("--no-k-sweep", action="store_true")
     ap.add_argument("--no-perm", action="store_true", help="skip the random-permutation variant")
     ap.add_argument("--no-records", action="store_true",
@@ -476,19 +551,20 @@ def main():
         roof["traffic"] = round(tr_d["bytes_per_merged_element"] * per_launch)
         roof["traffic_per_merged_element"] = tr_d["bytes_per_merged_element"]
         roof["traffic_ratio_to_algorithmic"] = tr_d["ratio_to_algorithmic"]
-    # measured copy ceiling: a device-to-device copy of the same key and payload
-    # arrays (every byte read once and written once), as context for the roofline
+    # measured copy ceiling: the library's streaming copy kernel (mps_stream_copy) over
+    # the same key and payload arrays, every byte read once and written once
     cp_ms = []
-    for _ in range(3):
+    for _ in range(5):
         c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         c0.record()
-        keys.copy_(keys0)
-        pay.copy_(pay0)
+        mps.stream_copy(keys, keys0)
+        mps.stream_copy(pay, pay0)
         c1.record()
         c1.synchronize()
         cp_ms.append(c0.elapsed_time(c1))
-    copy_gbs = 2 * n * KV / (min(cp_ms) * 1e-3) / 1e9
+    copy_gbs = 2 * n * KV / (min(cp_ms[1:]) * 1e-3) / 1e9
     roof["copy_ceiling_GBs"] = round(copy_gbs, 1)
+    roof["copy_ceiling_kernel"] = "mps_stream_copy (16-byte loads/stores, 1024 x 256 threads)"
     roof["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 4)
     levels_all = merge_bytes / ((merge_ms + corank_ms) * 1e-3) / 1e9
     sort_bytes = n * 8 + 2 * KV * placed + 2 * KV * tr.merge_cost
@@ -563,7 +639,8 @@ def main():
         out["perm_variant"] = bench_perm(args, torch, mps, workloads, tcfg)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(keys_h, pay_h, 1 << args.cpu_sample_log2n, args.k)
+        out["cpu_baseline"] = cpu_baseline(keys_h, pay_h, 1 << args.cpu_sample_log2n, args.k,
+                                           full=args.cpu_full)
     del keys_h, pay_h, keys0, pay0, keys, pay
     mps.release_workspaces()
     torch.cuda.empty_cache()

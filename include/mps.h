@@ -253,14 +253,26 @@ int mps_free_workspaces(void);
 int mps_trace_fetch(const void *workspace, mps_trace *trace);
 
 /* Per-level figures of the most recent sort on the current device that was
- * run with MPS_OPT_TIME_LEVELS: the number of merge levels, and for each
- * level d < min(cap, n_levels) the number of elements its merges output
+ * run with MPS_OPT_TIME_LEVELS: the number of levels run by the level merges
+ * (1 + the deepest depth of a node whose span exceeds 1024 elements; the
+ * smaller subtrees are finished by one pass before the levels and are not
+ * counted), and for each level d < min(cap, n_levels) the number of elements
+ * the level merges output
  * (the level's share of the merge cost, Section 2.3) and the durations of
  * its co-rank and merge launches in milliseconds (HIP events on the sort's
  * stream).  Any output pointer may be NULL.  Waits for that sort to finish.
  * MPS_E_NOTFOUND if there was no such sort. */
 int mps_last_level_stats(uint32_t cap, uint32_t *n_levels, uint64_t *level_elems,
                          float *corank_ms, float *merge_ms);
+
+/* A streaming device-to-device copy of `bytes` bytes from src to dst (device
+ * pointers, both 16-byte aligned, not overlapping), enqueued on `stream`:
+ * 16-byte loads and stores, every byte read once and written once.  Not part
+ * of the sort; it is the measuring stick for the HBM bandwidth that a one-pass
+ * kernel reaches on the device (the benchmark's copy ceiling, and the copy of
+ * known size that calibrates the traffic counters).  MPS_E_INVALID for a NULL
+ * or misaligned pointer. */
+int mps_stream_copy(const void *src, void *dst, uint64_t bytes, void *stream);
 
 /* ------------------------------------------------------------ serving
  * A continuous-batching server (a systems layer around the sort; the paper has

@@ -27,6 +27,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
+_REF_PATH = os.path.join(_HERE, "libstableref.so")
+_REF_SRC = os.path.join(_HERE, "stable_ref.cpp")
 
 KEY_TYPES = {np.dtype(np.int32): 0, np.dtype(np.int64): 1, np.dtype(np.float32): 2}
 
@@ -39,13 +41,45 @@ NODE_DTYPE = np.dtype({
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain -O2, no tuning)."""
+    """Compile liboracle.so with gcc (plain -O2, no tuning), and beside it the
+    std::stable_sort reference (libstableref.so, g++ -O2)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
                                "-o", tmp, _SRC], cwd=_HERE)
         os.replace(tmp, _LIB_PATH)
+    if force or not os.path.exists(_REF_PATH):
+        tmp = _REF_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared",
+                               "-o", tmp, _REF_SRC], cwd=_HERE)
+        os.replace(tmp, _REF_PATH)
     return _LIB_PATH
+
+
+_ref = None
+
+
+def stable_sort_ref(keys: np.ndarray, payload: np.ndarray | None = None):
+    """std::stable_sort of (key, payload) records on one thread (the library
+    reference); returns (keys, payload) sorted.  Float32 keys follow the
+    IEEE-754 total order, like the oracle."""
+    global _ref
+    if _ref is None:
+        build()
+        _ref = ctypes.CDLL(_REF_PATH)
+        _ref.ref_stable_sort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        _ref.ref_stable_sort.restype = ctypes.c_int
+    keys = np.ascontiguousarray(keys)
+    kt = KEY_TYPES[keys.dtype]
+    ko = np.empty_like(keys)
+    po = np.empty(keys.size, np.uint32)
+    pin = None if payload is None else np.ascontiguousarray(payload, dtype=np.uint32)
+    rc = _ref.ref_stable_sort(keys.ctypes.data, None if pin is None else pin.ctypes.data,
+                              keys.size, kt, ko.ctypes.data, po.ctypes.data)
+    if rc != 0:
+        raise ValueError("unsupported key type")
+    return ko, po
 
 
 class _Node(ctypes.Structure):

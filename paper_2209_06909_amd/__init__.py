@@ -32,7 +32,7 @@ EXPORTED = ["mps_workspace_bytes", "mps_sort", "mps_sort_i32", "mps_sort_i64", "
             "mps_sort_ex", "mps_sort_noalloc", "mps_noalloc_scratch_bytes", "mps_sort_kv64",
             "mps_sort_batched", "mps_autotune", "mps_sort_status",
             "mps_free_workspaces", "mps_trace_fetch",
-            "mps_last_level_stats", "mps_serve_create", "mps_serve_submit", "mps_serve_poll",
+            "mps_last_level_stats", "mps_stream_copy", "mps_serve_create", "mps_serve_submit", "mps_serve_poll",
             "mps_serve_release", "mps_serve_stats", "mps_serve_destroy", "mps_serve_selftest",
             "mps_last_error"]
 
@@ -153,6 +153,8 @@ def lib() -> ctypes.CDLL:
             l.mps_trace_fetch.restype = i32
             l.mps_last_level_stats.argtypes = [u32, P, P, P, P]
             l.mps_last_level_stats.restype = i32
+            l.mps_stream_copy.argtypes = [P, P, u64, P]
+            l.mps_stream_copy.restype = i32
             l.mps_serve_create.argtypes = [ctypes.POINTER(_ServeCfg), ctypes.POINTER(P)]
             l.mps_serve_create.restype = i32
             l.mps_serve_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(u64)]
@@ -326,6 +328,22 @@ def check_last(device=None, stream=None):
     status(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(st.cuda_stream))
 
 
+def last_trace(device=None, stream=None, arrays: bool = True) -> Trace:
+    """mps_trace_fetch: the trace of the last sort() / sort_batched() on `stream`
+    (default: the current stream of `device`), also when it ran without trace=True;
+    synchronises the device."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = _stream_of(dev, stream)
+    with _ws_lock:
+        buf = _ws.get((dev.type, dev.index, st.cuda_stream))
+    if buf is None:
+        raise MpsError(-5, "no sort has run on this stream")
+    t = _Trace()
+    _check(lib().mps_trace_fetch(ctypes.c_void_p(buf.data_ptr()), ctypes.byref(t)))
+    return _fetch_trace(ctypes.c_void_p(buf.data_ptr()), t, arrays)
+
+
 def sort(keys, payload=None, *, k: int = 4, trace: bool = False, trace_arrays: bool = True,
          stream=None, time_levels: bool = False, graph: bool = False, tile: int | None = None,
          lane_slice: int | None = None, min_run: int = 1, merge_down: bool = False,
@@ -487,6 +505,17 @@ def autotune(keys, payload, host_offsets, *, sample_keys: int = 1 << 27, graph: 
         out["candidates"] = [dict(k=k, tile=t, lane_slice=e, ms=float(x))
                              for (k, t, e), x in zip(TUNE_CANDIDATES, times)]
     return out
+
+
+def stream_copy(dst, src, stream=None):
+    """mps_stream_copy: copy the bytes of tensor src into tensor dst (same size, both
+    16-byte aligned) with the library's streaming copy kernel, on `stream`."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise MpsError(-1, "size mismatch")
+    st = _stream_of(src.device, stream)
+    _check(lib().mps_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                 nbytes, ctypes.c_void_p(st.cuda_stream)))
 
 
 def level_stats(cap: int = 64):

@@ -19,7 +19,7 @@ LIB = os.path.join(LIBDIR, "libmps.so")
 SOURCES = ["mps_detect.hip", "mps_minrun.hip", "mps_tree.hip", "mps_merge.hip", "mps_merge_1024x256.hip",
            "mps_merge_2048x256.hip", "mps_merge_2048x512.hip", "mps_merge_4096x512.hip",
            "mps_merge_4096x1024.hip",
-           "mps_leaf.hip", "mps_api.hip", "mps_tune.hip", "mps_serve.hip"]
+           "mps_leaf.hip", "mps_api.hip", "mps_tune.hip", "mps_serve.hip", "mps_copy.hip"]
 ARCH = os.environ.get("MPS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

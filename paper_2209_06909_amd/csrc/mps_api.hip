@@ -183,7 +183,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.dist0 = take(c, rmax + 1);
   L.dist1 = take(c, rmax + 1);
   L.leaf_depth = take(c, rmax);
-  L.sflag = take(c, rmax + 1);
+  L.sflag = take(c, rmax + 17);   // read 16 flags at a time
   L.cfirst = take(c, (N / kLeafChunk + 2) * 4);
   L.croot = take(c, (N / kLeafChunk + 2) * kChunkRec * 4);
   L.lvl_cnt = take(c, nbb * kMaxLevels * 4);
@@ -301,6 +301,70 @@ template <typename T> T *at(void *base, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
+// Device views of the workspace at `base` (laid out by L).
+void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uint32_t k, int tile,
+               int threads, bool payload, const uint64_t *d_off) {
+  w.N = N;
+  w.m = m;
+  w.rmax = L.rmax;
+  w.k = (int)k;
+  w.logk = k == 2 ? 1 : (k == 4 ? 2 : 3);
+  w.tile = tile;
+  w.threads = threads;
+  w.alt_keys = at<void>(base, L.alt_keys);
+  w.alt_vals = payload ? at<uint32_t>(base, L.alt_vals) : nullptr;
+  w.seg_off_local = at<uint64_t>(base, L.seg_off);
+  w.off = d_off ? d_off : w.seg_off_local;
+  w.seg_bits = m > 1 ? at<uint64_t>(base, L.seg_bits) : nullptr;
+  w.dbits = at<uint64_t>(base, L.dbits);
+  w.det_agg = at<DetAgg>(base, L.det_agg);
+  w.det_zin = at<uint64_t>(base, L.det_zin);
+  w.det_off = at<uint64_t>(base, L.det_off);
+  w.run_start = at<uint64_t>(base, L.run_start);
+  w.run_desc = at<uint8_t>(base, L.run_desc);
+  if (m == 1) {
+    w.nat_start = at<uint64_t>(base, L.nat_start);
+    w.nat_desc = at<uint8_t>(base, L.nat_desc);
+    w.mr_first = at<uint32_t>(base, L.mr_first);
+    w.mr_nxt = at<uint8_t>(base, L.mr_nxt);
+    w.mr_cnt = at<uint16_t>(base, L.mr_cnt);
+    w.mr_gnxt = at<uint8_t>(base, L.mr_gnxt);
+    w.mr_gcnt = at<uint32_t>(base, L.mr_gcnt);
+    w.mr_gentry = at<uint8_t>(base, L.mr_gentry);
+    w.mr_goff = at<uint32_t>(base, L.mr_goff);
+    w.mr_centry = at<uint8_t>(base, L.mr_centry);
+    w.mr_coff = at<uint32_t>(base, L.mr_coff);
+  }
+  w.power = at<uint8_t>(base, L.power);
+  w.ansv_bl = at<uint32_t>(base, L.ansv_bl);
+  w.ansv_bf = at<uint32_t>(base, L.ansv_bf);
+  w.ansv_cl = at<uint32_t>(base, L.ansv_cl);
+  w.ansv_cr = at<uint32_t>(base, L.ansv_cr);
+  w.Ls = at<uint32_t>(base, L.Ls);
+  w.Rs = at<uint32_t>(base, L.Rs);
+  w.Le = at<uint32_t>(base, L.Le);
+  w.Re = at<uint32_t>(base, L.Re);
+  w.nd_arity = at<uint8_t>(base, L.nd_arity);
+  w.nd_mem = at<uint32_t>(base, L.nd_mem);
+  w.jump0 = at<uint32_t>(base, L.jump0);
+  w.jump1 = at<uint32_t>(base, L.jump1);
+  w.dist0 = at<uint8_t>(base, L.dist0);
+  w.dist1 = at<uint8_t>(base, L.dist1);
+  w.leaf_depth = at<uint8_t>(base, L.leaf_depth);
+  w.sflag = at<uint8_t>(base, L.sflag);
+  w.cfirst = at<uint32_t>(base, L.cfirst);
+  w.croot = at<uint32_t>(base, L.croot);
+  w.lvl_cnt = at<uint32_t>(base, L.lvl_cnt);
+  w.lvl_list = at<uint32_t>(base, L.lvl_list);
+  w.lvl_np = at<uint64_t>(base, L.lvl_np);
+  w.scan_tmp = at<uint64_t>(base, L.scan_tmp);
+  w.corank = at<uint32_t>(base, L.corank);
+  w.tile_desc = at<void>(base, L.tile_desc);
+  w.gen_list = at<uint32_t>(base, L.gen_list);
+  w.samples = at<uint64_t>(base, L.samples);
+  w.plan = at<Plan>(base, L.plan);
+}
+
 // Copies the trace of the sort that last used the workspace at `base`.
 int fill_trace(void *base, mps_trace *tr) {
   Plan plan;
@@ -308,6 +372,19 @@ int fill_trace(void *base, mps_trace *tr) {
   HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
   if (plan.error)
     return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", plan.error);
+  if (plan.lean && plan.n >= 2) {
+    // the sort left the insides of its small subtrees out: build them now
+    Layout L;
+    if (!make_layout(plan.n, plan.m, (int)plan.kt, plan.has_payload != 0, plan.k, L))
+      return fail(MPS_E_DEVICE, "workspace header does not describe a layout");
+    Work w{};
+    bind_work(w, base, L, plan.n, plan.m, plan.k, 0, 0, plan.has_payload != 0, nullptr);
+    HIP_TRY(launch_tree_complete(w, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
+    if (plan.error)
+      return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", plan.error);
+  }
   tr->r = plan.r;
   tr->n_nodes = plan.n_nodes;
   tr->merge_cost = plan.merge_cost;
@@ -521,67 +598,9 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   base = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(base) + 255) & ~(uintptr_t)255);
 
   Work w{};
-  w.N = N;
-  w.m = m;
-  w.rmax = L.rmax;
-  w.k = (int)k;
-  w.logk = k == 2 ? 1 : (k == 4 ? 2 : 3);
-  w.tile = tile;
-  w.threads = threads;
-  w.alt_keys = at<void>(base, L.alt_keys);
-  w.alt_vals = payload ? at<uint32_t>(base, L.alt_vals) : nullptr;
-  w.seg_off_local = at<uint64_t>(base, L.seg_off);
-  w.off = d_off ? d_off : w.seg_off_local;
-  w.seg_bits = m > 1 ? at<uint64_t>(base, L.seg_bits) : nullptr;
-  w.dbits = at<uint64_t>(base, L.dbits);
-  w.det_agg = at<DetAgg>(base, L.det_agg);
-  w.det_zin = at<uint64_t>(base, L.det_zin);
-  w.det_off = at<uint64_t>(base, L.det_off);
-  w.run_start = at<uint64_t>(base, L.run_start);
-  w.run_desc = at<uint8_t>(base, L.run_desc);
+  bind_work(w, base, L, N, m, k, tile, threads, payload != nullptr, d_off);
   w.min_run = (int)min_run;
   w.merge_down = (flags & MPS_OPT_MERGE_DOWN) ? 1 : 0;
-  if (m == 1) {
-    w.nat_start = at<uint64_t>(base, L.nat_start);
-    w.nat_desc = at<uint8_t>(base, L.nat_desc);
-    w.mr_first = at<uint32_t>(base, L.mr_first);
-    w.mr_nxt = at<uint8_t>(base, L.mr_nxt);
-    w.mr_cnt = at<uint16_t>(base, L.mr_cnt);
-    w.mr_gnxt = at<uint8_t>(base, L.mr_gnxt);
-    w.mr_gcnt = at<uint32_t>(base, L.mr_gcnt);
-    w.mr_gentry = at<uint8_t>(base, L.mr_gentry);
-    w.mr_goff = at<uint32_t>(base, L.mr_goff);
-    w.mr_centry = at<uint8_t>(base, L.mr_centry);
-    w.mr_coff = at<uint32_t>(base, L.mr_coff);
-  }
-  w.power = at<uint8_t>(base, L.power);
-  w.ansv_bl = at<uint32_t>(base, L.ansv_bl);
-  w.ansv_bf = at<uint32_t>(base, L.ansv_bf);
-  w.ansv_cl = at<uint32_t>(base, L.ansv_cl);
-  w.ansv_cr = at<uint32_t>(base, L.ansv_cr);
-  w.Ls = at<uint32_t>(base, L.Ls);
-  w.Rs = at<uint32_t>(base, L.Rs);
-  w.Le = at<uint32_t>(base, L.Le);
-  w.Re = at<uint32_t>(base, L.Re);
-  w.nd_arity = at<uint8_t>(base, L.nd_arity);
-  w.nd_mem = at<uint32_t>(base, L.nd_mem);
-  w.jump0 = at<uint32_t>(base, L.jump0);
-  w.jump1 = at<uint32_t>(base, L.jump1);
-  w.dist0 = at<uint8_t>(base, L.dist0);
-  w.dist1 = at<uint8_t>(base, L.dist1);
-  w.leaf_depth = at<uint8_t>(base, L.leaf_depth);
-  w.sflag = at<uint8_t>(base, L.sflag);
-  w.cfirst = at<uint32_t>(base, L.cfirst);
-  w.croot = at<uint32_t>(base, L.croot);
-  w.lvl_cnt = at<uint32_t>(base, L.lvl_cnt);
-  w.lvl_list = at<uint32_t>(base, L.lvl_list);
-  w.lvl_np = at<uint64_t>(base, L.lvl_np);
-  w.scan_tmp = at<uint64_t>(base, L.scan_tmp);
-  w.corank = at<uint32_t>(base, L.corank);
-  w.tile_desc = at<void>(base, L.tile_desc);
-  w.gen_list = at<uint32_t>(base, L.gen_list);
-  w.samples = at<uint64_t>(base, L.samples);
-  w.plan = at<Plan>(base, L.plan);
   uint64_t *lvl_tot = at<uint64_t>(base, L.lvl_tot);
   uint64_t *tile_base = at<uint64_t>(base, L.tile_base);
   uint32_t *tj = at<uint32_t>(base, L.tj);
@@ -884,7 +903,7 @@ extern "C" int mps_last_level_stats(uint32_t cap, uint32_t *n_levels, uint64_t *
   Plan plan;
   HIP_TRY(hipEventSynchronize(tm.ev[2]));  // level 0's merge is the last launch
   HIP_TRY(hipMemcpy(&plan, tm.base, sizeof(Plan), hipMemcpyDeviceToHost));
-  uint32_t nl = plan.n_levels;
+  uint32_t nl = plan.lvl_levels;   // the levels the level merges ran
   if (n_levels) *n_levels = nl;
   for (uint32_t d = 0; d < nl && d < cap && d < (uint32_t)tm.levels; d++) {
     if (level_elems) level_elems[d] = plan.lvl_total[d];

@@ -51,7 +51,7 @@ struct Plan {
   uint64_t n_nodes;                  // internal merge-tree nodes
   uint32_t n_levels;                 // 1 + deepest internal-node depth (0: nothing to merge)
   uint32_t error;                    // nonzero: a device-side check failed
-  uint64_t merge_cost;               // filled only when a trace is requested
+  uint64_t merge_cost;               // filled when a trace is requested or fetched
   uint64_t lvl_begin[kMaxLevels + 1];  // level-sorted node list offsets
   uint64_t lvl_total[kMaxLevels];    // sum of node sizes per level
   uint64_t lvl_tiles[kMaxLevels];    // merge tiles per level
@@ -61,8 +61,10 @@ struct Plan {
   uint32_t jump_more[8];             // pointer-jumping round i left a target that is not a root
   uint64_t r_nat;                    // natural runs, when a minimal run length replaced them
   uint64_t n_small;                  // nodes of span <= kSmallSpan (merged by the small-subtree pass)
-  uint32_t small_depth_end;          // 1 + deepest depth of such a node (0: none)
-  uint32_t pad2;
+  uint32_t small_depth_end;          // 1 + deepest depth of such a node (0: none, or not computed)
+  uint32_t lvl_levels;               // levels holding a node of the level lists (1 + deepest depth)
+  uint32_t lean;                     // 1: the tree was built without FULL (see launch_tree)
+  uint32_t pmax;                     // the largest node power
 };
 
 // Small subtrees: a node whose span is at most kSmallSpan elements is
@@ -76,9 +78,11 @@ constexpr int kLeafChunk = 1024;
 constexpr int kLeafCap = kLeafChunk + kSmallSpan;
 // Work::sflag, per boundary: kSmallNode on the leader (first boundary) of a
 // node of span <= kSmallSpan, plus kSmallRoot if its parent is larger or it
-// has none; 0 on every other boundary.
+// has none; kBigLeader on the leader of a larger node; 0 on every other
+// boundary.
 constexpr uint8_t kSmallNode = 0x80;
 constexpr uint8_t kSmallRoot = 0x40;
+constexpr uint8_t kBigLeader = 0x20;   // the leader of a node of span > kSmallSpan
 // Per chunk, kChunkRec words: the number of small roots whose spans start in
 // the chunk, then the first kChunkRec - 1 of them to be recorded (start -
 // chunk start | end - chunk start << 11 | depth parity << 23).  With more
@@ -233,12 +237,18 @@ inline bool tile_config_ok(int tile, int threads) {
 int fail_msg(int code, const char *msg);
 
 hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s);
+// Powers, nearest smaller values, nodes, depths, leaf depths and the level
+// lists.  With want_cost (a traced sort) the whole tree is built and the
+// merge cost summed; otherwise the records inside small subtrees are left
+// out (plan->lean), and launch_tree_complete adds them later if a trace of
+// the sort is fetched.
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
                        uint32_t *tj, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_tree_complete(const Work &w, hipStream_t s);
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
-// The small-subtree pass: every maximal subtree of span <= kSmallSpan is merged
-// in LDS, from the runs in keys / vals (buffer 0) to the buffer of its root's
-// depth parity.
+// The small-subtree pass: every maximal subtree of span <= kSmallSpan is
+// finished in LDS, from the runs in keys / vals (buffer 0) to the buffer of
+// its root's depth parity.
 hipError_t launch_leaf(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 // Replaces the natural runs (w.nat_start / w.nat_desc, plan->r) by the runs
 // extended to w.min_run (w.run_start / w.run_desc, plan->r) and sorts the

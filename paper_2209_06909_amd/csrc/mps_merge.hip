@@ -207,7 +207,11 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
         }
       }
     } else if (!(nr == 1 && fl0 == 0)) {
-      place_general<KT>(keys, vals, akeys, avals, smp, sRs, sFl, nr, bs, be, t);
+      // blocks whose runs all stay where they are (even depth, ascending, or
+      // inside a small subtree) have nothing to move
+      bool mine = false;
+      for (int x = t; x < nr; x += T) mine = mine || sFl[x] != 0;
+      if (__syncthreads_or(mine)) place_general<KT>(keys, vals, akeys, avals, smp, sRs, sFl, nr, bs, be, t);
     }
     jc = jn;
     __syncthreads();   // the run table is restaged for the next block

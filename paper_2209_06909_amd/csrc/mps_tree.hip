@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
                                                 Plan *__restrict__ plan, int logk,
                                                 uint8_t *__restrict__ P) {
   const uint64_t r = plan->r;
+  uint32_t pmax = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= r;
        i += (uint64_t)gridDim.x * blockDim.x) {
     uint8_t p = 0;
@@ -52,16 +53,23 @@ __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
       }
     }
     P[i] = p;
+    pmax = p > pmax ? p : pmax;
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t y = __shfl_down(pmax, o);
+    pmax = y > pmax ? y : pmax;
+  }
+  if ((threadIdx.x & 63) == 0 && pmax) atomicMax(&plan->pmax, pmax);
 }
 
 // ---------------------------------------------------------------- ANSV
 // Per block of 1024 boundaries: for every value v in [1, kVMax], the last
 // (stored +1; 0 = none) and first (kNone32 = none) boundary with power < v.
+// Only v <= vmax = 1 + the largest power present are ever asked for.
 __device__ inline void wave_masks(const uint8_t *__restrict__ P, uint64_t r, uint64_t i,
-                                  uint64_t *masks /* [kVMax] per wave, LDS */, int lane) {
+                                  uint64_t *masks /* [kVMax] per wave, LDS */, int lane, int vmax) {
   uint32_t p = i <= r ? P[i] : 255u;
-  for (int v = 1; v <= kVMax; v++) {
+  for (int v = 1; v <= vmax; v++) {
     uint64_t mk = ballot64(p < (uint32_t)v);
     if (lane == 0) masks[v - 1] = mk;
   }
@@ -75,11 +83,12 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_block(const uint8_t *__re
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int vmax = (int)plan->pmax + 1;
   for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
     uint64_t i = b * kTreeThreads + t;
-    wave_masks(P, r, i, sM[w], lane);
+    wave_masks(P, r, i, sM[w], lane, vmax);
     __syncthreads();
-    if (t < kVMax) {
+    if (t < vmax) {
       uint32_t last = 0, first = kNone32;
       for (int ww = 0; ww < kTreeWaves; ww++) {
         uint64_t mk = sM[ww][t];
@@ -107,6 +116,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_scan(const uint32_t *__re
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
   const int v = blockIdx.x, t = threadIdx.x;
+  if (v > (int)plan->pmax) return;   // value v + 1 is never asked for
   if (t == 0) carry = 0;
   __syncthreads();
   for (uint64_t base = 0; base < nbb; base += kTreeThreads) {
@@ -162,11 +172,12 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_final(
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int vmax = (int)plan->pmax + 1;
   for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
     uint64_t i = b * kTreeThreads + t;
-    wave_masks(P, r, i, sM[w], lane);
+    wave_masks(P, r, i, sM[w], lane, vmax);
     __syncthreads();
-    if (t < kVMax) {
+    if (t < vmax) {
       uint32_t last = 0;
       for (int ww = 0; ww < kTreeWaves; ww++) {
         sPL[ww][t] = last;
@@ -275,9 +286,16 @@ __device__ inline uint32_t group_leader(const uint8_t *P, const uint32_t *Le, ui
 
 // Node records, one boundary at a time: the leader (first boundary) of a
 // group gets its parent's leader and distance 1, or itself and 0 for a root.
-// Small nodes (span <= kSmallSpan elements) are flagged at their leader
-// (sflag: kSmallNode, plus kSmallRoot when the parent is not small or there
-// is none); every other boundary gets sflag 0.
+// A node's span is [rs[Ls], rs[Rs]) for every boundary of its group.  The
+// leader of a node of span <= kSmallSpan gets sflag kSmallNode, plus
+// kSmallRoot when its parent is larger or it has none; the leader of a larger
+// node gets kBigLeader; every other boundary gets 0.
+//
+// FULL builds every node.  Otherwise only what the sort itself reads is
+// built: the member lists, arities and parent links of the larger nodes, and
+// the parent links of the small roots (inside a small subtree only the root's
+// span and depth parity matter, the small-subtree pass sorts the rest).
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
                                                const uint32_t *__restrict__ Ls,
                                                const uint32_t *__restrict__ Rs,
@@ -293,36 +311,54 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
   uint32_t n_small = 0;
   for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
        ii += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t i = (uint32_t)ii;
-    uint32_t p = P[i];
+    const uint32_t i = (uint32_t)ii;
+    const uint32_t p = P[i];
     uint8_t f = 0;
     if (p > 0) {
-      uint32_t slot;
-      uint32_t lead = group_leader(P, Le, i, &slot);
-      if ((int)slot > k - 2) {
-        atomicOr(&plan->error, 1u);
-      } else {
-        mem[(uint64_t)lead * (k - 1) + slot] = i;
-        if (P[Re[i]] < p) arity[lead] = (uint8_t)(slot + 2);
-        if (slot == 0) {
-          uint32_t l = Ls[i], rr = Rs[i];
-          uint32_t pb = P[l] >= P[rr] ? l : rr;
-          const bool small = rs[rr] - rs[l] <= (uint64_t)kSmallSpan;
-          bool parent_small = false;
-          if (P[pb] == 0) {
-            jump[i] = i;
-            dist[i] = 0;
-          } else {
-            uint32_t s2;
-            const uint32_t pl = group_leader(P, Le, pb, &s2);
-            jump[i] = pl;
-            dist[i] = 1;
-            if (small) parent_small = rs[Rs[pl]] - rs[Ls[pl]] <= (uint64_t)kSmallSpan;
+      const uint32_t l = Ls[i], rr = Rs[i];
+      const bool small = rs[rr] - rs[l] <= (uint64_t)kSmallSpan;
+      const uint32_t pb = P[l] >= P[rr] ? l : rr;   // the parent's boundary
+      if (FULL || !small) {
+        uint32_t slot;
+        const uint32_t lead = group_leader(P, Le, i, &slot);
+        if ((int)slot > k - 2) {
+          atomicOr(&plan->error, 1u);
+        } else {
+          mem[(uint64_t)lead * (k - 1) + slot] = i;
+          if (P[Re[i]] < p) arity[lead] = (uint8_t)(slot + 2);
+          if (slot == 0) {
+            bool parent_small = false;
+            if (P[pb] == 0) {
+              jump[i] = i;
+              dist[i] = 0;
+            } else {
+              uint32_t s2;
+              const uint32_t pl = group_leader(P, Le, pb, &s2);
+              jump[i] = pl;
+              dist[i] = 1;
+              if (small) parent_small = rs[Rs[pl]] - rs[Ls[pl]] <= (uint64_t)kSmallSpan;
+            }
+            if (small) {
+              f = (uint8_t)(kSmallNode | (parent_small ? 0 : kSmallRoot));
+              n_small++;
+            } else {
+              f = kBigLeader;
+            }
           }
-          if (small) {
-            f = (uint8_t)(kSmallNode | (parent_small ? 0 : kSmallRoot));
-            n_small++;
-          }
+        }
+      } else if (P[Le[i]] < p) {   // the leader of a small node
+        n_small++;
+        if (P[pb] == 0) {
+          f = kSmallNode | kSmallRoot;
+          jump[i] = i;
+          dist[i] = 0;
+        } else if (rs[Rs[pb]] - rs[Ls[pb]] > (uint64_t)kSmallSpan) {
+          uint32_t s2;
+          f = kSmallNode | kSmallRoot;
+          jump[i] = group_leader(P, Le, pb, &s2);
+          dist[i] = 1;
+        } else {
+          f = kSmallNode;
         }
       }
     }
@@ -333,17 +369,13 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
     atomicAdd((unsigned long long *)&plan->n_small, (unsigned long long)n_small);
 }
 
-__device__ inline bool is_leader(const uint8_t *P, const uint32_t *Le, uint32_t i) {
-  uint32_t p = P[i];
-  return p > 0 && P[Le[i]] < p;
-}
-
-// One pointer-jumping round over the node leaders: the jump target moves to
-// the target's target and the distance adds up.  Roots point to themselves
-// with distance 0, so once every target is a root further rounds change
-// nothing; a round that finds this recorded by its predecessor only copies.
-__global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ P,
-                                              const uint32_t *__restrict__ Le,
+// One pointer-jumping round over the boundaries whose sflag has a bit of
+// `mask` (the leaders whose depth is wanted; their parents are among them):
+// the jump target moves to the target's target and the distance adds up.
+// Roots point to themselves with distance 0, so once every target is a root
+// further rounds change nothing; a round that finds this recorded by its
+// predecessor only copies.
+__global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ sflag, uint8_t mask,
                                               Plan *__restrict__ plan, int round,
                                               const uint32_t *__restrict__ jin,
                                               const uint8_t *__restrict__ din,
@@ -352,20 +384,28 @@ __global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ P,
   const uint64_t r = plan->r;
   const bool copy = round > 0 && plan->jump_more[round - 1] == 0;
   bool more = false;
-  for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
-       ii += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t i = (uint32_t)ii;
-    if (copy) {
-      jout[i] = jin[i];
-      dout[i] = din[i];
-      continue;
+  // 16 boundaries per thread: one 16-byte load of their flags (sflag has
+  // rmax + 1 >= r entries, padded to 16 bytes by the workspace layout)
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g * 16 < r;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    const uint4 fv = reinterpret_cast<const uint4 *>(sflag)[g];
+    const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      if (!((fw[q >> 2] >> ((q & 3) * 8)) & mask)) continue;
+      const uint32_t i = (uint32_t)(g * 16 + q);
+      if (i == 0 || i >= r) continue;
+      if (copy) {
+        jout[i] = jin[i];
+        dout[i] = din[i];
+        continue;
+      }
+      const uint32_t j = jin[i];
+      dout[i] = din[i] + din[j];
+      const uint32_t j2 = jin[j];
+      jout[i] = j2;
+      more = more || jin[j2] != j2;
     }
-    if (!is_leader(P, Le, i)) continue;
-    uint32_t j = jin[i];
-    dout[i] = din[i] + din[j];
-    const uint32_t j2 = jin[j];
-    jout[i] = j2;
-    more = more || jin[j2] != j2;
   }
   if (__syncthreads_or(more) && threadIdx.x == 0) atomicOr(&plan->jump_more[round], 1u);
 }
@@ -374,8 +414,11 @@ __global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ P,
 // node owning the larger of their powers (the leaf-depth identity in the
 // proof of Theorem 3.3); both 0 means the run is a whole segment.  Bit 7
 // (kLeafInSmall) marks a run whose parent is a small node: the small-subtree
-// pass, not placement, reads it.
+// pass, not placement, reads it; without FULL its depth is not computed.
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
+                                                const uint32_t *__restrict__ Ls,
+                                                const uint32_t *__restrict__ Rs,
                                                 const uint32_t *__restrict__ Le,
                                                 const uint8_t *__restrict__ dist,
                                                 const uint64_t *__restrict__ rs, Plan *plan,
@@ -390,21 +433,27 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
     uint32_t b = pa >= pb ? (uint32_t)j : (uint32_t)(j + 1);
     uint8_t d = 0, in_small = 0;
     if (P[b] > 0) {
-      uint32_t s;
-      const uint32_t lead = group_leader(P, Le, b, &s);
-      d = (uint8_t)(dist[lead] + 1);
-      in_small = (sflag[lead] & kSmallNode) ? kLeafInSmall : 0;
+      if (!FULL && rs[Rs[b]] - rs[Ls[b]] <= (uint64_t)kSmallSpan) {
+        in_small = kLeafInSmall;
+      } else {
+        uint32_t s;
+        const uint32_t lead = group_leader(P, Le, b, &s);
+        d = (uint8_t)(dist[lead] + 1);
+        in_small = (sflag[lead] & kSmallNode) ? kLeafInSmall : 0;
+      }
     }
     leaf_depth[j] = d | in_small;
-    if (in_small && d > dend) dend = d;
+    if (FULL && in_small && d > dend) dend = d;
     if (want_cost) cost += (uint64_t)d * (rs[j + 1] - rs[j]);
   }
-  // the deepest small node sits just above the deepest leaf of a small subtree
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t y = __shfl_down(dend, o);
-    dend = y > dend ? y : dend;
+  if (FULL) {
+    // the deepest small node sits just above the deepest leaf of a small subtree
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t y = __shfl_down(dend, o);
+      dend = y > dend ? y : dend;
+    }
+    if ((threadIdx.x & 63) == 0 && dend) atomicMax(&plan->small_depth_end, dend);
   }
-  if ((threadIdx.x & 63) == 0 && dend) atomicMax(&plan->small_depth_end, dend);
   if (want_cost) {
     for (int o = 32; o > 0; o >>= 1) cost += __shfl_down(cost, o);
     if ((threadIdx.x & 63) == 0 && cost) atomicAdd((unsigned long long *)&plan->merge_cost, (unsigned long long)cost);
@@ -413,9 +462,7 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
 
 // ---------------------------------------------------------------- level lists
 // Stable counting sort of the nodes (leaders) by depth.
-__global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__restrict__ P,
-                                                            const uint32_t *__restrict__ Le,
-                                                            const uint8_t *__restrict__ dist,
+__global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__restrict__ dist,
                                                             const uint8_t *__restrict__ sflag,
                                                             const Plan *__restrict__ plan,
                                                             uint32_t *__restrict__ cnt) {
@@ -427,8 +474,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__res
     if (t < kMaxLevels) sc[t] = 0;
     __syncthreads();
     uint64_t i = b * kTreeThreads + t;
-    if (i > 0 && i < r && is_leader(P, Le, (uint32_t)i) && !(sflag[i] & kSmallNode))
-      atomicAdd(&sc[dist[i]], 1u);
+    if (i > 0 && i < r && (sflag[i] & kBigLeader)) atomicAdd(&sc[dist[i]], 1u);
     __syncthreads();
     if (t < kMaxLevels) cnt[b * kMaxLevels + t] = sc[t];
     __syncthreads();
@@ -465,7 +511,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_scan(uint32_t *__restrict_
   if (t == 0) totals[d] = carry;
 }
 
-__global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals) {
+__global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals, int full) {
   if (threadIdx.x != 0) return;
   uint64_t acc = 0;
   uint32_t nl = 0;
@@ -478,22 +524,23 @@ __global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals) {
   // the level lists hold the nodes above the small subtrees; the small ones
   // count towards the tree's size and depth all the same
   plan->n_nodes = acc + plan->n_small;
+  plan->lvl_levels = nl;
   plan->n_levels = nl > plan->small_depth_end ? nl : plan->small_depth_end;
+  plan->lean = full ? 0u : 1u;
 }
 
 __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
-    const uint8_t *__restrict__ P, const uint32_t *__restrict__ Le,
     const uint8_t *__restrict__ dist, const uint8_t *__restrict__ sflag,
     const Plan *__restrict__ plan, const uint32_t *__restrict__ cnt,
     uint32_t *__restrict__ list) {
   __shared__ uint32_t sw[kTreeWaves][kMaxLevels];
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
-  const int nl = (int)plan->n_levels;   // every leader's depth is below this
+  const int nl = (int)plan->lvl_levels;   // every listed leader's depth is below this
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   for (uint64_t b = blockIdx.x; b < nbb; b += gridDim.x) {
     uint64_t i = b * kTreeThreads + t;
-    bool lead = i > 0 && i < r && is_leader(P, Le, (uint32_t)i) && !(sflag[i] & kSmallNode);
+    bool lead = i > 0 && i < r && (sflag[i] & kBigLeader);
     int myd = lead ? dist[i] : -1;
     uint32_t rank = 0;
     for (int d = 0; d < nl; d++) {
@@ -647,6 +694,23 @@ __global__ __launch_bounds__(256) void k_tile_map(const uint64_t *__restrict__ n
   }
 }
 
+// Before the tree of a sort built without FULL is rebuilt in full (for a
+// trace): the counters that the full build adds up start again.
+__global__ void k_tree_reset(Plan *plan) {
+  if (threadIdx.x != 0) return;
+  plan->n_small = 0;
+  plan->small_depth_end = 0;
+  plan->merge_cost = 0;
+  for (int i = 0; i < 8; i++) plan->jump_more[i] = 0;
+}
+
+// Sets n_levels from the rebuilt tree (the level lists keep their depths).
+__global__ void k_tree_done(Plan *plan) {
+  if (threadIdx.x != 0) return;
+  plan->n_levels = plan->lvl_levels > plan->small_depth_end ? plan->lvl_levels : plan->small_depth_end;
+  plan->lean = 0;
+}
+
 // ---------------------------------------------------------------- host side
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
                        uint32_t *tj, unsigned gtree, hipStream_t s) {
@@ -663,23 +727,50 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
   hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
   hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);
-  hipLaunchKernelGGL(k_nodes, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
+  const bool full = want_cost != 0;
+  if (full)
+    hipLaunchKernelGGL(k_nodes<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
+  else
+    hipLaunchKernelGGL(k_nodes<false>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
+  const uint8_t mask = full ? (uint8_t)(kBigLeader | kSmallNode) : (uint8_t)(kBigLeader | kSmallRoot);
   for (int round = 0; round < 6; round++) {  // depths < 64
     bool even = (round & 1) == 0;
-    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.power, w.Le, w.plan, round, even ? w.jump0 : w.jump1,
+    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.sflag, mask, w.plan, round, even ? w.jump0 : w.jump1,
                        even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0, even ? w.dist1 : w.dist0);
   }
-  hipLaunchKernelGGL(k_leaves, g256, b256, 0, s, w.power, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
-  hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.sflag, w.plan, w.lvl_cnt);
+  if (full)
+    hipLaunchKernelGGL(k_leaves<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
+  else
+    hipLaunchKernelGGL(k_leaves<false>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
+  hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt);
   hipLaunchKernelGGL(k_lvl_scan, dim3(kMaxLevels), dim3(kTreeThreads), 0, s, w.lvl_cnt, w.plan, lvl_tot);
-  hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot);
-  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.Le, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_list);
+  hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot, full ? 1 : 0);
+  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_list);
   hipLaunchKernelGGL(k_node_sizes, g256, b256, 0, s, w.lvl_list, w.Ls, w.Rs, w.run_start, w.plan, w.lvl_np);
   hipLaunchKernelGGL(k_scan_sums, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
   hipLaunchKernelGGL(k_scan_apply, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_lvl_tiles, dim3(1), dim3(64), 0, s, w.plan, w.lvl_np, w.tile, tile_base);
   hipLaunchKernelGGL(k_tile_map, dim3(2048), b256, 0, s, w.lvl_np, w.plan, w.tile, tile_base, tj);
+  return hipGetLastError();
+}
+
+// Rebuilds every node record, depth and leaf depth of the last sort's tree
+// (built without FULL), and its merge cost, from its powers, nearest-smaller
+// arrays and runs, all still in the workspace; the sort's output is not
+// touched.
+hipError_t launch_tree_complete(const Work &w, hipStream_t s) {
+  const dim3 g256(1024), b256(256);
+  hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, w.plan);
+  hipLaunchKernelGGL(k_nodes<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
+  for (int round = 0; round < 6; round++) {
+    bool even = (round & 1) == 0;
+    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.sflag, (uint8_t)(kBigLeader | kSmallNode), w.plan, round,
+                       even ? w.jump0 : w.jump1, even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0,
+                       even ? w.dist1 : w.dist0);
+  }
+  hipLaunchKernelGGL(k_leaves<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, 1, w.sflag, w.leaf_depth);
+  hipLaunchKernelGGL(k_tree_done, dim3(1), dim3(64), 0, s, w.plan);
   return hipGetLastError();
 }
 

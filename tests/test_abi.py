@@ -59,6 +59,15 @@ def test_argument_errors_need_no_gpu():
                                 None) == -4
 
 
+def test_stream_copy_argument_errors_need_no_gpu():
+    lib = mps.lib()
+    fake = ctypes.c_void_p(1 << 40)                                        # never dereferenced
+    assert lib.mps_stream_copy(None, fake, 64, None) == -1
+    assert lib.mps_stream_copy(ctypes.c_void_p((1 << 40) + 8), fake, 64, None) == -1   # misaligned
+    assert b"aligned" in lib.mps_last_error()
+    assert lib.mps_stream_copy(fake, fake, 0, None) == 0                   # nothing to copy
+
+
 def test_min_run_argument_errors_need_no_gpu():
     """min_run above 32, or with several arrays, is rejected before the
     workspace or the GPU is touched; 0 and 1 both mean natural runs."""

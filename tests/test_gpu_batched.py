@@ -68,6 +68,10 @@ def test_tile_configs_vs_oracle(tile, lane_slice, k):
         assert np.array_equal(tr.run_start, ot.run_start)
         assert np.array_equal(tr.power, ot.power)
         assert tr.merge_cost == ot.merge_cost
+        kd, pd = to_dev(keys), pay_dev(pay)     # without a trace
+        mps.sort(kd, pd, k=k, tile=tile, lane_slice=lane_slice)
+        assert np.array_equal(bits(kd.cpu().numpy()), bits(ok))
+        assert np.array_equal(pd.cpu().numpy().view(np.uint32), op)
 
 
 def test_bad_tile_config_rejected():
@@ -103,6 +107,15 @@ def test_batched_uneven_vs_oracle(tile, lane_slice):
     assert tr.merge_cost == M
     assert np.array_equal(tr.run_start, rs)
     assert np.array_equal(tr.power, pw)
+    kd, pd = to_dev(keys), pay_dev(pay)     # without a trace; the trace fetched afterwards
+    mps.sort_batched(kd, pd, od, k=4, host_offsets=off, tile=tile, lane_slice=lane_slice)
+    assert np.array_equal(kd.cpu().numpy(), ok)
+    assert np.array_equal(pd.cpu().numpy().view(np.uint32), op)
+    lt = mps.last_trace(DEV)
+    assert lt.merge_cost == M and lt.n_nodes == tr.n_nodes and lt.n_levels == tr.n_levels
+    assert np.array_equal(lt.leaf_depth, tr.leaf_depth)
+    assert np.array_equal(lt.node_depth, tr.node_depth)
+    assert np.array_equal(lt.node_arity, tr.node_arity)
 
 
 def test_graph_replay_matches_eager():

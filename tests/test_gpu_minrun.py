@@ -44,12 +44,19 @@ def gpu_sort(keys, pay, k, m, trace=True, graph=False):
 
 
 def check_vs_oracle(keys, pay, k, m):
+    """With a trace requested (whole tree built while sorting) and without (the
+    tree inside small subtrees is built only when the trace is fetched)."""
     ok, op, ot = oracle.sort(keys, pay, k=k, min_run=m)
     gk, gp, gt = gpu_sort(keys, pay, k, m)
     assert np.array_equal(bits(gk), bits(ok))
     if pay is not None:
         assert np.array_equal(gp, op)
     check_trace(gt, ot)
+    lk, lp, _ = gpu_sort(keys, pay, k, m, trace=False)
+    assert np.array_equal(bits(lk), bits(ok))
+    if pay is not None:
+        assert np.array_equal(lp, op)
+    check_trace(mps.last_trace("cuda:0"), ot)
     return gt
 
 

@@ -71,12 +71,20 @@ def check_trace(gt, ot):
 
 
 def check_vs_oracle(keys, pay, k):
+    """Both ways of running the sort against the oracle: with a trace requested
+    (the whole tree is built while sorting) and without (only the tree above the
+    small subtrees is built; fetching the trace afterwards builds the rest)."""
     ok, op, ot = oracle.sort(keys, pay, k=k)
     gk, gp, gt = gpu_sort(keys, pay, k)
     assert np.array_equal(bits(gk), bits(ok))
     if pay is not None:
         assert np.array_equal(gp, op)
     check_trace(gt, ot)
+    lk, lp, _ = gpu_sort(keys, pay, k, trace=False)
+    assert np.array_equal(bits(lk), bits(ok))
+    if pay is not None:
+        assert np.array_equal(lp, op)
+    check_trace(mps.last_trace(DEV), ot)
     return gt
 
 
@@ -250,9 +258,16 @@ def test_full_size(name, n):
     say(f"[gpu] full {name} n={n}: generating")
     keys, pay = workloads.WORKLOADS[name](n=n)
     say(f"[gpu] full {name}: sorting")
-    gk, gp, gt = gpu_sort(keys, pay, 4, trace=True)
+    gk, gp, _ = gpu_sort(keys, pay, 4, trace=False)     # as the benchmark runs it
+    gt = mps.last_trace(DEV)
     say(f"[gpu] full {name}: checking r={gt.r} nodes={gt.n_nodes}")
     check_stable_sort_properties(keys, gk, gp)
+    tk, tp, tt = gpu_sort(keys, pay, 4, trace=True)     # the whole tree built while sorting
+    assert np.array_equal(bits(tk), bits(gk)) and np.array_equal(tp, gp)
+    for f in ("r", "n_nodes", "merge_cost", "n_levels"):
+        assert getattr(tt, f) == getattr(gt, f), f
+    for f in ("run_start", "power", "leaf_depth", "node_first", "node_arity", "node_depth"):
+        assert np.array_equal(getattr(tt, f), getattr(gt, f)), f
     rs, rd = oracle.runs(keys)
     assert np.array_equal(gt.run_start, rs) and np.array_equal(gt.run_desc, rd)
     ot = oracle.tree_from_runs(rs, 4)

@@ -309,6 +309,30 @@ def test_matches_library_stable_sort(name, n, k):
         check_tree_invariants(tr, k)
 
 
+@pytest.mark.parametrize("name,n", [("runs_i32", 1 << 17), ("runs_i64", 1 << 17),
+                                    ("ties_i32", 1 << 17)])
+def test_matches_std_stable_sort(name, n):
+    """The oracle against C++ std::stable_sort of (key, payload) records."""
+    keys, pay = workloads.WORKLOADS[name](n=n)
+    rk, rp = oracle.stable_sort_ref(keys, pay)
+    for k in (2, 4):
+        sk, sp, _ = oracle.sort(keys, pay, k=k)
+        assert np.array_equal(sk, rk) and np.array_equal(sp, rp)
+
+
+def test_float_total_order_matches_std_stable_sort():
+    """Signed zeros and both signs under the total order, against std::stable_sort."""
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(50000).astype(np.float32)
+    f[::7] = -0.0
+    f[::11] = 0.0
+    f[::13] = np.float32(1e-42)        # subnormal
+    pay = np.arange(f.size, dtype=np.uint32)
+    rk, rp = oracle.stable_sort_ref(f, pay)
+    sk, sp, _ = oracle.sort(f, pay, k=4)
+    assert np.array_equal(sk.view(np.uint32), rk.view(np.uint32)) and np.array_equal(sp, rp)
+
+
 def test_permutation_exact():
     keys, pay = workloads.perm_i64(n=1 << 17, seed=5)
     sk, sp, _ = oracle.sort(keys, pay, k=4)
