@@ -470,6 +470,7 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
   }
   HIP_TRY(launch_tree(w, want_cost, lvl_tot, tile_base, tj, gtree, s));
   HIP_TRY(hipGetLastError());
+  if (w.min_run > 1) HIP_TRY(launch_minrun_sort(kt, keys, payload, w, s));
   HIP_TRY(launch_place(kt, keys, payload, w, s));
   HIP_TRY(launch_leaf(kt, keys, payload, w, s));
   for (int d = L.levels - 1; d >= 0; d--) {

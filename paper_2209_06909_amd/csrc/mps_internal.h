@@ -251,9 +251,11 @@ hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipSt
 // its root's depth parity.
 hipError_t launch_leaf(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 // Replaces the natural runs (w.nat_start / w.nat_desc, plan->r) by the runs
-// extended to w.min_run (w.run_start / w.run_desc, plan->r) and sorts the
-// extended runs of keys / vals in place.
+// extended to w.min_run (w.run_start / w.run_desc, plan->r).
 hipError_t launch_minrun(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
+// Sorts the extended runs of keys / vals in place, except those inside small
+// subtrees (after launch_tree: it reads the leaf depths).
+hipError_t launch_minrun_sort(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 hipError_t launch_level(int kt, const LevelArgs &a, const Work &w, const uint32_t *tj,
                         const uint64_t *tile_base, int level, hipStream_t s);
 // The merge launches of one level for one tile configuration (each defined in

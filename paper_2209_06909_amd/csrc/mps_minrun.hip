@@ -480,16 +480,20 @@ __device__ inline void rank_sort_run(uint32_t len, Load ld, Store st) {
   }
 }
 
-// Sorts the extended runs in place.  A workgroup takes kMrSortRuns
-// consecutive runs; when their span fits in LDS it is staged there with
-// coalesced loads, each thread sorts its own run between LDS and registers,
-// and the span is stored back coalesced (positions that carry a co-rank
-// sample refresh it).  A longer span (a long natural run among them) is
-// handled run by run straight from memory.
+// Sorts the extended runs in place, after the tree is built: a run inside a
+// small subtree is skipped, since the small-subtree pass sorts the subtree's
+// whole span anyway (the stable sort of a span does not depend on the order
+// inside its runs).  A workgroup takes kMrSortRuns consecutive runs; when
+// their span fits in LDS it is staged there with coalesced loads, each thread
+// sorts its own run between LDS and registers, and the span is stored back
+// coalesced (positions that carry a co-rank sample refresh it).  A longer
+// span (a long natural run among them) is handled run by run straight from
+// memory.
 template <int KT, int W>
 __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__restrict__ keys,
                                                          uint32_t *__restrict__ vals,
                                                          const uint64_t *__restrict__ rs,
+                                                         const uint8_t *__restrict__ leaf_depth,
                                                          const Plan *__restrict__ plan,
                                                          uint32_t m, uint64_t *__restrict__ smp) {
   using U = typename Key<KT>::U;
@@ -510,7 +514,8 @@ __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__
       s = rs[j];
       len = (uint32_t)(rs[j + 1] - s);
     }
-    const bool mine = len >= 2 && len <= m;
+    const bool mine = len >= 2 && len <= m && !(leaf_depth[j] & kLeafInSmall);
+    if (!__syncthreads_or(mine)) continue;   // uniform: nothing to sort here
     if (span <= kCap) {
       const uint32_t sp = (uint32_t)span;
       for (uint32_t x = t; x < sp; x += kMrSortRuns) {
@@ -560,9 +565,9 @@ template <int W>
 hipError_t launch_mr_sort(int kt, void *keys, uint32_t *vals, const Work &w, uint32_t m,
                           unsigned gs, hipStream_t s) {
   switch (kt) {
-    case 0: hipLaunchKernelGGL((k_mr_sort<0, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
-    case 1: hipLaunchKernelGGL((k_mr_sort<1, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint64_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
-    default: hipLaunchKernelGGL((k_mr_sort<2, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.plan, m, w.samples); break;
+    case 0: hipLaunchKernelGGL((k_mr_sort<0, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
+    case 1: hipLaunchKernelGGL((k_mr_sort<1, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint64_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
+    default: hipLaunchKernelGGL((k_mr_sort<2, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
   }
   return hipGetLastError();
 }
@@ -593,7 +598,12 @@ hipError_t launch_minrun(int kt, void *keys, uint32_t *vals, const Work &w, hipS
   hipLaunchKernelGGL(k_mr_emit, dim3(grid_for(nch, 1, 8192)), dim3(kMrThreads), 0, s,
                      w.nat_start, w.nat_desc, w.plan, (uint32_t)N, m, nch, w.mr_first, w.mr_centry,
                      w.mr_coff, w.rmax, w.run_start, w.run_desc);
-  const unsigned gs = grid_for(N / 2 + 2, kMrSortRuns, 16384);
+  return hipGetLastError();
+}
+
+hipError_t launch_minrun_sort(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s) {
+  const uint32_t m = (uint32_t)w.min_run;
+  const unsigned gs = grid_for(w.N / 2 + 2, kMrSortRuns, 16384);
   if (m <= 8) return launch_mr_sort<8>(kt, keys, vals, w, m, gs, s);
   if (m <= 16) return launch_mr_sort<16>(kt, keys, vals, w, m, gs, s);
   if (m <= 24) return launch_mr_sort<24>(kt, keys, vals, w, m, gs, s);

@@ -24,6 +24,17 @@ constexpr int kTreeThreads = 1024;   // boundaries per block
 constexpr int kTreeWaves = kTreeThreads / kWave;
 
 // ---------------------------------------------------------------- powers
+// floor(a * 2^31 / n) for a < 2n, n <= 2^31 (so the quotient is < 2^32 and
+// q * n < 2^63): a double estimate (relative error about 2^-52, hence off by
+// at most one), corrected with exact integer products.
+__device__ inline uint32_t quot31(uint64_t a, uint64_t n, double inv) {
+  const uint64_t num = a << 31;
+  uint64_t q = (uint64_t)((double)a * inv);
+  if (q * n > num) q--;
+  else if ((q + 1) * n <= num) q++;
+  return (uint32_t)q;
+}
+
 __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
                                                 const uint64_t *__restrict__ off, uint64_t m,
                                                 Plan *__restrict__ plan, int logk,
@@ -41,8 +52,9 @@ __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
         uint64_t n = off[sg + 1] - base;
         uint64_t A = (rs[i - 1] - base) + (s - base);
         uint64_t B = (s - base) + (rs[i + 1] - base);
-        uint32_t x = (uint32_t)((A << 31) / n);
-        uint32_t y = (uint32_t)((B << 31) / n);
+        const double inv = 2147483648.0 / (double)n;
+        uint32_t x = quot31(A, n, inv);
+        uint32_t y = quot31(B, n, inv);
         uint32_t p2 = (uint32_t)__clz(x ^ y) + 1;
         uint32_t pk = (p2 - 1) / (uint32_t)logk + 1;
         if (x == y || pk >= (uint32_t)kVMax) {  // impossible: b - a >= 1/n, n <= 2^31
@@ -105,58 +117,76 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_block(const uint8_t *__re
 }
 
 // One workgroup per value v: exclusive prefix max of BL and exclusive suffix
-// min of BF over the blocks.
+// min of BF over the blocks, kTreeThreads blocks per step: a shuffle scan in
+// every wave, then the wave totals.
+template <bool MAX>
+__device__ inline uint32_t blk_scan_incl(uint32_t x, uint32_t *sw, int t) {
+  const int lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(x, d);
+    if (lane >= d) x = MAX ? (o > x ? o : x) : (o < x ? o : x);
+  }
+  if (lane == 63) sw[w] = x;
+  __syncthreads();
+  for (int ww = 0; ww < w; ww++) {
+    const uint32_t o = sw[ww];
+    x = MAX ? (o > x ? o : x) : (o < x ? o : x);
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(kTreeThreads) void k_ansv_scan(const uint32_t *__restrict__ BL,
                                                             const uint32_t *__restrict__ BF,
                                                             const Plan *__restrict__ plan,
                                                             uint32_t *__restrict__ CL,
                                                             uint32_t *__restrict__ CR) {
-  __shared__ uint32_t s[kTreeThreads];
-  __shared__ uint32_t carry;
+  __shared__ uint32_t sw[kTreeWaves];
+  __shared__ uint32_t stot;
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
   const int v = blockIdx.x, t = threadIdx.x;
   if (v > (int)plan->pmax) return;   // value v + 1 is never asked for
-  if (t == 0) carry = 0;
-  __syncthreads();
+  uint32_t carry = 0;
+  uint32_t x = t < (int)nbb ? BL[(uint64_t)t * kVMax + v] : 0;
   for (uint64_t base = 0; base < nbb; base += kTreeThreads) {
-    uint64_t b = base + t;
-    uint32_t x = b < nbb ? BL[b * kVMax + v] : 0;
-    s[t] = x;
-    __syncthreads();
-    for (int d = 1; d < kTreeThreads; d <<= 1) {
-      uint32_t o = t >= d ? s[t - d] : 0;
-      __syncthreads();
-      if (o > s[t]) s[t] = o;
-      __syncthreads();
+    const uint64_t b = base + t, bn = b + kTreeThreads;
+    const uint32_t xn = bn < nbb ? BL[bn * kVMax + v] : 0;   // the next step's value, in flight
+    const uint32_t inc = blk_scan_incl<true>(x, sw, t);
+    const uint32_t prev = __shfl_up(inc, 1);
+    uint32_t ex = prev;
+    if ((t & 63) == 0) {
+      ex = 0;
+      for (int ww = 0; ww < (t >> 6); ww++) ex = sw[ww] > ex ? sw[ww] : ex;
     }
-    uint32_t ex = t > 0 ? s[t - 1] : 0;
-    if (carry > ex) ex = carry;
+    ex = carry > ex ? carry : ex;
     if (b < nbb) CL[b * kVMax + v] = ex;
+    if (t == kTreeThreads - 1) stot = inc;
     __syncthreads();
-    if (t == kTreeThreads - 1 && s[t] > carry) carry = s[t];
+    carry = stot > carry ? stot : carry;
     __syncthreads();
+    x = xn;
   }
-  if (t == 0) carry = kNone32;
-  __syncthreads();
+  carry = kNone32;
+  // from the end: slot t holds block nbb-1-(done+t)
+  x = t < (int)nbb ? BF[(nbb - 1 - (uint64_t)t) * kVMax + v] : kNone32;
   for (uint64_t done = 0; done < nbb; done += kTreeThreads) {
-    // process blocks from the end: slot t holds block nbb-1-(done+t)
-    uint64_t rb = done + t;
-    uint32_t x = rb < nbb ? BF[(nbb - 1 - rb) * kVMax + v] : kNone32;
-    s[t] = x;
-    __syncthreads();
-    for (int d = 1; d < kTreeThreads; d <<= 1) {
-      uint32_t o = t >= d ? s[t - d] : kNone32;
-      __syncthreads();
-      if (o < s[t]) s[t] = o;
-      __syncthreads();
+    const uint64_t rb = done + t, rn = rb + kTreeThreads;
+    const uint32_t xn = rn < nbb ? BF[(nbb - 1 - rn) * kVMax + v] : kNone32;
+    const uint32_t inc = blk_scan_incl<false>(x, sw, t);
+    const uint32_t prev = __shfl_up(inc, 1);
+    uint32_t ex = prev;
+    if ((t & 63) == 0) {
+      ex = kNone32;
+      for (int ww = 0; ww < (t >> 6); ww++) ex = sw[ww] < ex ? sw[ww] : ex;
     }
-    uint32_t ex = t > 0 ? s[t - 1] : kNone32;
-    if (carry < ex) ex = carry;
+    ex = carry < ex ? carry : ex;
     if (rb < nbb) CR[(nbb - 1 - rb) * kVMax + v] = ex;
+    if (t == kTreeThreads - 1) stot = inc;
     __syncthreads();
-    if (t == kTreeThreads - 1 && s[t] < carry) carry = s[t];
+    carry = stot < carry ? stot : carry;
     __syncthreads();
+    x = xn;
   }
 }
 
