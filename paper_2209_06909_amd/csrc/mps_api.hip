@@ -115,7 +115,7 @@ namespace {
 struct Layout {
   size_t total = 0;
   size_t alt_keys, alt_vals, seg_off, seg_bits, dbits, det_agg, det_zin, det_off, run_start, run_desc,
-      power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
+      power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, ansv_tl, ansv_tr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
       dist0, dist1, leaf_depth, sflag, cfirst, croot, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
       tj, samples, plan, nat_start, nat_desc, mr_first, mr_nxt, mr_cnt, mr_gnxt, mr_gcnt,
       mr_gentry, mr_goff, mr_centry, mr_coff;
@@ -172,6 +172,8 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.ansv_bf = take(c, nbb * kVMax * 4);
   L.ansv_cl = take(c, nbb * kVMax * 4);
   L.ansv_cr = take(c, nbb * kVMax * 4);
+  L.ansv_tl = take(c, (nbb / 1024 + 1) * kVMax * 4);   // chunks of 1024 blocks
+  L.ansv_tr = take(c, (nbb / 1024 + 1) * kVMax * 4);
   L.Ls = take(c, (rmax + 1) * 4);
   L.Rs = take(c, (rmax + 1) * 4);
   L.Le = take(c, (rmax + 1) * 4);
@@ -340,6 +342,8 @@ void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uin
   w.ansv_bf = at<uint32_t>(base, L.ansv_bf);
   w.ansv_cl = at<uint32_t>(base, L.ansv_cl);
   w.ansv_cr = at<uint32_t>(base, L.ansv_cr);
+  w.ansv_tl = at<uint32_t>(base, L.ansv_tl);
+  w.ansv_tr = at<uint32_t>(base, L.ansv_tr);
   w.Ls = at<uint32_t>(base, L.Ls);
   w.Rs = at<uint32_t>(base, L.Rs);
   w.Le = at<uint32_t>(base, L.Le);

@@ -134,6 +134,7 @@ struct Work {
   uint32_t *mr_goff, *mr_coff;       // [ng], [nch] index of the first run started there
   uint8_t *power;                    // [rmax+1], power[0] = power[r] = 0
   uint32_t *ansv_bl, *ansv_bf, *ansv_cl, *ansv_cr;   // [nbb * kVMax]
+  uint32_t *ansv_tl, *ansv_tr;       // [(nbb / 1024 + 1) * kVMax] carries per chunk of 1024 blocks
   uint32_t *Ls, *Rs, *Le, *Re;       // [rmax+1]
   uint8_t *nd_arity;                 // [rmax+1] (indexed by leader boundary)
   uint32_t *nd_mem;                  // [(rmax+1)*(k-1)]

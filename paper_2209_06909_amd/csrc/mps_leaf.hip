@@ -449,7 +449,7 @@ hipError_t launch_leaf(int kt, void *keys, uint32_t *vals, const Work &w, hipStr
   const unsigned gc = (unsigned)((nch + 1 + 255) / 256 < 4096 ? (nch + 1 + 255) / 256 : 4096);
   hipLaunchKernelGGL(k_chunk_runs, dim3(gc), dim3(256), 0, s, w.run_start, w.plan, w.N, w.cfirst,
                      w.croot);
-  hipLaunchKernelGGL(k_chunk_mark, dim3(1024), dim3(256), 0, s, w.run_start, w.Ls, w.Rs, w.sflag,
+  hipLaunchKernelGGL(k_chunk_mark, dim3(8192), dim3(256), 0, s, w.run_start, w.Ls, w.Rs, w.sflag,
                      w.dist0, w.plan, w.croot);
   switch (kt) {
     case 0: launch_leaf_kt<0>(keys, vals, w, s); break;

@@ -116,9 +116,12 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_block(const uint8_t *__re
   }
 }
 
-// One workgroup per value v: exclusive prefix max of BL and exclusive suffix
-// min of BF over the blocks, kTreeThreads blocks per step: a shuffle scan in
-// every wave, then the wave totals.
+// Carries across blocks, for every value v: CL = exclusive prefix max of BL
+// and CR = exclusive suffix min of BF over the blocks.  Done in two steps so
+// that every step is parallel: k_ansv_scan scans each chunk of kTreeThreads
+// blocks on its own (workgroup (chunk, v)) and records the chunk's total in
+// TL / TR; k_ansv_carry turns the chunk totals into exclusive carries over
+// the chunks; k_ansv_final combines the two.
 template <bool MAX>
 __device__ inline uint32_t blk_scan_incl(uint32_t x, uint32_t *sw, int t) {
   const int lane = t & 63, w = t >> 6;
@@ -140,18 +143,19 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_scan(const uint32_t *__re
                                                             const uint32_t *__restrict__ BF,
                                                             const Plan *__restrict__ plan,
                                                             uint32_t *__restrict__ CL,
-                                                            uint32_t *__restrict__ CR) {
+                                                            uint32_t *__restrict__ CR,
+                                                            uint32_t *__restrict__ TL,
+                                                            uint32_t *__restrict__ TR) {
   __shared__ uint32_t sw[kTreeWaves];
-  __shared__ uint32_t stot;
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
-  const int v = blockIdx.x, t = threadIdx.x;
+  const uint64_t nch = (nbb + kTreeThreads - 1) / kTreeThreads;
+  const int v = blockIdx.y, t = threadIdx.x;
   if (v > (int)plan->pmax) return;   // value v + 1 is never asked for
-  uint32_t carry = 0;
-  uint32_t x = t < (int)nbb ? BL[(uint64_t)t * kVMax + v] : 0;
-  for (uint64_t base = 0; base < nbb; base += kTreeThreads) {
-    const uint64_t b = base + t, bn = b + kTreeThreads;
-    const uint32_t xn = bn < nbb ? BL[bn * kVMax + v] : 0;   // the next step's value, in flight
+  for (uint64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    // prefix max, blocks in order
+    const uint64_t b = c * kTreeThreads + t;
+    const uint32_t x = b < nbb ? BL[b * kVMax + v] : 0u;
     const uint32_t inc = blk_scan_incl<true>(x, sw, t);
     const uint32_t prev = __shfl_up(inc, 1);
     uint32_t ex = prev;
@@ -159,34 +163,70 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_scan(const uint32_t *__re
       ex = 0;
       for (int ww = 0; ww < (t >> 6); ww++) ex = sw[ww] > ex ? sw[ww] : ex;
     }
-    ex = carry > ex ? carry : ex;
     if (b < nbb) CL[b * kVMax + v] = ex;
+    if (t == kTreeThreads - 1) TL[c * kVMax + v] = inc;
+    __syncthreads();
+    // suffix min: slot t holds the chunk's block kTreeThreads-1-t
+    const uint64_t bb = c * kTreeThreads + (kTreeThreads - 1 - t);
+    const uint32_t y = bb < nbb ? BF[bb * kVMax + v] : kNone32;
+    const uint32_t inc2 = blk_scan_incl<false>(y, sw, t);
+    const uint32_t prev2 = __shfl_up(inc2, 1);
+    uint32_t ex2 = prev2;
+    if ((t & 63) == 0) {
+      ex2 = kNone32;
+      for (int ww = 0; ww < (t >> 6); ww++) ex2 = sw[ww] < ex2 ? sw[ww] : ex2;
+    }
+    if (bb < nbb) CR[bb * kVMax + v] = ex2;
+    if (t == kTreeThreads - 1) TR[c * kVMax + v] = inc2;
+    __syncthreads();
+  }
+}
+
+// Chunk totals -> exclusive carries over the chunks (prefix max for TL,
+// suffix min for TR), one workgroup per value.
+__global__ __launch_bounds__(kTreeThreads) void k_ansv_carry(const Plan *__restrict__ plan,
+                                                             uint32_t *__restrict__ TL,
+                                                             uint32_t *__restrict__ TR) {
+  __shared__ uint32_t sw[kTreeWaves];
+  __shared__ uint32_t stot;
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const uint64_t nch = (nbb + kTreeThreads - 1) / kTreeThreads;
+  const int v = blockIdx.x, t = threadIdx.x;
+  if (v > (int)plan->pmax) return;
+  uint32_t carry = 0;
+  for (uint64_t base = 0; base < nch; base += kTreeThreads) {
+    const uint64_t c = base + t;
+    const uint32_t x = c < nch ? TL[c * kVMax + v] : 0u;
+    const uint32_t inc = blk_scan_incl<true>(x, sw, t);
+    uint32_t ex = __shfl_up(inc, 1);
+    if ((t & 63) == 0) {
+      ex = 0;
+      for (int ww = 0; ww < (t >> 6); ww++) ex = sw[ww] > ex ? sw[ww] : ex;
+    }
+    ex = carry > ex ? carry : ex;
     if (t == kTreeThreads - 1) stot = inc;
     __syncthreads();
+    if (c < nch) TL[c * kVMax + v] = ex;
     carry = stot > carry ? stot : carry;
     __syncthreads();
-    x = xn;
   }
   carry = kNone32;
-  // from the end: slot t holds block nbb-1-(done+t)
-  x = t < (int)nbb ? BF[(nbb - 1 - (uint64_t)t) * kVMax + v] : kNone32;
-  for (uint64_t done = 0; done < nbb; done += kTreeThreads) {
-    const uint64_t rb = done + t, rn = rb + kTreeThreads;
-    const uint32_t xn = rn < nbb ? BF[(nbb - 1 - rn) * kVMax + v] : kNone32;
+  for (uint64_t done = 0; done < nch; done += kTreeThreads) {
+    const uint64_t rc = done + t;   // chunk nch-1-rc
+    const uint32_t x = rc < nch ? TR[(nch - 1 - rc) * kVMax + v] : kNone32;
     const uint32_t inc = blk_scan_incl<false>(x, sw, t);
-    const uint32_t prev = __shfl_up(inc, 1);
-    uint32_t ex = prev;
+    uint32_t ex = __shfl_up(inc, 1);
     if ((t & 63) == 0) {
       ex = kNone32;
       for (int ww = 0; ww < (t >> 6); ww++) ex = sw[ww] < ex ? sw[ww] : ex;
     }
     ex = carry < ex ? carry : ex;
-    if (rb < nbb) CR[(nbb - 1 - rb) * kVMax + v] = ex;
     if (t == kTreeThreads - 1) stot = inc;
     __syncthreads();
+    if (rc < nch) TR[(nch - 1 - rc) * kVMax + v] = ex;
     carry = stot < carry ? stot : carry;
     __syncthreads();
-    x = xn;
   }
 }
 
@@ -194,7 +234,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_scan(const uint32_t *__re
 // both sides of every boundary 1 <= i < r with power > 0.
 __global__ __launch_bounds__(kTreeThreads) void k_ansv_final(
     const uint8_t *__restrict__ P, Plan *__restrict__ plan, const uint32_t *__restrict__ CL,
-    const uint32_t *__restrict__ CR, uint32_t *__restrict__ Ls, uint32_t *__restrict__ Rs,
+    const uint32_t *__restrict__ CR, const uint32_t *__restrict__ TL,
+    const uint32_t *__restrict__ TR, uint32_t *__restrict__ Ls, uint32_t *__restrict__ Rs,
     uint32_t *__restrict__ Le, uint32_t *__restrict__ Re) {
   __shared__ uint64_t sM[kTreeWaves][kVMax];
   __shared__ uint32_t sPL[kTreeWaves][kVMax];   // last+1 in earlier waves (0 = none)
@@ -235,12 +276,18 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_final(
           uint32_t L;
           if (mk) L = (uint32_t)(wbase + 63 - __clzll(mk));
           else if (sPL[w][vi]) L = sPL[w][vi] - 1;
-          else L = CL[b * kVMax + vi] - 1;
+          else {
+            const uint32_t c0 = CL[b * kVMax + vi], c1 = TL[(b / kTreeThreads) * kVMax + vi];
+            L = (c0 > c1 ? c0 : c1) - 1;
+          }
           uint64_t mr = sM[w][vi] & above;
           uint32_t R;
           if (mr) R = (uint32_t)(wbase + __ffsll((long long)mr) - 1);
           else if (sPR[w][vi] != kNone32) R = sPR[w][vi];
-          else R = CR[b * kVMax + vi];
+          else {
+            const uint32_t c0 = CR[b * kVMax + vi], c1 = TR[(b / kTreeThreads) * kVMax + vi];
+            R = c0 < c1 ? c0 : c1;
+          }
           if (L >= i || R <= i || R > r) {  // P[0] = P[r] = 0 make both always exist
             atomicOr(&plan->error, 64u);
             L = 0;
@@ -742,21 +789,30 @@ __global__ void k_tree_done(Plan *plan) {
 }
 
 // ---------------------------------------------------------------- host side
+static void launch_ansv_carries(const Work &w, hipStream_t s) {
+  const uint64_t nbb = (w.rmax + 1 + kTreeThreads - 1) / kTreeThreads;
+  const uint64_t nch = (nbb + kTreeThreads - 1) / kTreeThreads;
+  const unsigned gx = (unsigned)(nch < 1024 ? nch : 1024);
+  hipLaunchKernelGGL(k_ansv_scan, dim3(gx, kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan,
+                     w.ansv_cl, w.ansv_cr, w.ansv_tl, w.ansv_tr);
+  hipLaunchKernelGGL(k_ansv_carry, dim3(kVMax), dim3(kTreeThreads), 0, s, w.plan, w.ansv_tl, w.ansv_tr);
+}
+
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
                        uint32_t *tj, unsigned gtree, hipStream_t s) {
-  const dim3 g256(1024), b256(256);
+  const dim3 g256(8192), b256(256);
   hipLaunchKernelGGL(k_powers, g256, b256, 0, s, w.run_start, w.off, w.m, w.plan, w.logk, w.power);
   if (w.merge_down && w.k > 2) {
     // nearest smaller values of the true powers give the spine; its groups
     // get their new powers, and the pass below runs on those
     hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
-    hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
-    hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);
+    launch_ansv_carries(w, s);
+    hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.ansv_tl, w.ansv_tr, w.Ls, w.Rs, w.Le, w.Re);
     hipLaunchKernelGGL(k_spine, dim3(1), dim3(64), 0, s, w.power, w.Le, w.plan, w.k);
   }
   hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
-  hipLaunchKernelGGL(k_ansv_scan, dim3(kVMax), dim3(kTreeThreads), 0, s, w.ansv_bl, w.ansv_bf, w.plan, w.ansv_cl, w.ansv_cr);
-  hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.Ls, w.Rs, w.Le, w.Re);
+  launch_ansv_carries(w, s);
+  hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.ansv_tl, w.ansv_tr, w.Ls, w.Rs, w.Le, w.Re);
   const bool full = want_cost != 0;
   if (full)
     hipLaunchKernelGGL(k_nodes<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
@@ -790,7 +846,7 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
 // arrays and runs, all still in the workspace; the sort's output is not
 // touched.
 hipError_t launch_tree_complete(const Work &w, hipStream_t s) {
-  const dim3 g256(1024), b256(256);
+  const dim3 g256(8192), b256(256);
   hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, w.plan);
   hipLaunchKernelGGL(k_nodes<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
   for (int round = 0; round < 6; round++) {
