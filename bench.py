@@ -461,6 +461,9 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=3)
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--only", choices=["perm", "records"],
+                    help="run just the random-permutation or the 16-byte-record variant and print "
+                         "its figures (for profiling them on their own)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -473,6 +476,11 @@ def main():
     import workloads
 
     n = 1 << args.log2n
+    tcfg = dict(tile=args.tile, lane_slice=args.lane_slice)
+    if args.only == "perm":
+        torch.cuda.set_device(0)
+        print(json.dumps({"perm_variant": bench_perm(args, torch, mps, workloads, tcfg)}), flush=True)
+        return
     log(f"generating runs_i64 n=2^{args.log2n}")
     keys_h, pay_h = workloads.runs_i64(n=n)
     dev = torch.device("cuda:0")
@@ -482,11 +490,14 @@ def main():
     keys = torch.empty_like(keys0)
     pay = torch.empty_like(pay0)
     KV = 8 + 4
+    if args.only == "records":
+        del pay0, pay
+        print(json.dumps({"records16": bench_records(args, torch, mps, keys0, tcfg)}), flush=True)
+        return
 
     # one untimed traced sort: runs, merge cost and placement volume
     keys.copy_(keys0)
     pay.copy_(pay0)
-    tcfg = dict(tile=args.tile, lane_slice=args.lane_slice)
     tr = mps.sort(keys, pay, k=args.k, trace=True, **tcfg)
     rs = tr.run_start.astype(np.int64)
     lens = np.diff(rs)

@@ -116,7 +116,7 @@ struct Layout {
   size_t total = 0;
   size_t alt_keys, alt_vals, seg_off, seg_bits, dbits, det_agg, det_zin, det_off, run_start, run_desc,
       power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, ansv_tl, ansv_tr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
-      dist0, dist1, leaf_depth, sflag, cfirst, croot, lvl_cnt, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
+      dist0, dist1, leaf_depth, sflag, cfirst, croot, lvl_cnt, lvl_car, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
       tj, samples, plan, nat_start, nat_desc, mr_first, mr_nxt, mr_cnt, mr_gnxt, mr_gcnt,
       mr_gentry, mr_goff, mr_centry, mr_coff;
   uint64_t rmax, nbb, tiles_max, tj_cap;
@@ -189,6 +189,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   L.cfirst = take(c, (N / kLeafChunk + 2) * 4);
   L.croot = take(c, (N / kLeafChunk + 2) * kChunkRec * 4);
   L.lvl_cnt = take(c, nbb * kMaxLevels * 4);
+  L.lvl_car = take(c, (nbb / 1024 + 1) * kMaxLevels * 4);
   L.lvl_tot = take(c, kMaxLevels * 8);
   L.lvl_list = take(c, rmax * 4);
   L.lvl_np = take(c, (rmax + 2) * 8);
@@ -359,6 +360,7 @@ void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uin
   w.cfirst = at<uint32_t>(base, L.cfirst);
   w.croot = at<uint32_t>(base, L.croot);
   w.lvl_cnt = at<uint32_t>(base, L.lvl_cnt);
+  w.lvl_car = at<uint32_t>(base, L.lvl_car);
   w.lvl_list = at<uint32_t>(base, L.lvl_list);
   w.lvl_np = at<uint64_t>(base, L.lvl_np);
   w.scan_tmp = at<uint64_t>(base, L.scan_tmp);

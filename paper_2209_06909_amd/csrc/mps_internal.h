@@ -145,6 +145,7 @@ struct Work {
   uint32_t *cfirst;                  // [N/kLeafChunk + 2] run holding each chunk's first position
   uint32_t *croot;                   // [(N/kLeafChunk + 2) * kChunkRec] small roots starting in each chunk
   uint32_t *lvl_cnt;                 // [nbb * kMaxLevels]
+  uint32_t *lvl_car;                 // [(nbb / 1024 + 1) * kMaxLevels] carries per chunk of 1024 blocks
   uint32_t *lvl_list;                // [rmax]
   uint64_t *lvl_np;                  // [rmax+1] exclusive prefix of node sizes
   uint64_t *scan_tmp;                // [nbb + 1024]

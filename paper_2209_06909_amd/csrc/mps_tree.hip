@@ -558,31 +558,60 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_count(const uint8_t *__res
   }
 }
 
-// One workgroup per depth: exclusive prefix over blocks (in place) and the total.
+// Exclusive prefix sums of the per-block counts over the blocks, for every
+// depth, in two parallel steps: workgroup (chunk, d) scans a chunk of
+// kTreeThreads blocks and records its total; k_lvl_carry turns the chunk
+// totals into exclusive carries (and the depth's total).  A block's offset is
+// its chunk-local prefix plus its chunk's carry.
+__device__ inline uint32_t blk_sum_incl(uint32_t x, uint32_t *sw, int t) {
+  const int lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(x, d);
+    if (lane >= d) x += o;
+  }
+  if (lane == 63) sw[w] = x;
+  __syncthreads();
+  for (int ww = 0; ww < w; ww++) x += sw[ww];
+  return x;
+}
+
 __global__ __launch_bounds__(kTreeThreads) void k_lvl_scan(uint32_t *__restrict__ cnt,
-                                                           Plan *__restrict__ plan,
-                                                           uint64_t *__restrict__ totals) {
-  __shared__ uint32_t s[kTreeThreads];
-  __shared__ uint64_t carry;
+                                                           const Plan *__restrict__ plan,
+                                                           uint32_t *__restrict__ car) {
+  __shared__ uint32_t sw[kTreeWaves];
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const uint64_t nch = (nbb + kTreeThreads - 1) / kTreeThreads;
+  const int d = blockIdx.y, t = threadIdx.x;
+  for (uint64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const uint64_t b = c * kTreeThreads + t;
+    const uint32_t x = b < nbb ? cnt[b * kMaxLevels + d] : 0u;
+    const uint32_t inc = blk_sum_incl(x, sw, t);
+    if (b < nbb) cnt[b * kMaxLevels + d] = inc - x;
+    if (t == kTreeThreads - 1) car[c * kMaxLevels + d] = inc;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kTreeThreads) void k_lvl_carry(const Plan *__restrict__ plan,
+                                                            uint32_t *__restrict__ car,
+                                                            uint64_t *__restrict__ totals) {
+  __shared__ uint32_t sw[kTreeWaves];
+  __shared__ uint32_t stot;
+  const uint64_t r = plan->r;
+  const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
+  const uint64_t nch = (nbb + kTreeThreads - 1) / kTreeThreads;
   const int d = blockIdx.x, t = threadIdx.x;
-  if (t == 0) carry = 0;
-  __syncthreads();
-  for (uint64_t base = 0; base < nbb; base += kTreeThreads) {
-    uint64_t b = base + t;
-    uint32_t x = b < nbb ? cnt[b * kMaxLevels + d] : 0;
-    s[t] = x;
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < nch; base += kTreeThreads) {
+    const uint64_t c = base + t;
+    const uint32_t x = c < nch ? car[c * kMaxLevels + d] : 0u;
+    const uint32_t inc = blk_sum_incl(x, sw, t);
+    if (t == kTreeThreads - 1) stot = inc;
     __syncthreads();
-    for (int o = 1; o < kTreeThreads; o <<= 1) {
-      uint32_t y = t >= o ? s[t - o] : 0;
-      __syncthreads();
-      s[t] += y;
-      __syncthreads();
-    }
-    if (b < nbb) cnt[b * kMaxLevels + d] = (uint32_t)(carry + s[t] - x);
-    __syncthreads();
-    if (t == kTreeThreads - 1) carry += s[t];
+    if (c < nch) car[c * kMaxLevels + d] = (uint32_t)(carry + inc - x);
+    carry += stot;
     __syncthreads();
   }
   if (t == 0) totals[d] = carry;
@@ -609,7 +638,7 @@ __global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals, int 
 __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
     const uint8_t *__restrict__ dist, const uint8_t *__restrict__ sflag,
     const Plan *__restrict__ plan, const uint32_t *__restrict__ cnt,
-    uint32_t *__restrict__ list) {
+    const uint32_t *__restrict__ car, uint32_t *__restrict__ list) {
   __shared__ uint32_t sw[kTreeWaves][kMaxLevels];
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
@@ -636,7 +665,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
     }
     __syncthreads();
     if (lead) {
-      uint64_t pos = plan->lvl_begin[myd] + cnt[b * kMaxLevels + myd] + sw[w][myd] + rank;
+      uint64_t pos = plan->lvl_begin[myd] + car[(b / kTreeThreads) * kMaxLevels + myd] +
+                     cnt[b * kMaxLevels + myd] + sw[w][myd] + rank;
       list[pos] = (uint32_t)i;
     }
     __syncthreads();
@@ -829,9 +859,15 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   else
     hipLaunchKernelGGL(k_leaves<false>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
   hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt);
-  hipLaunchKernelGGL(k_lvl_scan, dim3(kMaxLevels), dim3(kTreeThreads), 0, s, w.lvl_cnt, w.plan, lvl_tot);
+  {
+    const uint64_t nbb = (w.rmax + 1 + kTreeThreads - 1) / kTreeThreads;
+    const uint64_t nch = (nbb + kTreeThreads - 1) / kTreeThreads;
+    const unsigned gx = (unsigned)(nch < 1024 ? nch : 1024);
+    hipLaunchKernelGGL(k_lvl_scan, dim3(gx, kMaxLevels), dim3(kTreeThreads), 0, s, w.lvl_cnt, w.plan, w.lvl_car);
+    hipLaunchKernelGGL(k_lvl_carry, dim3(kMaxLevels), dim3(kTreeThreads), 0, s, w.plan, w.lvl_car, lvl_tot);
+  }
   hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot, full ? 1 : 0);
-  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_list);
+  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_car, w.lvl_list);
   hipLaunchKernelGGL(k_node_sizes, g256, b256, 0, s, w.lvl_list, w.Ls, w.Rs, w.run_start, w.plan, w.lvl_np);
   hipLaunchKernelGGL(k_scan_sums, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
