@@ -186,11 +186,10 @@ uint64_t mps_noalloc_scratch_bytes(void);
 /* Records of a key and an 8-byte payload, such as the key-and-pointer records
  * of the paper's experiments with 16-byte records (Section 4): the stable sort
  * of mps_sort_ex, with payload (device, n u64) permuted with the keys.  The
- * merges carry each record's 4-byte index; the payload is gathered once after
- * the last merge, through a buffer in the workspace (mps_workspace_bytes with
- * has_payload = 2: 12 bytes per key more than a u32 payload).  Options, trace,
- * limits and errors as mps_sort_ex; payload NULL or n <= 1 is mps_sort_ex
- * without a payload. */
+ * merges carry each 8-byte payload with its key (mps_workspace_bytes with
+ * has_payload = 2: an 8-byte ping-pong payload buffer, 4 bytes per key more
+ * than a u32 payload).  Options, trace, limits and errors as mps_sort_ex;
+ * payload NULL or n <= 1 is mps_sort_ex without a payload. */
 int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uint64_t n,
                   const mps_opts *opts, mps_trace *trace, void *stream);
 

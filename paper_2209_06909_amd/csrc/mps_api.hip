@@ -48,25 +48,6 @@ __global__ void k_report(const Plan *plan, uint32_t *error_out) {
   if (threadIdx.x == 0 && plan->error) atomicOr(error_out, plan->error);
 }
 
-// Records with an 8-byte payload: the sort carries the u32 index of every
-// record; the payload is gathered once at the end.
-__global__ __launch_bounds__(256) void k_iota32(uint32_t *__restrict__ idx, uint64_t n) {
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
-    idx[i] = (uint32_t)i;
-}
-
-__global__ __launch_bounds__(256) void k_gather64(const uint64_t *__restrict__ src,
-                                                  const uint32_t *__restrict__ idx,
-                                                  uint64_t *__restrict__ dst, uint64_t n) {
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
-    dst[i] = src[idx[i]];
-}
-
-__global__ __launch_bounds__(256) void k_copy64(const uint64_t *__restrict__ src,
-                                                uint64_t *__restrict__ dst, uint64_t n) {
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
-    dst[i] = src[i];
-}
 
 __global__ void k_check_offsets(const uint64_t *off, uint64_t m, uint64_t total, Plan *plan) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
@@ -142,9 +123,8 @@ int levels_for(uint64_t n, uint32_t k) {
 
 // Bytes after a sort's workspace for records with an 8-byte payload: the u32
 // record indices and the gather buffer, each 256-byte aligned.
-uint64_t record_extra(uint64_t n) { return 256 + ((n * 4 + 255) & ~(uint64_t)255) + n * 8 + 256; }
 
-bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layout &L) {
+bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) {
   if (N == 0 || m == 0) return false;
   size_t ks = kt == MPS_I64 ? 8 : 4;
   uint64_t rmax = N / 2 + m + 2;
@@ -158,7 +138,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, bool payload, uint32_t k, Layou
   size_t c = 0;
   L.plan = take(c, sizeof(Plan));    // first: a later trace fetch finds it at the base
   L.alt_keys = take(c, N * ks);
-  L.alt_vals = take(c, payload ? N * 4 : 0);
+  L.alt_vals = take(c, N * (uint64_t)pb);   // pb: payload bytes per key (0, 4 or 8)
   L.seg_off = take(c, 16);
   L.seg_bits = take(c, m > 1 ? nwords * 8 + 8 : 0);
   L.dbits = take(c, nwords * 8 + 8);
@@ -306,7 +286,7 @@ template <typename T> T *at(void *base, size_t off) {
 
 // Device views of the workspace at `base` (laid out by L).
 void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uint32_t k, int tile,
-               int threads, bool payload, const uint64_t *d_off) {
+               int threads, int pb, const uint64_t *d_off) {
   w.N = N;
   w.m = m;
   w.rmax = L.rmax;
@@ -315,7 +295,8 @@ void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uin
   w.tile = tile;
   w.threads = threads;
   w.alt_keys = at<void>(base, L.alt_keys);
-  w.alt_vals = payload ? at<uint32_t>(base, L.alt_vals) : nullptr;
+  w.alt_vals = pb ? at<uint32_t>(base, L.alt_vals) : nullptr;
+  w.pay8 = pb == 8 ? 1 : 0;
   w.seg_off_local = at<uint64_t>(base, L.seg_off);
   w.off = d_off ? d_off : w.seg_off_local;
   w.seg_bits = m > 1 ? at<uint64_t>(base, L.seg_bits) : nullptr;
@@ -381,10 +362,10 @@ int fill_trace(void *base, mps_trace *tr) {
   if (plan.lean && plan.n >= 2) {
     // the sort left the insides of its small subtrees out: build them now
     Layout L;
-    if (!make_layout(plan.n, plan.m, (int)plan.kt, plan.has_payload != 0, plan.k, L))
+    if (!make_layout(plan.n, plan.m, (int)plan.kt, (int)plan.has_payload, plan.k, L))
       return fail(MPS_E_DEVICE, "workspace header does not describe a layout");
     Work w{};
-    bind_work(w, base, L, plan.n, plan.m, plan.k, 0, 0, plan.has_payload != 0, nullptr);
+    bind_work(w, base, L, plan.n, plan.m, plan.k, 0, 0, (int)plan.has_payload, nullptr);
     HIP_TRY(launch_tree_complete(w, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
@@ -397,7 +378,7 @@ int fill_trace(void *base, mps_trace *tr) {
   tr->n_levels = plan.n_levels;
   tr->k = plan.k;
   Layout L;
-  if (plan.n < 2 || !make_layout(plan.n, plan.m, (int)plan.kt, plan.has_payload != 0, plan.k, L))
+  if (plan.n < 2 || !make_layout(plan.n, plan.m, (int)plan.kt, (int)plan.has_payload, plan.k, L))
     return MPS_OK;
   const uint64_t r = plan.r;
   bool want_runs = tr->run_start || tr->run_desc || tr->power || tr->leaf_depth;
@@ -460,7 +441,8 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
                  hipStream_t s) {
   const unsigned gtree = (unsigned)(L.nbb < 4096 ? L.nbb : 4096);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w.plan, w.seg_off_local, w.N, w.m,
-                     (uint32_t)kt, payload ? 1u : 0u, (uint32_t)w.k, d_off ? 0 : 1, init_error);
+                     (uint32_t)kt, payload ? (w.pay8 ? 8u : 4u) : 0u, (uint32_t)w.k, d_off ? 0 : 1,
+                     init_error);
   if (d_off)
     hipLaunchKernelGGL(k_check_offsets, dim3(64), dim3(256), 0, s, d_off, w.m, w.N, w.plan);
   HIP_TRY(hipGetLastError());
@@ -505,15 +487,15 @@ int enqueue_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, c
 // launch sequence.  Captured on a library stream (capture only records), then
 // launched on the caller's stream.
 struct GraphKey {
-  int dev, kt, k, tile, threads, want_cost, min_run, merge_down;
+  int dev, kt, k, tile, threads, want_cost, min_run, merge_down, pb;
   uint32_t init_error;
   const void *keys, *payload, *off, *base, *error_out;
   uint64_t m, N;
   bool operator<(const GraphKey &o) const {
-    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, merge_down, init_error, keys,
-                    payload, off, base, error_out, m, N) <
+    return std::tie(dev, kt, k, tile, threads, want_cost, min_run, merge_down, pb, init_error,
+                    keys, payload, off, base, error_out, m, N) <
            std::tie(o.dev, o.kt, o.k, o.tile, o.threads, o.want_cost, o.min_run, o.merge_down,
-                    o.init_error, o.keys, o.payload, o.off, o.base, o.error_out, o.m, o.N);
+                    o.pb, o.init_error, o.keys, o.payload, o.off, o.base, o.error_out, o.m, o.N);
   }
 };
 std::mutex g_graph_mu;
@@ -573,8 +555,10 @@ int resolve_tile(const mps_opts *opts, int &tile, int &threads) {
   return MPS_OK;
 }
 
+// pb: payload bytes per key when payload is not NULL (4, or 8 for records).
 int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint64_t m,
-             uint64_t N, const mps_opts *opts, mps_trace *trace, hipStream_t s) {
+             uint64_t N, const mps_opts *opts, mps_trace *trace, hipStream_t s, int pb = 4) {
+  if (!payload) pb = 0;
   uint32_t k = opts ? opts->k : 0;
   int rc = check_k(k);
   if (rc) return rc;
@@ -592,7 +576,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   if ((flags & MPS_OPT_GRAPH) && (flags & MPS_OPT_TIME_LEVELS))
     return fail(MPS_E_INVALID, "MPS_OPT_GRAPH cannot be combined with MPS_OPT_TIME_LEVELS");
   Layout L;
-  if (!make_layout(N, m, kt, payload != nullptr, k, L)) return fail(MPS_E_INVALID, "bad sizes");
+  if (!make_layout(N, m, kt, pb, k, L)) return fail(MPS_E_INVALID, "bad sizes");
   void *base = nullptr;
   if (opts && opts->workspace) {
     if (opts->workspace_bytes < L.total)
@@ -605,7 +589,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   base = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(base) + 255) & ~(uintptr_t)255);
 
   Work w{};
-  bind_work(w, base, L, N, m, k, tile, threads, payload != nullptr, d_off);
+  bind_work(w, base, L, N, m, k, tile, threads, pb, d_off);
   w.min_run = (int)min_run;
   w.merge_down = (flags & MPS_OPT_MERGE_DOWN) ? 1 : 0;
   uint64_t *lvl_tot = at<uint64_t>(base, L.lvl_tot);
@@ -618,7 +602,7 @@ int run_sort(void *keys, int kt, uint32_t *payload, const uint64_t *d_off, uint6
   HIP_TRY(hipGetDevice(&dev));
 
   if (flags & MPS_OPT_GRAPH) {
-    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, w.merge_down, init_error,
+    GraphKey key{dev, kt, (int)k, tile, threads, want_cost, w.min_run, w.merge_down, pb, init_error,
                  keys, payload, d_off, base, error_out, m, N};
     rc = graph_launch(key, keys, kt, payload, d_off, w, L, lvl_tot, tile_base, tj, s);
     if (rc) return rc;
@@ -656,9 +640,9 @@ extern "C" uint64_t mps_workspace_bytes(uint64_t n, uint64_t m, mps_key_type kt,
   if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return 0;
   if (has_payload < 0 || has_payload > 2 || (has_payload == 2 && m > 1)) return 0;
   Layout L;
-  if (!make_layout(n < 2 ? 2 : n, m < 1 ? 1 : m, kt, has_payload != 0, k, L)) return 0;
-  // 8-byte payloads: the record indices and a gather buffer follow the sort's part
-  return has_payload == 2 ? L.total + record_extra(n < 2 ? 2 : n) : L.total;
+  if (!make_layout(n < 2 ? 2 : n, m < 1 ? 1 : m, kt, has_payload == 2 ? 8 : (has_payload ? 4 : 0), k, L))
+    return 0;
+  return L.total;
 }
 
 extern "C" int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
@@ -697,47 +681,9 @@ extern "C" int mps_sort_kv64(void *keys, mps_key_type kt, uint64_t *payload, uin
   if (kt != MPS_I32 && kt != MPS_I64 && kt != MPS_F32) return fail(MPS_E_INVALID, "unknown key type");
   if (!keys) return fail(MPS_E_INVALID, "keys is NULL");
   if (n > (1ull << 31)) return fail(MPS_E_UNSUPPORTED, "arrays longer than 2^31 are not supported");
-  uint32_t k = opts ? opts->k : 0;
-  int rc = check_k(k);
-  if (rc) return rc;
-  Layout L;
-  if (!make_layout(n, 1, kt, true, k, L)) return fail(MPS_E_INVALID, "bad sizes");
-  const uint64_t need = L.total + record_extra(n);
-  void *base = nullptr;
-  if (opts && opts->workspace) {
-    if (opts->workspace_bytes < need)
-      return failf(MPS_E_NOMEM, "workspace too small: need %llu bytes", (unsigned long long)need);
-    base = opts->workspace;
-  } else {
-    rc = get_workspace(need, (hipStream_t)stream, &base);
-    if (rc) return rc;
-  }
-  char *ex = static_cast<char *>(base) + L.total;
-  ex = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ex) + 255) & ~(uintptr_t)255);
-  uint32_t *idx = reinterpret_cast<uint32_t *>(ex);
-  uint64_t *tmp = reinterpret_cast<uint64_t *>(ex + ((n * 4 + 255) & ~(uint64_t)255));
-  hipStream_t s = (hipStream_t)stream;
-  const unsigned g = (unsigned)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
-  hipLaunchKernelGGL(k_iota32, dim3(g), dim3(256), 0, s, idx, n);
-  HIP_TRY(hipGetLastError());
-  mps_opts o{};
-  if (opts) o = *opts;
-  o.workspace = base;
-  o.workspace_bytes = L.total;
-  rc = run_sort(keys, kt, idx, nullptr, 1, n, &o, trace, s);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_gather64, dim3(g), dim3(256), 0, s, (const uint64_t *)payload,
-                     (const uint32_t *)idx, tmp, n);
-  hipLaunchKernelGGL(k_copy64, dim3(g), dim3(256), 0, s, (const uint64_t *)tmp, payload, n);
-  HIP_TRY(hipGetLastError());
-  if (!(opts && opts->workspace)) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 64) {
-      g_last_base[dev] = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(base) + 255) & ~(uintptr_t)255);
-    }
-  }
-  return MPS_OK;
+  // the merges carry the 8-byte payload with its key
+  return run_sort(keys, kt, reinterpret_cast<uint32_t *>(payload), nullptr, 1, n, opts, trace,
+                  (hipStream_t)stream, 8);
 }
 
 // ---------------------------------------------------------------- fixed scratch
@@ -790,7 +736,7 @@ extern "C" int mps_sort_noalloc(void *keys, mps_key_type kt, uint32_t *payload, 
   int rc = check_k(k);
   if (rc) return rc;
   Layout L;
-  if (!make_layout(n, 1, kt, payload != nullptr, k, L)) return fail(MPS_E_INVALID, "bad sizes");
+  if (!make_layout(n, 1, kt, payload ? 4 : 0, k, L)) return fail(MPS_E_INVALID, "bad sizes");
   if (L.total > kScratchBytes)
     return failf(MPS_E_NOMEM,
                  "this sort needs %llu bytes of workspace; the fixed scratch of mps_sort_noalloc "

@@ -123,6 +123,7 @@ struct Work {
   uint8_t *run_desc;                 // [rmax]
   int min_run;                       // 1: natural runs; 2..kMrMaxMinRun: extended runs
   int merge_down;                    // final phase of Appendix A.3 (single arrays)
+  int pay8;                          // the payload is 8 bytes per key (its pointers are cast)
   uint64_t *nat_start;               // [rmax+1] natural runs when min_run > 1 (single arrays)
   uint8_t *nat_desc;                 // [rmax]
   uint32_t *mr_first;                // [nch+1] first natural run at or after each chunk start

@@ -96,11 +96,11 @@ constexpr uint32_t kMkEnd = 1, kMkStart = 2, kMkOdd = 4;
 constexpr int kLeafPad = kLeafCap + kLeafCap / kLeafItems;
 __device__ inline int lph(int p) { return p + p / kLeafItems; }
 
-template <typename O, bool HV>
+template <typename O, bool HV, typename V>
 struct LeafSmem {
   O key[kLeafPad];                   // order keys
   uint32_t tag[kLeafPad];            // source positions; before the sort: the root list and marks
-  uint32_t val[HV ? kLeafCap : 1];   // payloads in source order
+  V val[HV ? kLeafCap : 1];          // payloads in source order
   uint16_t pinfo[kLeafCap + 2];      // piece table
   uint32_t wsum[kLeafThreads / 64];
   uint32_t misc[8];
@@ -147,10 +147,10 @@ __device__ inline uint32_t leaf_scan_excl(uint32_t v, uint32_t *wsum, uint32_t *
   return pre + incl - v;
 }
 
-template <int KT, bool HV>
+template <int KT, bool HV, typename V>
 __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
-    typename Key<KT>::U *__restrict__ keys, uint32_t *__restrict__ vals,
-    typename Key<KT>::U *__restrict__ akeys, uint32_t *__restrict__ avals, uint64_t N,
+    typename Key<KT>::U *__restrict__ keys, V *__restrict__ vals,
+    typename Key<KT>::U *__restrict__ akeys, V *__restrict__ avals, uint64_t N,
     const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
     const uint32_t *__restrict__ Rs, const uint8_t *__restrict__ sflag,
     const uint8_t *__restrict__ dist, const uint32_t *__restrict__ cfirst,
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
   constexpr int CAP = kLeafCap;
   constexpr int T = kLeafThreads;
   constexpr int E = kLeafItems;
-  __shared__ LeafSmem<O, HV> sm;
+  __shared__ LeafSmem<O, HV, V> sm;
   uint32_t *roots = sm.tag;                // fallback root list [kLeafChunk]
   uint32_t *mark = sm.tag + kLeafChunk;    // fallback marks [CAP / 4]
   const int t = threadIdx.x;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
       const int Tp = (Tt + E - 1) & ~(E - 1);
       // ---- source elements, coalesced
       U kr[E];
-      uint32_t vr[E];
+      V vr[E];
 #pragma unroll
       for (int q = 0; q < E; q++) {
         const int e = t + q * T;
@@ -428,20 +428,22 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
   }
 }
 
+template <int KT, bool HV, typename V>
+static void launch_leaf_v(void *keys, uint32_t *vals, const Work &w, unsigned g, hipStream_t s) {
+  using U = typename Key<KT>::U;
+  hipLaunchKernelGGL((k_leaf_pass<KT, HV, V>), dim3(g), dim3(kLeafThreads), 0, s, (U *)keys,
+                     (V *)vals, (U *)w.alt_keys, (V *)w.alt_vals, w.N, w.run_start, w.Ls, w.Rs,
+                     w.sflag, w.dist0, w.cfirst, w.croot, w.plan, w.samples);
+}
+
 template <int KT>
 static void launch_leaf_kt(void *keys, uint32_t *vals, const Work &w, hipStream_t s) {
-  using U = typename Key<KT>::U;
   const uint64_t nch = (w.N + kLeafChunk - 1) / kLeafChunk;
   const uint64_t nbatch = (nch + 63) / 64;
   const unsigned g = (unsigned)(nbatch < 8192 ? nbatch : 8192);
-  if (vals)
-    hipLaunchKernelGGL((k_leaf_pass<KT, true>), dim3(g), dim3(kLeafThreads), 0, s, (U *)keys, vals,
-                       (U *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.Ls, w.Rs, w.sflag,
-                       w.dist0, w.cfirst, w.croot, w.plan, w.samples);
-  else
-    hipLaunchKernelGGL((k_leaf_pass<KT, false>), dim3(g), dim3(kLeafThreads), 0, s, (U *)keys, vals,
-                       (U *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.Ls, w.Rs, w.sflag,
-                       w.dist0, w.cfirst, w.croot, w.plan, w.samples);
+  if (!vals) launch_leaf_v<KT, false, uint32_t>(keys, vals, w, g, s);
+  else if (w.pay8) launch_leaf_v<KT, true, uint64_t>(keys, vals, w, g, s);
+  else launch_leaf_v<KT, true, uint32_t>(keys, vals, w, g, s);
 }
 
 hipError_t launch_leaf(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s) {

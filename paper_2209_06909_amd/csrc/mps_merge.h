@@ -367,10 +367,10 @@ __global__ __launch_bounds__(256) void k_tile_desc(
 // The keys have 16 bytes of padding in front and behind: a lane's outputs are
 // written back 16 bytes at a time, and a search probe of an empty range may
 // read one element before or after the keys.
-template <typename O, int K, int TILE>
+template <typename O, int K, int TILE, int VB = 4>
 struct FastSmem {
   static constexpr size_t kKeyBytes = (size_t)(TILE + 4) * 8;
-  static constexpr size_t kBuf = kKeyBytes + (size_t)TILE * 4;
+  static constexpr size_t kBuf = kKeyBytes + (size_t)TILE * VB;
   static constexpr int kTabWords = (int)(sizeof(TileTab<K>) / 4);
   alignas(16) unsigned char bufA[kBuf];
   TileTab<K> tab[2];
@@ -379,12 +379,12 @@ struct FastSmem {
 
 // LDS of the general kernel (tiles spanning many small nodes): one tile buffer
 // (the stages merge in place) and the piece and slice tables.
-template <typename O, int K, int TILE, int THREADS>
+template <typename O, int K, int TILE, int THREADS, int VB = 4>
 struct GenSmem {
   static constexpr int kMaxSlices = TILE + 2 * K + 2;
   static constexpr int kMaxPieces = TILE / 2 + 4;
   static constexpr int kWaves = THREADS / 64;
-  static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + 4);
+  static constexpr size_t kBuf = (size_t)TILE * (sizeof(O) + VB);
   static constexpr size_t kAux = kBuf > (size_t)kMaxSlices * 8 ? kBuf : (size_t)kMaxSlices * 8;
   alignas(16) unsigned char bufA[kAux];   // the tile; holds the slices' global starts during setup
   uint64_t pc_out[kMaxPieces];
@@ -451,9 +451,9 @@ __device__ inline void addr_desc(uint64_t (&g)[E], const TileTab<K> &T, int t) {
   }
 }
 
-template <typename O, int E, bool HV>
-__device__ inline void issue_at(O (&kreg)[E], uint32_t (&vreg)[E], const O *in_keys,
-                                const uint32_t *in_vals, const uint64_t (&g)[E]) {
+template <typename O, typename V, int E, bool HV>
+__device__ inline void issue_at(O (&kreg)[E], V (&vreg)[E], const O *in_keys,
+                                const V *in_vals, const uint64_t (&g)[E]) {
 #pragma unroll
   for (int i = 0; i < E; i++) {
     kreg[i] = in_keys[g[i]];
@@ -461,9 +461,9 @@ __device__ inline void issue_at(O (&kreg)[E], uint32_t (&vreg)[E], const O *in_k
   }
 }
 
-template <typename Kt, typename O, int E, int THREADS>
-__device__ inline void commit_loads(const O (&kreg)[E], const uint32_t (&vreg)[E], O *kA,
-                                    uint32_t *vA, bool has_vals, int Tt, int t) {
+template <typename Kt, typename O, typename V, int E, int THREADS>
+__device__ inline void commit_loads(const O (&kreg)[E], const V (&vreg)[E], O *kA,
+                                    V *vA, bool has_vals, int Tt, int t) {
 #pragma unroll
   for (int i = 0; i < E; i++) {
     int e = t + i * THREADS;
@@ -479,8 +479,8 @@ __device__ inline void commit_loads(const O (&kreg)[E], const uint32_t (&vreg)[E
 // [t*E, t*E+E) into registers, unit by unit, and writes them back after a
 // barrier (every read of the stage done).  A lane's outputs may come from
 // several merge units; output q of the lane is selected into register q.
-template <typename O, int K, int TILE, int THREADS, bool HV>
-__device__ inline void merge_stages_gen(O *ks, uint32_t *vs, const uint16_t *sl_off,
+template <typename O, typename V, int K, int TILE, int THREADS, bool HV>
+__device__ inline void merge_stages_gen(O *ks, V *vs, const uint16_t *sl_off,
                                         const uint16_t *pos_sl, const uint16_t *sl_pc,
                                         const uint16_t *pc_sl, int Tt, int t) {
   constexpr int E = TILE / THREADS;
@@ -537,7 +537,7 @@ __device__ inline void merge_stages_gen(O *ks, uint32_t *vs, const uint16_t *sl_
         if (takeL) ka = kn; else kb = kn;
       }
     }
-    uint32_t pv[E];
+    V pv[E];
     if (HV) {
 #pragma unroll
       for (int i = 0; i < E; i++) pv[i] = vs[os[i]];
@@ -589,8 +589,8 @@ __device__ inline int lift_search(const O *a, const O *b, int lo, int hi) {
 // an unrolled E-step merge produce them.  Lanes spanning more units (only when
 // a unit is shorter than E) walk unit by unit.  The key buffer carries one element of padding,
 // so reading one past a unit is harmless.
-template <typename O, int K, int TILE, int THREADS, bool HV>
-__device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t *sl_off_l, int S,
+template <typename O, typename V, int K, int TILE, int THREADS, bool HV>
+__device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off_l, int S,
                                             const uint16_t *pc_sl_l, int P, int Tt, int t) {
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
@@ -725,7 +725,7 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
         }
       }
     }
-    uint32_t pv[E];
+    V pv[E];
     if (HV) {
 #pragma unroll
       for (int i = 0; i < E; i++) pv[i] = vs[os[i] / KS];
@@ -745,10 +745,20 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
           reinterpret_cast<u64x2 *>(ks + e0)[i] = v;
         }
         if (HV) {
+          if constexpr (sizeof(V) == 8) {
 #pragma unroll
-          for (int i = 0; i < E / 4; i++)
-            reinterpret_cast<uint4 *>(vs + e0)[i] =
-                make_uint4(pv[4 * i], pv[4 * i + 1], pv[4 * i + 2], pv[4 * i + 3]);
+            for (int i = 0; i < E / 2; i++) {
+              u64x2 v;
+              v.x = pv[2 * i];
+              v.y = pv[2 * i + 1];
+              reinterpret_cast<u64x2 *>(vs + e0)[i] = v;
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < E / 4; i++)
+              reinterpret_cast<uint4 *>(vs + e0)[i] =
+                  make_uint4(pv[4 * i], pv[4 * i + 1], pv[4 * i + 2], pv[4 * i + 3]);
+          }
         }
       } else {
 #pragma unroll
@@ -773,9 +783,9 @@ __device__ inline void merge_stages_inplace(O *ks, uint32_t *vs, const uint16_t 
 
 // Coalesced stores of a merged tile; outputs at multiples of kSampleStride also
 // refresh the co-rank sample of their position.
-template <typename Kt, typename O, int E, int THREADS>
-__device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
-                                  uint32_t *out_vals, bool has_vals, const uint16_t *pc_loff,
+template <typename Kt, typename O, typename V, int E, int THREADS>
+__device__ inline void store_tile(const O *ks, const V *vs, O *out_keys,
+                                  V *out_vals, bool has_vals, const uint16_t *pc_loff,
                                   const uint64_t *pc_out, const uint16_t *pos_sl,
                                   const uint16_t *sl_pc, int Tt, int t, uint64_t *smp) {
 #pragma unroll
@@ -795,8 +805,8 @@ __device__ inline void store_tile(const O *ks, const uint32_t *vs, O *out_keys,
 // of position e is base0 + e before the second piece and base1 + e from it on.
 // The base is chosen once per wave unless the piece split falls among the
 // wave's 64 positions.
-template <typename Kt, typename O, int E, int THREADS>
-__device__ inline void store_fast(const O *ks, const uint32_t *vs, O *out_keys, uint32_t *out_vals,
+template <typename Kt, typename O, typename V, int E, int THREADS>
+__device__ inline void store_fast(const O *ks, const V *vs, O *out_keys, V *out_vals,
                                   bool has_vals, const uint16_t *pc_loff, const uint64_t *pc_out,
                                   int P, int Tt, int t) {
   const int split = P == 2 ? (int)pc_loff[1] : Tt;
@@ -847,23 +857,23 @@ constexpr int kGenClaim = 4;
 // i+2 and the input slices of tile i+1 are already being fetched into
 // registers, so global latency overlaps the LDS work.  A tile's table is
 // copied to LDS by the lanes of the first wave, one word each.
-template <int KT, int K, int TILE, int THREADS, bool HV>
-// With 4-byte keys, k <= 4 and 4 outputs per lane the kernel fits in 64
-// registers, which lets 4 workgroups of 512 threads share a CU.
-__global__ __launch_bounds__(THREADS, (sizeof(typename Key<KT>::U) == 4 && K <= 4 && TILE == 4 * THREADS) ? 8 : 1)
+template <int KT, int K, int TILE, int THREADS, bool HV, typename V = uint32_t>
+// With 4-byte keys, 4-byte payloads, k <= 4 and 4 outputs per lane the kernel
+// fits in 64 registers, which lets 4 workgroups of 512 threads share a CU.
+__global__ __launch_bounds__(THREADS, (sizeof(typename Key<KT>::U) == 4 && sizeof(V) == 4 && K <= 4 && TILE == 4 * THREADS) ? 8 : 1)
 void k_merge_fast(
-    const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
-    typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
+    const typename Key<KT>::U *__restrict__ in_keys, const V *__restrict__ in_vals,
+    typename Key<KT>::U *__restrict__ out_keys, V *__restrict__ out_vals,
     Plan *__restrict__ plan, int level, const TileTab<K> *__restrict__ desc,
     uint64_t *__restrict__ smp) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
-  using SM = FastSmem<O, K, TILE>;
+  using SM = FastSmem<O, K, TILE, (int)sizeof(V)>;
   constexpr int E = TILE / THREADS;
   constexpr int NW = SM::kTabWords;
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA + 16);
-  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + SM::kKeyBytes);
+  V *vA = reinterpret_cast<V *>(sm.bufA + SM::kKeyBytes);
   const uint32_t *descw = reinterpret_cast<const uint32_t *>(desc);
 
   const uint64_t tiles = plan->lvl_tiles[level];
@@ -881,7 +891,7 @@ void k_merge_fast(
   if (tile >= tiles) return;
 
   O kreg[E];
-  uint32_t vreg[E];
+  V vreg[E];
   uint64_t ga[E];
   uint32_t dreg = 0;   // one word of a prefetched table (lanes 0..NW-1)
 
@@ -892,7 +902,7 @@ void k_merge_fast(
   if (t < NW && nxt < tiles) dreg = descw[nxt * NW + t];
   if (sm.tab[0].kind == kTabFast) {
     addr_desc<E, THREADS, K>(ga, sm.tab[0], t);
-    issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
+    issue_at<O, V, E, HV>(kreg, vreg, in_keys, in_vals, ga);
   }
   int cur = 0;
 
@@ -904,7 +914,7 @@ void k_merge_fast(
     TileTab<K> &T = sm.tab[cur];
     TileTab<K> &N = sm.tab[cur ^ 1];
     const int kind = T.kind;
-    if (kind == kTabFast) commit_loads<Kt, O, E, THREADS>(kreg, vreg, kA, vA, HV, T.Tt, t);
+    if (kind == kTabFast) commit_loads<Kt, O, V, E, THREADS>(kreg, vreg, kA, vA, HV, T.Tt, t);
     // next tile's table from its prefetched words (kTabNone past the end)
     if (t < NW) reinterpret_cast<uint32_t *>(&N)[t] = nxt < tiles ? dreg : 0u;
     if (t == 0 && reclaim) sm.claim[1] = claimed;
@@ -917,11 +927,11 @@ void k_merge_fast(
     if (t < NW && after < tiles) dreg = descw[after * NW + t];
     if (N.kind == kTabFast) {
       addr_desc<E, THREADS, K>(ga, N, t);
-      issue_at<O, E, HV>(kreg, vreg, in_keys, in_vals, ga);
+      issue_at<O, V, E, HV>(kreg, vreg, in_keys, in_vals, ga);
     }
     if (kind == kTabFast) {
-      merge_stages_inplace<O, K, TILE, THREADS, HV>(kA, vA, T.sl_off, T.S, T.pc_sl, T.P, T.Tt, t);
-      store_fast<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV, T.pc_loff, T.pc_out, T.P,
+      merge_stages_inplace<O, V, K, TILE, THREADS, HV>(kA, vA, T.sl_off, T.S, T.pc_sl, T.P, T.Tt, t);
+      store_fast<Kt, O, V, E, THREADS>(kA, vA, out_keys, out_vals, HV, T.pc_loff, T.pc_out, T.P,
                                     T.Tt, t);
       if (t >= THREADS - 64) store_samples<O>(kA, T.pc_loff, T.pc_out, T.P, T.Tt, lane, smp);
     } else if (kind == kTabBad) {
@@ -937,10 +947,10 @@ void k_merge_fast(
 // Tiles spanning many small nodes (listed by the descriptor kernel): piece
 // and slice tables are built from the node records, then the same staged
 // merge runs.  Not pipelined.
-template <int KT, int K, int TILE, int THREADS, bool HV>
+template <int KT, int K, int TILE, int THREADS, bool HV, typename V = uint32_t>
 __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
-    const typename Key<KT>::U *__restrict__ in_keys, const uint32_t *__restrict__ in_vals,
-    typename Key<KT>::U *__restrict__ out_keys, uint32_t *__restrict__ out_vals,
+    const typename Key<KT>::U *__restrict__ in_keys, const V *__restrict__ in_vals,
+    typename Key<KT>::U *__restrict__ out_keys, V *__restrict__ out_vals,
     const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
     const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
     const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
@@ -950,11 +960,11 @@ __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
     uint64_t *__restrict__ smp) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
-  using SM = GenSmem<O, K, TILE, THREADS>;
+  using SM = GenSmem<O, K, TILE, THREADS, (int)sizeof(V)>;
   constexpr int E = TILE / THREADS;
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA);
-  uint32_t *vA = reinterpret_cast<uint32_t *>(sm.bufA + (size_t)TILE * sizeof(O));
+  V *vA = reinterpret_cast<V *>(sm.bufA + (size_t)TILE * sizeof(O));
   uint64_t *sl_g = reinterpret_cast<uint64_t *>(sm.bufA);
 
   const uint32_t ngen = plan->gen_cnt[level];
@@ -1103,15 +1113,15 @@ __global__ __launch_bounds__(THREADS, K <= 4 ? 6 : 1) void k_merge_general(
           if (b0 + i < Tt) sm.pos_sl[b0 + i] = (uint16_t)(rv[i] > pre ? rv[i] : pre);
         lds_barrier();
         O k2[E];
-        uint32_t v2[E];
+        V v2[E];
         addr_table<E, THREADS>(ga, sm.pos_sl, sm.sl_off, sl_g, Tt, t);
-        issue_at<O, E, HV>(k2, v2, in_keys, in_vals, ga);
+        issue_at<O, V, E, HV>(k2, v2, in_keys, in_vals, ga);
         lds_barrier();   // the slice starts, kept in the tile buffer, are read
-        commit_loads<Kt, O, E, THREADS>(k2, v2, kA, vA, HV, Tt, t);
+        commit_loads<Kt, O, V, E, THREADS>(k2, v2, kA, vA, HV, Tt, t);
         lds_barrier();
-        merge_stages_gen<O, K, TILE, THREADS, HV>(kA, vA, sm.sl_off, sm.pos_sl, sm.sl_pc,
-                                                  sm.pc_sl, Tt, t);
-        store_tile<Kt, O, E, THREADS>(kA, vA, out_keys, out_vals, HV, sm.pc_loff, sm.pc_out,
+        merge_stages_gen<O, V, K, TILE, THREADS, HV>(kA, vA, sm.sl_off, sm.pos_sl, sm.sl_pc,
+                                                     sm.pc_sl, Tt, t);
+        store_tile<Kt, O, V, E, THREADS>(kA, vA, out_keys, out_vals, HV, sm.pc_loff, sm.pc_out,
                                       sm.pos_sl, sm.sl_pc, Tt, t, smp);
       }
     }
@@ -1149,36 +1159,35 @@ inline unsigned fill_grid(const void *kernel, int threads, unsigned fallback) {
   return g;
 }
 
+template <int KT, int K, int TILE, int THREADS, bool HV, typename V>
+void launch_merges_v(const LevelArgs &a, const Work &w, const uint32_t *tj,
+                     const uint64_t *tile_base, int level, hipStream_t s) {
+  using U = typename Key<KT>::U;
+  const TileTab<K> *desc = reinterpret_cast<const TileTab<K> *>(w.tile_desc);
+  auto kf = k_merge_fast<KT, K, TILE, THREADS, HV, V>;
+  auto kg = k_merge_general<KT, K, TILE, THREADS, HV, V>;
+  unsigned gf = fill_grid((const void *)kf, THREADS, 1024);
+  unsigned gg = fill_grid((const void *)kg, THREADS, 1024);
+  const V *iv = reinterpret_cast<const V *>(a.in_vals);
+  V *ov = reinterpret_cast<V *>(a.out_vals);
+  hipLaunchKernelGGL(kf, dim3(gf), dim3(THREADS), 0, s, (const U *)a.in_keys, iv, (U *)a.out_keys,
+                     ov, w.plan, level, desc, w.samples);
+  hipLaunchKernelGGL(kg, dim3(gg), dim3(THREADS), 0, s, (const U *)a.in_keys, iv, (U *)a.out_keys,
+                     ov, w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
+                     tile_base, w.plan, level, w.corank, w.gen_list, w.samples);
+}
+
 // The two merge launches of one level (descriptor tiles, then general tiles)
-// for one tile configuration.
+// for one tile configuration; the payload is absent, 4 or 8 bytes per key.
 template <int KT, int K, int TILE, int THREADS>
 void launch_merges_kt(const LevelArgs &a, const Work &w, const uint32_t *tj,
                       const uint64_t *tile_base, int level, hipStream_t s) {
-  using U = typename Key<KT>::U;
-  const TileTab<K> *desc = reinterpret_cast<const TileTab<K> *>(w.tile_desc);
-  if (a.in_vals) {
-    auto kf = k_merge_fast<KT, K, TILE, THREADS, true>;
-    auto kg = k_merge_general<KT, K, TILE, THREADS, true>;
-    unsigned gf = fill_grid((const void *)kf, THREADS, 1024);
-    unsigned gg = fill_grid((const void *)kg, THREADS, 1024);
-    hipLaunchKernelGGL(kf, dim3(gf), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.plan, level, desc, w.samples);
-    hipLaunchKernelGGL(kg, dim3(gg), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
-                       w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
-                       w.gen_list, w.samples);
-  } else {
-    auto kf = k_merge_fast<KT, K, TILE, THREADS, false>;
-    auto kg = k_merge_general<KT, K, TILE, THREADS, false>;
-    unsigned gf = fill_grid((const void *)kf, THREADS, 1024);
-    unsigned gg = fill_grid((const void *)kg, THREADS, 1024);
-    hipLaunchKernelGGL(kf, dim3(gf), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.plan, level, desc, w.samples);
-    hipLaunchKernelGGL(kg, dim3(gg), dim3(THREADS), 0, s, (const U *)a.in_keys, a.in_vals,
-                       (U *)a.out_keys, a.out_vals, w.run_start, w.Ls, w.Rs, w.nd_mem,
-                       w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level, w.corank,
-                       w.gen_list, w.samples);
-  }
+  if (!a.in_vals)
+    launch_merges_v<KT, K, TILE, THREADS, false, uint32_t>(a, w, tj, tile_base, level, s);
+  else if (w.pay8)
+    launch_merges_v<KT, K, TILE, THREADS, true, uint64_t>(a, w, tj, tile_base, level, s);
+  else
+    launch_merges_v<KT, K, TILE, THREADS, true, uint32_t>(a, w, tj, tile_base, level, s);
 }
 
 template <int TILE, int THREADS>

@@ -39,11 +39,11 @@ __device__ inline uint64_t run_of(const uint64_t *rs, uint64_t lo, uint64_t hi, 
 // Positions of a block that is not one ascending run: each finds its run in
 // the staged table and acts on it, in two halves of kPlaceE/2 positions per
 // thread.
-template <int KT>
+template <int KT, typename V>
 __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
-                                     uint32_t *__restrict__ vals,
+                                     V *__restrict__ vals,
                                      typename Key<KT>::U *__restrict__ akeys,
-                                     uint32_t *__restrict__ avals, uint64_t *__restrict__ smp,
+                                     V *__restrict__ avals, uint64_t *__restrict__ smp,
                                      const uint64_t *sRs, const uint8_t *sFl, int nr, uint64_t bs,
                                      uint64_t be, int t) {
   using U = typename Key<KT>::U;
@@ -77,7 +77,7 @@ __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
       }
     }
     U ka[HE], kb[HE];
-    uint32_t va[HE], vb[HE];
+    V va[HE], vb[HE];
 #pragma unroll
     for (int i = 0; i < HE; i++) {
       const uint64_t e = bs + t + (uint64_t)(h * HE + i) * T;
@@ -124,11 +124,11 @@ __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
 // by the threads of their first half, each swapping with its mirror position.
 // A block overlapping more than kPlaceThreads runs stages all of them (at most
 // one per position) in a second round.
-template <int KT>
+template <int KT, typename V>
 __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__restrict__ keys,
-                                                         uint32_t *__restrict__ vals,
+                                                         V *__restrict__ vals,
                                                          typename Key<KT>::U *__restrict__ akeys,
-                                                         uint32_t *__restrict__ avals, uint64_t N,
+                                                         V *__restrict__ avals, uint64_t N,
                                                          const uint64_t *__restrict__ rs,
                                                          const uint8_t *__restrict__ desc,
                                                          const uint8_t *__restrict__ leaf_depth,
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
       const U *ks = keys + bs;
       U *kd = akeys + bs;
       U kv[kPlaceE];
-      uint32_t vv[kPlaceE];
+      V vv[kPlaceE];
 #pragma unroll
       for (int i = 0; i < kPlaceE; i++) {
         const int o = t + i * T;
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
       // inside a small subtree) have nothing to move
       bool mine = false;
       for (int x = t; x < nr; x += T) mine = mine || sFl[x] != 0;
-      if (__syncthreads_or(mine)) place_general<KT>(keys, vals, akeys, avals, smp, sRs, sFl, nr, bs, be, t);
+      if (__syncthreads_or(mine)) place_general<KT, V>(keys, vals, akeys, avals, smp, sRs, sFl, nr, bs, be, t);
     }
     jc = jn;
     __syncthreads();   // the run table is restaged for the next block
@@ -219,22 +219,27 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
 }
 
 // ---------------------------------------------------------------- host side
+template <int KT, typename V>
+static void launch_place_v(void *keys, void *vals, const Work &w, unsigned g, hipStream_t s) {
+  using U = typename Key<KT>::U;
+  hipLaunchKernelGGL((k_place<KT, V>), dim3(g), dim3(kPlaceThreads), 0, s, (U *)keys, (V *)vals,
+                     (U *)w.alt_keys, (V *)w.alt_vals, w.N, w.run_start, w.run_desc, w.leaf_depth,
+                     w.plan, w.samples);
+}
+
+template <int KT>
+static void launch_place_kt(void *keys, uint32_t *vals, const Work &w, unsigned g, hipStream_t s) {
+  if (vals && w.pay8) launch_place_v<KT, uint64_t>(keys, vals, w, g, s);
+  else launch_place_v<KT, uint32_t>(keys, vals, w, g, s);
+}
+
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s) {
   uint64_t nblk = (w.N + kPlaceBlock - 1) / kPlaceBlock;
   unsigned g = (unsigned)(nblk < 8192 ? nblk : 8192);
   if (g == 0) return hipSuccess;
-  if (kt == 1)
-    hipLaunchKernelGGL(k_place<1>, dim3(g), dim3(kPlaceThreads), 0, s, (uint64_t *)keys, vals,
-                       (uint64_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
-                       w.leaf_depth, w.plan, w.samples);
-  else if (kt == 2)
-    hipLaunchKernelGGL(k_place<2>, dim3(g), dim3(kPlaceThreads), 0, s, (uint32_t *)keys, vals,
-                       (uint32_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
-                       w.leaf_depth, w.plan, w.samples);
-  else
-    hipLaunchKernelGGL(k_place<0>, dim3(g), dim3(kPlaceThreads), 0, s, (uint32_t *)keys, vals,
-                       (uint32_t *)w.alt_keys, w.alt_vals, w.N, w.run_start, w.run_desc,
-                       w.leaf_depth, w.plan, w.samples);
+  if (kt == 1) launch_place_kt<1>(keys, vals, w, g, s);
+  else if (kt == 2) launch_place_kt<2>(keys, vals, w, g, s);
+  else launch_place_kt<0>(keys, vals, w, g, s);
   return hipGetLastError();
 }
 

@@ -447,10 +447,10 @@ __global__ __launch_bounds__(kMrThreads) void k_mr_emit(
 // strictly decreasing; an extended one is neither) are left alone.  Each
 // element's place is the number of elements that are smaller, or equal and
 // earlier: the order a stable insertion sort gives.
-template <typename U, int W, typename Load, typename Store>
+template <typename U, typename V, int W, typename Load, typename Store>
 __device__ inline void rank_sort_run(uint32_t len, Load ld, Store st) {
   U k[W];
-  uint32_t v[W];
+  V v[W];
 #pragma unroll
   for (int i = 0; i < W; i++) {
     k[i] = (U)~(U)0;
@@ -489,9 +489,9 @@ __device__ inline void rank_sort_run(uint32_t len, Load ld, Store st) {
 // coalesced (positions that carry a co-rank sample refresh it).  A longer
 // span (a long natural run among them) is handled run by run straight from
 // memory.
-template <int KT, int W>
+template <int KT, int W, typename V>
 __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__restrict__ keys,
-                                                         uint32_t *__restrict__ vals,
+                                                         V *__restrict__ vals,
                                                          const uint64_t *__restrict__ rs,
                                                          const uint8_t *__restrict__ leaf_depth,
                                                          const Plan *__restrict__ plan,
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__
   constexpr uint64_t SM = kSampleStride - 1;
   constexpr uint32_t kCap = kMrSortRuns * W;
   __shared__ U sk[kCap];
-  __shared__ uint32_t sv[kCap];
+  __shared__ V sv[kCap];
   const int t = threadIdx.x;
   const uint64_t r = plan->r;
   for (uint64_t j0 = (uint64_t)blockIdx.x * kMrSortRuns; j0 < r;
@@ -525,13 +525,13 @@ __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__
       __syncthreads();
       if (mine) {
         const uint32_t o = (uint32_t)(s - S0);
-        rank_sort_run<U, W>(
+        rank_sort_run<U, V, W>(
             len,
-            [&](int i, U &kk, uint32_t &vv) {
+            [&](int i, U &kk, V &vv) {
               kk = sk[o + i];
               if (vals) vv = sv[o + i];
             },
-            [&](uint32_t rank, U kk, uint32_t vv) {
+            [&](uint32_t rank, U kk, V vv) {
               sk[o + rank] = kk;
               if (vals) sv[o + rank] = vv;
             });
@@ -545,13 +545,13 @@ __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__
       }
       __syncthreads();
     } else if (mine) {
-      rank_sort_run<U, W>(
+      rank_sort_run<U, V, W>(
           len,
-          [&](int i, U &kk, uint32_t &vv) {
+          [&](int i, U &kk, V &vv) {
             kk = Key<KT>::ord(keys[s + i]);
             if (vals) vv = vals[s + i];
           },
-          [&](uint32_t rank, U kk, uint32_t vv) {
+          [&](uint32_t rank, U kk, V vv) {
             const uint64_t dst = s + rank;
             keys[dst] = Key<KT>::unord(kk);
             if (vals) vals[dst] = vv;
@@ -561,14 +561,21 @@ __global__ __launch_bounds__(kMrSortRuns) void k_mr_sort(typename Key<KT>::U *__
   }
 }
 
+template <int W, typename V>
+void launch_mr_sort_v(int kt, void *keys, V *vals, const Work &w, uint32_t m, unsigned gs,
+                      hipStream_t s) {
+  switch (kt) {
+    case 0: hipLaunchKernelGGL((k_mr_sort<0, W, V>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
+    case 1: hipLaunchKernelGGL((k_mr_sort<1, W, V>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint64_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
+    default: hipLaunchKernelGGL((k_mr_sort<2, W, V>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
+  }
+}
+
 template <int W>
 hipError_t launch_mr_sort(int kt, void *keys, uint32_t *vals, const Work &w, uint32_t m,
                           unsigned gs, hipStream_t s) {
-  switch (kt) {
-    case 0: hipLaunchKernelGGL((k_mr_sort<0, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
-    case 1: hipLaunchKernelGGL((k_mr_sort<1, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint64_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
-    default: hipLaunchKernelGGL((k_mr_sort<2, W>), dim3(gs), dim3(kMrSortRuns), 0, s, (uint32_t *)keys, vals, w.run_start, w.leaf_depth, w.plan, m, w.samples); break;
-  }
+  if (vals && w.pay8) launch_mr_sort_v<W, uint64_t>(kt, keys, reinterpret_cast<uint64_t *>(vals), w, m, gs, s);
+  else launch_mr_sort_v<W, uint32_t>(kt, keys, vals, w, m, gs, s);
   return hipGetLastError();
 }
 

@@ -42,6 +42,11 @@ def check_records(keys, pay64, k=4, min_run=1):
     assert np.array_equal(bits(kd.cpu().numpy()), bits(ok))
     assert np.array_equal(pd.cpu().numpy(), pay64[op.astype(np.int64)])
     check_trace(tr, ot)
+    kd, pd = to_dev(keys), to_dev(pay64)      # without a trace, as the benchmark runs it
+    mps.sort(kd, pd, k=k, min_run=min_run)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits(kd.cpu().numpy()), bits(ok))
+    assert np.array_equal(pd.cpu().numpy(), pay64[op.astype(np.int64)])
 
 
 CASES = [("runs_i64", (1 << 17) + 3), ("perm_i64", (1 << 16) + 5), ("ties_i32", (1 << 17) + 1),
