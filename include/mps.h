@@ -167,7 +167,7 @@ int mps_sort_ex(void *keys, mps_key_type kt, uint32_t *payload, uint64_t n,
  * process ends.  The call allocates nothing: no hipMalloc / hipFree, no HIP
  * events, streams or graphs, no host memory.
  *  - Limit: mps_workspace_bytes(n, 1, kt, payload != NULL, k) must not exceed
- *    the scratch (about 1.38M int64 or 1.5M int32/float32 keys with a u32
+ *    the scratch (about 2.2M int64 or 1.9M int32/float32 keys with a u32
  *    payload at k = 4); larger sorts return MPS_E_NOMEM before any work is
  *    enqueued.
  *  - opts may be NULL.  opts->workspace must be NULL (MPS_E_INVALID);

@@ -100,8 +100,9 @@ struct Layout {
       dist0, dist1, leaf_depth, sflag, cfirst, croot, lvl_cnt, lvl_car, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
       tj, samples, plan, nat_start, nat_desc, mr_first, mr_nxt, mr_cnt, mr_gnxt, mr_gcnt,
       mr_gentry, mr_goff, mr_centry, mr_coff;
-  uint64_t rmax, nbb, tiles_max, tj_cap;
+  uint64_t rmax, nbb, tiles_max, tj_cap, lvl_cap;
   int levels;
+  bool tree_tmp_in_alt;   // Le, Re, jump0/1, dist1 share the ping-pong buffer's bytes
 };
 
 size_t take(size_t &cur, size_t bytes) {
@@ -121,9 +122,15 @@ int levels_for(uint64_t n, uint32_t k) {
   return p < 1 ? 1 : p;
 }
 
-// Bytes after a sort's workspace for records with an 8-byte payload: the u32
-// record indices and the gather buffer, each 256-byte aligned.
-
+// The ping-pong buffer (alt_keys, alt_vals) is first written by placement,
+// after the tree is built.  Until then its bytes hold, when they fit, arrays
+// that die earlier: the natural runs of a minimal-run-length sort (dead once
+// the extended runs are made) and then the tree's scratch -- the nearest
+// smaller-or-equal boundaries Le / Re and the pointer-jumping buffers -- (dead
+// once the level lists and leaf depths are built; a trace fetched later
+// rebuilds them from the powers).  The level lists hold only nodes spanning
+// more than kSmallSpan elements: nodes of one depth are disjoint, so at most
+// N / (kSmallSpan + 1) per depth.
 bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) {
   if (N == 0 || m == 0) return false;
   size_t ks = kt == MPS_I64 ? 8 : 4;
@@ -135,10 +142,38 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
   uint64_t tiles_max = N / kTileMin + 2;   // enough for every tile configuration
   int levels = levels_for(N, k);
   if (levels >= kMaxLevels) return false;
+  uint64_t lvl_cap = (uint64_t)levels * (N / (kSmallSpan + 1) + m) + 2;
+  if (lvl_cap > rmax) lvl_cap = rmax;
   size_t c = 0;
   L.plan = take(c, sizeof(Plan));    // first: a later trace fetch finds it at the base
   L.alt_keys = take(c, N * ks);
   L.alt_vals = take(c, N * (uint64_t)pb);   // pb: payload bytes per key (0, 4 or 8)
+  const size_t alt_end = c;
+  // the tree's scratch inside the ping-pong buffer if it fits there
+  {
+    size_t t = L.alt_keys;
+    const size_t le = take(t, (rmax + 1) * 4), re = take(t, (rmax + 1) * 4);
+    const size_t j0 = take(t, (rmax + 1) * 4), j1 = take(t, (rmax + 1) * 4);
+    const size_t d1 = take(t, rmax + 1);
+    L.tree_tmp_in_alt = t <= alt_end;
+    if (L.tree_tmp_in_alt) {
+      L.Le = le;
+      L.Re = re;
+      L.jump0 = j0;
+      L.jump1 = j1;
+      L.dist1 = d1;
+    }
+  }
+  bool nat_in_alt = false;
+  if (m == 1) {
+    size_t t = L.alt_keys;
+    const size_t ns = take(t, (rmax + 1) * 8), nd = take(t, rmax);
+    nat_in_alt = t <= alt_end;
+    if (nat_in_alt) {
+      L.nat_start = ns;
+      L.nat_desc = nd;
+    }
+  }
   L.seg_off = take(c, 16);
   L.seg_bits = take(c, m > 1 ? nwords * 8 + 8 : 0);
   L.dbits = take(c, nwords * 8 + 8);
@@ -156,14 +191,18 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
   L.ansv_tr = take(c, (nbb / 1024 + 1) * kVMax * 4);
   L.Ls = take(c, (rmax + 1) * 4);
   L.Rs = take(c, (rmax + 1) * 4);
-  L.Le = take(c, (rmax + 1) * 4);
-  L.Re = take(c, (rmax + 1) * 4);
+  if (!L.tree_tmp_in_alt) {
+    L.Le = take(c, (rmax + 1) * 4);
+    L.Re = take(c, (rmax + 1) * 4);
+  }
   L.nd_arity = take(c, rmax + 1);
   L.nd_mem = take(c, (rmax + 1) * (k - 1) * 4);
-  L.jump0 = take(c, (rmax + 1) * 4);
-  L.jump1 = take(c, (rmax + 1) * 4);
+  if (!L.tree_tmp_in_alt) {
+    L.jump0 = take(c, (rmax + 1) * 4);
+    L.jump1 = take(c, (rmax + 1) * 4);
+  }
   L.dist0 = take(c, rmax + 1);
-  L.dist1 = take(c, rmax + 1);
+  if (!L.tree_tmp_in_alt) L.dist1 = take(c, rmax + 1);
   L.leaf_depth = take(c, rmax);
   L.sflag = take(c, rmax + 17);   // read 16 flags at a time
   L.cfirst = take(c, (N / kLeafChunk + 2) * 4);
@@ -171,9 +210,9 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
   L.lvl_cnt = take(c, nbb * kMaxLevels * 4);
   L.lvl_car = take(c, (nbb / 1024 + 1) * kMaxLevels * 4);
   L.lvl_tot = take(c, kMaxLevels * 8);
-  L.lvl_list = take(c, rmax * 4);
-  L.lvl_np = take(c, (rmax + 2) * 8);
-  L.scan_tmp = take(c, (rmax / 1024 + 2) * 8);
+  L.lvl_list = take(c, lvl_cap * 4);
+  L.lvl_np = take(c, (lvl_cap + 2) * 8);
+  L.scan_tmp = take(c, (lvl_cap / 1024 + 2) * 8);
   L.corank = take(c, tiles_max * k * 4);
   L.tile_desc = take(c, tiles_max * kTileDescBytes);
   L.gen_list = take(c, tiles_max * 4);
@@ -185,8 +224,10 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
   // and the chunk maps that turn them into extended runs
   const uint64_t nch = m == 1 ? (N + kMrChunk - 1) / kMrChunk : 0;
   const uint64_t ng = (nch + kMrGroup - 1) / kMrGroup;
-  L.nat_start = take(c, m == 1 ? (rmax + 1) * 8 : 0);
-  L.nat_desc = take(c, m == 1 ? rmax : 0);
+  if (!nat_in_alt) {
+    L.nat_start = take(c, m == 1 ? (rmax + 1) * 8 : 0);
+    L.nat_desc = take(c, m == 1 ? rmax : 0);
+  }
   L.mr_first = take(c, (nch + 1) * 4);
   L.mr_nxt = take(c, nch * kMrCand);
   L.mr_cnt = take(c, nch * kMrCand * 2);
@@ -200,6 +241,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
   L.rmax = rmax;
   L.nbb = nbb;
   L.tiles_max = tiles_max;
+  L.lvl_cap = lvl_cap;
   L.levels = levels;
   return true;
 }
@@ -343,6 +385,7 @@ void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uin
   w.lvl_cnt = at<uint32_t>(base, L.lvl_cnt);
   w.lvl_car = at<uint32_t>(base, L.lvl_car);
   w.lvl_list = at<uint32_t>(base, L.lvl_list);
+  w.lvl_cap = L.lvl_cap;
   w.lvl_np = at<uint64_t>(base, L.lvl_np);
   w.scan_tmp = at<uint64_t>(base, L.scan_tmp);
   w.corank = at<uint32_t>(base, L.corank);
@@ -359,18 +402,21 @@ int fill_trace(void *base, mps_trace *tr) {
   HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
   if (plan.error)
     return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", plan.error);
-  if (plan.lean && plan.n >= 2) {
-    // the sort left the insides of its small subtrees out: build them now
+  if (plan.n >= 2 && plan.r > 1) {
     Layout L;
     if (!make_layout(plan.n, plan.m, (int)plan.kt, (int)plan.has_payload, plan.k, L))
       return fail(MPS_E_DEVICE, "workspace header does not describe a layout");
-    Work w{};
-    bind_work(w, base, L, plan.n, plan.m, plan.k, 0, 0, (int)plan.has_payload, nullptr);
-    HIP_TRY(launch_tree_complete(w, nullptr));
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
-    if (plan.error)
-      return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", plan.error);
+    if (plan.lean || L.tree_tmp_in_alt) {
+      // the merges reused the tree's scratch, or the sort left the insides of
+      // its small subtrees out: rebuild them from the powers
+      Work w{};
+      bind_work(w, base, L, plan.n, plan.m, plan.k, 0, 0, (int)plan.has_payload, nullptr);
+      HIP_TRY(launch_tree_complete(w, plan.lean != 0, (unsigned)(L.nbb < 4096 ? L.nbb : 4096), nullptr));
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipMemcpy(&plan, base, sizeof(Plan), hipMemcpyDeviceToHost));
+      if (plan.error)
+        return failf(MPS_E_DEVICE, "device-side consistency check failed (error word 0x%x)", plan.error);
+    }
   }
   tr->r = plan.r;
   tr->n_nodes = plan.n_nodes;

@@ -147,8 +147,9 @@ struct Work {
   uint32_t *croot;                   // [(N/kLeafChunk + 2) * kChunkRec] small roots starting in each chunk
   uint32_t *lvl_cnt;                 // [nbb * kMaxLevels]
   uint32_t *lvl_car;                 // [(nbb / 1024 + 1) * kMaxLevels] carries per chunk of 1024 blocks
-  uint32_t *lvl_list;                // [rmax]
-  uint64_t *lvl_np;                  // [rmax+1] exclusive prefix of node sizes
+  uint32_t *lvl_list;                // [lvl_cap] nodes spanning more than kSmallSpan, by depth
+  uint64_t lvl_cap;
+  uint64_t *lvl_np;                  // [lvl_cap+2] exclusive prefix of node sizes
   uint64_t *scan_tmp;                // [nbb + 1024]
   uint32_t *corank;                  // [(N/tile + 2) * k]
   void *tile_desc;                   // [(N/tile + 2)] per-tile merge descriptors
@@ -247,7 +248,10 @@ hipError_t launch_detect(int kt, const void *keys, const Work &w, hipStream_t s)
 // the sort is fetched.
 hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t *tile_base,
                        uint32_t *tj, unsigned grid_blocks, hipStream_t s);
-hipError_t launch_tree_complete(const Work &w, hipStream_t s);
+// Rebuilds Ls / Rs / Le / Re from the powers (the merges may have reused the
+// bytes of Le / Re); with nodes, also every node record, depth and leaf depth
+// and the merge cost of a tree built without want_cost.
+hipError_t launch_tree_complete(const Work &w, bool nodes, unsigned grid_blocks, hipStream_t s);
 hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipStream_t s);
 // The small-subtree pass: every maximal subtree of span <= kSmallSpan is
 // finished in LDS, from the runs in keys / vals (buffer 0) to the buffer of

@@ -617,7 +617,8 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_carry(const Plan *__restri
   if (t == 0) totals[d] = carry;
 }
 
-__global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals, int full) {
+__global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals, int full,
+                           uint64_t cap) {
   if (threadIdx.x != 0) return;
   uint64_t acc = 0;
   uint32_t nl = 0;
@@ -625,6 +626,12 @@ __global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals, int 
     plan->lvl_begin[d] = acc;
     acc += totals[d];
     if (totals[d]) nl = d + 1;
+  }
+  if (acc > cap) {   // never expected: the lists are sized by a bound on such nodes
+    atomicOr(&plan->error, 4096u);
+    acc = 0;
+    nl = 0;
+    for (int d = 0; d < kMaxLevels; d++) plan->lvl_begin[d] = 0;
   }
   plan->lvl_begin[kMaxLevels] = acc;
   // the level lists hold the nodes above the small subtrees; the small ones
@@ -638,7 +645,7 @@ __global__ void k_lvl_plan(Plan *plan, const uint64_t *__restrict__ totals, int 
 __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
     const uint8_t *__restrict__ dist, const uint8_t *__restrict__ sflag,
     const Plan *__restrict__ plan, const uint32_t *__restrict__ cnt,
-    const uint32_t *__restrict__ car, uint32_t *__restrict__ list) {
+    const uint32_t *__restrict__ car, uint64_t cap, uint32_t *__restrict__ list) {
   __shared__ uint32_t sw[kTreeWaves][kMaxLevels];
   const uint64_t r = plan->r;
   const uint64_t nbb = (r + 1 + kTreeThreads - 1) / kTreeThreads;
@@ -667,7 +674,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_lvl_scatter(
     if (lead) {
       uint64_t pos = plan->lvl_begin[myd] + car[(b / kTreeThreads) * kMaxLevels + myd] +
                      cnt[b * kMaxLevels + myd] + sw[w][myd] + rank;
-      list[pos] = (uint32_t)i;
+      if (pos < cap) list[pos] = (uint32_t)i;
     }
     __syncthreads();
   }
@@ -866,8 +873,8 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
     hipLaunchKernelGGL(k_lvl_scan, dim3(gx, kMaxLevels), dim3(kTreeThreads), 0, s, w.lvl_cnt, w.plan, w.lvl_car);
     hipLaunchKernelGGL(k_lvl_carry, dim3(kMaxLevels), dim3(kTreeThreads), 0, s, w.plan, w.lvl_car, lvl_tot);
   }
-  hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot, full ? 1 : 0);
-  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_car, w.lvl_list);
+  hipLaunchKernelGGL(k_lvl_plan, dim3(1), dim3(64), 0, s, w.plan, lvl_tot, full ? 1 : 0, w.lvl_cap);
+  hipLaunchKernelGGL(k_lvl_scatter, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt, w.lvl_car, w.lvl_cap, w.lvl_list);
   hipLaunchKernelGGL(k_node_sizes, g256, b256, 0, s, w.lvl_list, w.Ls, w.Rs, w.run_start, w.plan, w.lvl_np);
   hipLaunchKernelGGL(k_scan_sums, dim3(1024), dim3(kScanBlk), 0, s, w.lvl_np, w.plan, w.scan_tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlk), 0, s, w.scan_tmp, w.plan);
@@ -877,12 +884,17 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   return hipGetLastError();
 }
 
-// Rebuilds every node record, depth and leaf depth of the last sort's tree
-// (built without FULL), and its merge cost, from its powers, nearest-smaller
-// arrays and runs, all still in the workspace; the sort's output is not
-// touched.
-hipError_t launch_tree_complete(const Work &w, hipStream_t s) {
+// After a sort, for its trace: the nearest smaller values again from the
+// powers (the merges may have reused the bytes of Le / Re; Ls / Rs come out
+// the same), and with nodes every node record, depth and leaf depth and the
+// merge cost of a tree built without FULL, from the powers and runs still in
+// the workspace.  The sort's output is not touched.
+hipError_t launch_tree_complete(const Work &w, bool nodes, unsigned gtree, hipStream_t s) {
   const dim3 g256(8192), b256(256);
+  hipLaunchKernelGGL(k_ansv_block, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_bl, w.ansv_bf);
+  launch_ansv_carries(w, s);
+  hipLaunchKernelGGL(k_ansv_final, dim3(gtree), dim3(kTreeThreads), 0, s, w.power, w.plan, w.ansv_cl, w.ansv_cr, w.ansv_tl, w.ansv_tr, w.Ls, w.Rs, w.Le, w.Re);
+  if (!nodes) return hipGetLastError();
   hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, w.plan);
   hipLaunchKernelGGL(k_nodes<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
   for (int round = 0; round < 6; round++) {

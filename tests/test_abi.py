@@ -28,14 +28,19 @@ def test_library_exports_every_declared_symbol():
 
 def test_workspace_bytes_host_logic():
     lib = mps.lib()
-    a = lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 1, 4)
-    b = lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I64, 1, 4)
-    c = lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 0, 4)
-    assert a > 0 and b > a and c < a
-    assert lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 1, 3) == 0   # k must be 2, 4 or 8
-    assert lib.mps_workspace_bytes(1 << 20, 1, 7, 1, 4) == 0             # unknown key type
+    n = 1 << 20
+    a = lib.mps_workspace_bytes(n, 1, mps.KEY_I32, 1, 4)
+    b = lib.mps_workspace_bytes(n, 1, mps.KEY_I64, 1, 4)
+    c = lib.mps_workspace_bytes(n, 1, mps.KEY_I32, 0, 4)
+    d = lib.mps_workspace_bytes(n, 1, mps.KEY_I64, 2, 4)
+    assert lib.mps_workspace_bytes(n, 1, mps.KEY_I32, 1, 3) == 0   # k must be 2, 4 or 8
+    assert lib.mps_workspace_bytes(n, 1, 7, 1, 4) == 0             # unknown key type
+    assert lib.mps_workspace_bytes(n, 2, mps.KEY_I64, 2, 4) == 0   # 8-byte payloads: single arrays
     # the ping-pong buffer alone is n*(key+payload) bytes
-    assert b >= (1 << 20) * 12
+    assert a >= n * 8 and b >= n * 12 and c >= n * 4 and d >= n * 16
+    # the tree's scratch shares the ping-pong buffer where it fits: an int64 key
+    # with a u32 payload needs at most 32 bytes per key
+    assert lib.mps_workspace_bytes(1 << 24, 1, mps.KEY_I64, 1, 4) <= 32 * (1 << 24)
 
 
 def test_argument_errors_need_no_gpu():
@@ -87,9 +92,13 @@ def test_min_run_argument_errors_need_no_gpu():
     assert b"MERGE_DOWN" in lib.mps_last_error()
     opts = mps._Opts(k=4, min_run=24)                                      # n <= 1: a no-op
     assert lib.mps_sort_ex(fake, mps.KEY_I64, None, 1, ctypes.byref(opts), None, None) == 0
-    # a single-array workspace has room for the natural runs and chunk maps
+    # a single-array workspace has room for the natural runs and chunk maps: apart
+    # when they do not fit in the ping-pong buffer (4-byte keys, no payload) ...
+    assert (lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I32, 0, 4)
+            > lib.mps_workspace_bytes(1 << 20, 2, mps.KEY_I32, 0, 4) + 8 * (1 << 19))
+    # ... and inside it when they do (int64 keys with a payload)
     assert (lib.mps_workspace_bytes(1 << 20, 1, mps.KEY_I64, 1, 4)
-            > lib.mps_workspace_bytes(1 << 20, 2, mps.KEY_I64, 1, 4) + 8 * (1 << 19))
+            < lib.mps_workspace_bytes(1 << 20, 2, mps.KEY_I64, 1, 4) + 8 * (1 << 19))
 
 
 def test_serve_host_selftest():
