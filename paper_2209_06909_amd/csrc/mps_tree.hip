@@ -87,6 +87,19 @@ __device__ inline void wave_masks(const uint8_t *__restrict__ P, uint64_t r, uin
   }
 }
 
+// Thread t = v * kTreeWaves + ww (v < vmax) looks at wave ww's mask for value
+// v + 1: the last boundary + 1 (0 = none) and the first boundary (kNone32 =
+// none) with power <= v.  The kTreeWaves threads of one value are consecutive
+// lanes, so their scans over the waves are shuffles within groups of
+// kTreeWaves lanes.
+__device__ inline void wave_ends(const uint64_t (*sM)[kVMax], uint64_t b, int v, int ww,
+                                 uint32_t &last1, uint32_t &first) {
+  const uint64_t mk = sM[ww][v];
+  const uint64_t base = b * kTreeThreads + (uint64_t)ww * kWave;
+  last1 = mk ? (uint32_t)(base + 63 - __clzll(mk)) + 1 : 0u;
+  first = mk ? (uint32_t)(base + __ffsll((long long)mk) - 1) : kNone32;
+}
+
 __global__ __launch_bounds__(kTreeThreads) void k_ansv_block(const uint8_t *__restrict__ P,
                                                              const Plan *__restrict__ plan,
                                                              uint32_t *__restrict__ BL,
@@ -100,17 +113,20 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_block(const uint8_t *__re
     uint64_t i = b * kTreeThreads + t;
     wave_masks(P, r, i, sM[w], lane, vmax);
     __syncthreads();
-    if (t < vmax) {
-      uint32_t last = 0, first = kNone32;
-      for (int ww = 0; ww < kTreeWaves; ww++) {
-        uint64_t mk = sM[ww][t];
-        if (!mk) continue;
-        uint64_t base = b * kTreeThreads + (uint64_t)ww * kWave;
-        if (first == kNone32) first = (uint32_t)(base + __ffsll((long long)mk) - 1);
-        last = (uint32_t)(base + 63 - __clzll(mk)) + 1;
+    if (t < vmax * kTreeWaves) {
+      const int v = t / kTreeWaves, ww = t % kTreeWaves;
+      uint32_t last, first;
+      wave_ends(sM, b, v, ww, last, first);
+#pragma unroll
+      for (int o = kTreeWaves / 2; o > 0; o >>= 1) {
+        const uint32_t l2 = __shfl_xor(last, o, kTreeWaves), f2 = __shfl_xor(first, o, kTreeWaves);
+        last = l2 > last ? l2 : last;
+        first = f2 < first ? f2 : first;
       }
-      BL[b * kVMax + t] = last;
-      BF[b * kVMax + t] = first;
+      if (ww == 0) {
+        BL[b * kVMax + v] = last;
+        BF[b * kVMax + v] = first;
+      }
     }
     __syncthreads();
   }
@@ -248,19 +264,23 @@ __global__ __launch_bounds__(kTreeThreads) void k_ansv_final(
     uint64_t i = b * kTreeThreads + t;
     wave_masks(P, r, i, sM[w], lane, vmax);
     __syncthreads();
-    if (t < vmax) {
-      uint32_t last = 0;
-      for (int ww = 0; ww < kTreeWaves; ww++) {
-        sPL[ww][t] = last;
-        uint64_t mk = sM[ww][t];
-        if (mk) last = (uint32_t)(b * kTreeThreads + (uint64_t)ww * kWave + 63 - __clzll(mk)) + 1;
+    if (t < vmax * kTreeWaves) {
+      // exclusive prefix max of the last ends over the earlier waves, exclusive
+      // suffix min of the first ones over the later waves
+      const int v = t / kTreeWaves, ww = t % kTreeWaves;
+      uint32_t last, first;
+      wave_ends(sM, b, v, ww, last, first);
+      uint32_t pl = last, pr = first;
+#pragma unroll
+      for (int o = 1; o < kTreeWaves; o <<= 1) {
+        const uint32_t a = __shfl_up(pl, o, kTreeWaves), c = __shfl_down(pr, o, kTreeWaves);
+        if (ww >= o) pl = a > pl ? a : pl;
+        if (ww + o < kTreeWaves) pr = c < pr ? c : pr;
       }
-      uint32_t first = kNone32;
-      for (int ww = kTreeWaves - 1; ww >= 0; ww--) {
-        sPR[ww][t] = first;
-        uint64_t mk = sM[ww][t];
-        if (mk) first = (uint32_t)(b * kTreeThreads + (uint64_t)ww * kWave + __ffsll((long long)mk) - 1);
-      }
+      // inclusive to exclusive: the neighbour's inclusive value
+      const uint32_t el = __shfl_up(pl, 1, kTreeWaves), er = __shfl_down(pr, 1, kTreeWaves);
+      sPL[ww][v] = ww > 0 ? el : 0u;
+      sPR[ww][v] = ww + 1 < kTreeWaves ? er : kNone32;
     }
     __syncthreads();
     if (i > 0 && i < r) {
