@@ -89,6 +89,10 @@ constexpr uint8_t kBigLeader = 0x20;   // the leader of a node of span > kSmallS
 // roots the pass finds them from the boundaries instead.
 constexpr int kChunkRec = 8;
 static_assert(kLeafChunk <= 2048 && kLeafCap <= 4096, "root records pack 11 + 12 bits");
+// Placement works in blocks of kPlaceBlock positions; Work::pflag[b] != 0
+// when a run overlapping block b has to move (odd depth or strictly
+// descending, and not inside a small subtree).
+constexpr uint64_t kPlaceBlock = 2048;
 // leaf_depth bit 7: the run's parent node is small (the small-subtree pass reads it)
 constexpr uint8_t kLeafInSmall = 0x80;
 
@@ -143,6 +147,7 @@ struct Work {
   uint8_t *dist0, *dist1;            // [rmax+1]
   uint8_t *leaf_depth;               // [rmax] depth of every run; bit 7: kLeafInSmall
   uint8_t *sflag;                    // [rmax+1] small-node flags per boundary
+  uint32_t *pflag;                   // [N/kPlaceBlock + 2] placement blocks with a run to move
   uint32_t *cfirst;                  // [N/kLeafChunk + 2] run holding each chunk's first position
   uint32_t *croot;                   // [(N/kLeafChunk + 2) * kChunkRec] small roots starting in each chunk
   uint32_t *lvl_cnt;                 // [nbb * kMaxLevels]

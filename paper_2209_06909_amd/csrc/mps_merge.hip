@@ -17,8 +17,8 @@ namespace mps {
 
 // ---------------------------------------------------------------- placement
 constexpr int kPlaceThreads = 256;
-constexpr int kPlaceE = 8;                                   // positions per thread
-constexpr uint64_t kPlaceBlock = (uint64_t)kPlaceThreads * kPlaceE;
+constexpr int kPlaceE = (int)(kPlaceBlock / kPlaceThreads);   // positions per thread
+static_assert(kPlaceE * kPlaceThreads == (int)kPlaceBlock && kPlaceE % 2 == 0, "placement block");
 
 // Placement flags of a run: bit 0 odd depth, bit 1 strictly descending.  A run
 // whose parent is a small node is left to the small-subtree pass (flags 0).
@@ -112,6 +112,25 @@ __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
   }
 }
 
+// Blocks that lie inside one run get that run's verdict (the leaf-depth pass
+// flagged only the first and last block of every run that moves).  One thread
+// per block, binary search in the run table.
+__global__ __launch_bounds__(256) void k_place_blocks(const uint64_t *__restrict__ rs,
+                                                      const uint8_t *__restrict__ desc,
+                                                      const uint8_t *__restrict__ leaf_depth,
+                                                      const Plan *__restrict__ plan, uint64_t N,
+                                                      uint32_t *__restrict__ pflag) {
+  const uint64_t r = plan->r;
+  const uint64_t nblk = (N + kPlaceBlock - 1) / kPlaceBlock;
+  if (r == 0) return;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblk;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
+    const uint64_t j = run_of(rs, 0, r - 1, bs);
+    if (rs[j + 1] >= be) pflag[b] = place_flags(leaf_depth[j], desc[j]) != 0 ? 1u : 0u;
+  }
+}
+
 // Each workgroup takes a contiguous range of blocks of kPlaceBlock positions.
 // For every block the threads stage, in one round of loads, the starts and
 // flags (bit 0 odd depth, bit 1 descending) of the kPlaceThreads runs from the
@@ -132,6 +151,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
                                                          const uint64_t *__restrict__ rs,
                                                          const uint8_t *__restrict__ desc,
                                                          const uint8_t *__restrict__ leaf_depth,
+                                                         const uint32_t *__restrict__ pflag,
                                                          const Plan *__restrict__ plan,
                                                          uint64_t *__restrict__ smp) {
   using U = typename Key<KT>::U;
@@ -149,11 +169,22 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(typename Key<KT>::U *__
   const uint64_t b0 = (uint64_t)blockIdx.x * per;
   const uint64_t b1 = b0 + per < nblk ? b0 + per : nblk;
   if (b0 >= b1 || r == 0) return;   // uniform in the workgroup
-  if (t == 0) sJ = run_of(rs, 0, r - 1, b0 * kPlaceBlock);
-  __syncthreads();
-  uint64_t jc = sJ;   // run holding the current block's first position
+  uint64_t jc = 0;      // run holding the current block's first position
+  bool known = false;   // jc is current
   for (uint64_t b = b0; b < b1; b++) {
     const uint64_t bs = b * kPlaceBlock, be = bs + kPlaceBlock < N ? bs + kPlaceBlock : N;
+    // blocks in which no run moves (flagged by the leaf-depth pass) are skipped
+    if (pflag[b] == 0u) {   // uniform
+      known = false;
+      continue;
+    }
+    if (!known) {
+      if (t == 0) sJ = run_of(rs, 0, r - 1, bs);
+      __syncthreads();
+      jc = sJ;
+      known = true;
+      __syncthreads();   // sJ is read before it is written again
+    }
     {
       const uint64_t i = jc + (uint64_t)t;
       sRs[t] = i <= r ? rs[i] : ~0ull;   // rs[r] = N
@@ -224,7 +255,7 @@ static void launch_place_v(void *keys, void *vals, const Work &w, unsigned g, hi
   using U = typename Key<KT>::U;
   hipLaunchKernelGGL((k_place<KT, V>), dim3(g), dim3(kPlaceThreads), 0, s, (U *)keys, (V *)vals,
                      (U *)w.alt_keys, (V *)w.alt_vals, w.N, w.run_start, w.run_desc, w.leaf_depth,
-                     w.plan, w.samples);
+                     w.pflag, w.plan, w.samples);
 }
 
 template <int KT>
@@ -237,6 +268,9 @@ hipError_t launch_place(int kt, void *keys, uint32_t *vals, const Work &w, hipSt
   uint64_t nblk = (w.N + kPlaceBlock - 1) / kPlaceBlock;
   unsigned g = (unsigned)(nblk < 8192 ? nblk : 8192);
   if (g == 0) return hipSuccess;
+  const unsigned gb = (unsigned)((nblk + 255) / 256 < 4096 ? (nblk + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_place_blocks, dim3(gb), dim3(256), 0, s, w.run_start, w.run_desc,
+                     w.leaf_depth, w.plan, w.N, w.pflag);
   if (kt == 1) launch_place_kt<1>(keys, vals, w, g, s);
   else if (kt == 2) launch_place_kt<2>(keys, vals, w, g, s);
   else launch_place_kt<0>(keys, vals, w, g, s);

@@ -512,6 +512,10 @@ __global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ sflag,
 // proof of Theorem 3.3); both 0 means the run is a whole segment.  Bit 7
 // (kLeafInSmall) marks a run whose parent is a small node: the small-subtree
 // pass, not placement, reads it; without FULL its depth is not computed.
+//
+// A run that placement has to move (odd depth or strictly descending, and not
+// inside a small subtree) flags the first and the last placement block it
+// touches (pflag, cleared by k_zero32 before).
 template <bool FULL>
 __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
                                                 const uint32_t *__restrict__ Ls,
@@ -520,7 +524,9 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
                                                 const uint8_t *__restrict__ dist,
                                                 const uint64_t *__restrict__ rs, Plan *plan,
                                                 int want_cost, const uint8_t *__restrict__ sflag,
-                                                uint8_t *__restrict__ leaf_depth) {
+                                                const uint8_t *__restrict__ desc,
+                                                uint8_t *__restrict__ leaf_depth,
+                                                uint32_t *__restrict__ pflag) {
   const uint64_t r = plan->r;
   uint64_t cost = 0;
   uint32_t dend = 0;
@@ -540,6 +546,10 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
       }
     }
     leaf_depth[j] = d | in_small;
+    if (!in_small && ((d & 1) || desc[j])) {
+      pflag[rs[j] / kPlaceBlock] = 1u;
+      pflag[(rs[j + 1] - 1) / kPlaceBlock] = 1u;
+    }
     if (FULL && in_small && d > dend) dend = d;
     if (want_cost) cost += (uint64_t)d * (rs[j + 1] - rs[j]);
   }
@@ -845,6 +855,12 @@ __global__ void k_tree_done(Plan *plan) {
   plan->lean = 0;
 }
 
+__global__ __launch_bounds__(256) void k_zero32(uint32_t *__restrict__ a, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+
 // ---------------------------------------------------------------- host side
 static void launch_ansv_carries(const Work &w, hipStream_t s) {
   const uint64_t nbb = (w.rmax + 1 + kTreeThreads - 1) / kTreeThreads;
@@ -881,10 +897,15 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
     hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.sflag, mask, w.plan, round, even ? w.jump0 : w.jump1,
                        even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0, even ? w.dist1 : w.dist0);
   }
+  {
+    const uint64_t nb = w.N / kPlaceBlock + 2;
+    hipLaunchKernelGGL(k_zero32, dim3((unsigned)((nb + 255) / 256 < 4096 ? (nb + 255) / 256 : 4096)),
+                       b256, 0, s, w.pflag, nb);
+  }
   if (full)
-    hipLaunchKernelGGL(k_leaves<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
+    hipLaunchKernelGGL(k_leaves<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.run_desc, w.leaf_depth, w.pflag);
   else
-    hipLaunchKernelGGL(k_leaves<false>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.leaf_depth);
+    hipLaunchKernelGGL(k_leaves<false>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, want_cost, w.sflag, w.run_desc, w.leaf_depth, w.pflag);
   hipLaunchKernelGGL(k_lvl_count, dim3(gtree), dim3(kTreeThreads), 0, s, w.dist0, w.sflag, w.plan, w.lvl_cnt);
   {
     const uint64_t nbb = (w.rmax + 1 + kTreeThreads - 1) / kTreeThreads;
@@ -923,7 +944,7 @@ hipError_t launch_tree_complete(const Work &w, bool nodes, unsigned gtree, hipSt
                        even ? w.jump0 : w.jump1, even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0,
                        even ? w.dist1 : w.dist0);
   }
-  hipLaunchKernelGGL(k_leaves<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, 1, w.sflag, w.leaf_depth);
+  hipLaunchKernelGGL(k_leaves<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.dist0, w.run_start, w.plan, 1, w.sflag, w.run_desc, w.leaf_depth, w.pflag);
   hipLaunchKernelGGL(k_tree_done, dim3(1), dim3(64), 0, s, w.plan);
   return hipGetLastError();
 }
