@@ -97,12 +97,13 @@ struct Layout {
   size_t total = 0;
   size_t alt_keys, alt_vals, seg_off, seg_bits, dbits, det_agg, det_zin, det_off, run_start, run_desc,
       power, ansv_bl, ansv_bf, ansv_cl, ansv_cr, ansv_tl, ansv_tr, Ls, Rs, Le, Re, nd_arity, nd_mem, jump0, jump1,
-      dist0, dist1, leaf_depth, sflag, pflag, cfirst, croot, lvl_cnt, lvl_car, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
+      dist0, dist1, leaf_depth, sflag, pflag, jlist, cfirst, croot, lvl_cnt, lvl_car, lvl_tot, lvl_list, lvl_np, scan_tmp, corank, tile_desc, gen_list, tile_base,
       tj, samples, plan, nat_start, nat_desc, mr_first, mr_nxt, mr_cnt, mr_gnxt, mr_gcnt,
       mr_gentry, mr_goff, mr_centry, mr_coff;
   uint64_t rmax, nbb, tiles_max, tj_cap, lvl_cap;
   int levels;
   bool tree_tmp_in_alt;   // Le, Re, jump0/1, dist1 share the ping-pong buffer's bytes
+  bool jlist_in_alt;      // so does the pointer-jumping list
 };
 
 size_t take(size_t &cur, size_t bytes) {
@@ -163,6 +164,11 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
       L.jump1 = j1;
       L.dist1 = d1;
     }
+    // the pointer-jumping list, after them, or alone at the start
+    size_t tl = L.tree_tmp_in_alt ? t : L.alt_keys;
+    const size_t jl = take(tl, (rmax + 1) * 4);
+    L.jlist_in_alt = tl <= alt_end;
+    if (L.jlist_in_alt) L.jlist = jl;
   }
   bool nat_in_alt = false;
   if (m == 1) {
@@ -205,6 +211,7 @@ bool make_layout(uint64_t N, uint64_t m, int kt, int pb, uint32_t k, Layout &L) 
   if (!L.tree_tmp_in_alt) L.dist1 = take(c, rmax + 1);
   L.leaf_depth = take(c, rmax);
   L.sflag = take(c, rmax + 17);   // read 16 flags at a time
+  if (!L.jlist_in_alt) L.jlist = take(c, (rmax + 1) * 4);
   L.pflag = take(c, (N / kPlaceBlock + 2) * 4);
   L.cfirst = take(c, (N / kLeafChunk + 2) * 4);
   L.croot = take(c, (N / kLeafChunk + 2) * kChunkRec * 4);
@@ -381,6 +388,7 @@ void bind_work(Work &w, void *base, const Layout &L, uint64_t N, uint64_t m, uin
   w.dist1 = at<uint8_t>(base, L.dist1);
   w.leaf_depth = at<uint8_t>(base, L.leaf_depth);
   w.sflag = at<uint8_t>(base, L.sflag);
+  w.jlist = at<uint32_t>(base, L.jlist);
   w.pflag = at<uint32_t>(base, L.pflag);
   w.cfirst = at<uint32_t>(base, L.cfirst);
   w.croot = at<uint32_t>(base, L.croot);

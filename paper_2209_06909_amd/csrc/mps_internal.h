@@ -65,6 +65,8 @@ struct Plan {
   uint32_t lvl_levels;               // levels holding a node of the level lists (1 + deepest depth)
   uint32_t lean;                     // 1: the tree was built without FULL (see launch_tree)
   uint32_t pmax;                     // the largest node power
+  uint32_t n_jump;                   // leaders listed for pointer jumping (Work::jlist)
+  uint32_t pad3;
 };
 
 // Small subtrees: a node whose span is at most kSmallSpan elements is
@@ -148,6 +150,7 @@ struct Work {
   uint8_t *leaf_depth;               // [rmax] depth of every run; bit 7: kLeafInSmall
   uint8_t *sflag;                    // [rmax+1] small-node flags per boundary
   uint32_t *pflag;                   // [N/kPlaceBlock + 2] placement blocks with a run to move
+  uint32_t *jlist;                   // [rmax + 1] leaders that take part in pointer jumping
   uint32_t *cfirst;                  // [N/kLeafChunk + 2] run holding each chunk's first position
   uint32_t *croot;                   // [(N/kLeafChunk + 2) * kChunkRec] small roots starting in each chunk
   uint32_t *lvl_cnt;                 // [nbb * kMaxLevels]

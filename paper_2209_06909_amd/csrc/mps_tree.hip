@@ -466,43 +466,85 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
     atomicAdd((unsigned long long *)&plan->n_small, (unsigned long long)n_small);
 }
 
-// One pointer-jumping round over the boundaries whose sflag has a bit of
-// `mask` (the leaders whose depth is wanted; their parents are among them):
-// the jump target moves to the target's target and the distance adds up.
-// Roots point to themselves with distance 0, so once every target is a root
-// further rounds change nothing; a round that finds this recorded by its
-// predecessor only copies.
-__global__ __launch_bounds__(256) void k_jump(const uint8_t *__restrict__ sflag, uint8_t mask,
+// The boundaries whose sflag has a bit of `mask` (the leaders whose depth is
+// wanted; their parents are among them), listed in jlist in no particular
+// order: 16 boundaries per thread from one 16-byte load of their flags (sflag
+// has rmax + 1 >= r entries, padded to 16 bytes by the workspace layout), a
+// block scan of the counts, and one atomic per workgroup for its slot.
+__global__ __launch_bounds__(256) void k_jump_list(const uint8_t *__restrict__ sflag, uint8_t mask,
+                                                   Plan *__restrict__ plan,
+                                                   uint32_t *__restrict__ jlist) {
+  __shared__ uint32_t sw[4];
+  __shared__ uint32_t sbase;
+  const uint64_t r = plan->r;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint64_t ng = (r + 15) / 16;
+  for (uint64_t g0 = (uint64_t)blockIdx.x * 256; g0 < ng; g0 += (uint64_t)gridDim.x * 256) {
+    const uint64_t g = g0 + t;
+    uint32_t fw[4] = {0u, 0u, 0u, 0u};
+    if (g < ng) {
+      const uint4 fv = reinterpret_cast<const uint4 *>(sflag)[g];
+      fw[0] = fv.x; fw[1] = fv.y; fw[2] = fv.z; fw[3] = fv.w;
+    }
+    uint32_t bits = 0;   // bit q: boundary g*16+q is listed
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      const uint32_t i = (uint32_t)(g * 16 + q);
+      if (((fw[q >> 2] >> ((q & 3) * 8)) & mask) && i > 0 && i < r) bits |= 1u << q;
+    }
+    const uint32_t cnt = (uint32_t)__popc(bits);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) sw[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ww++) {
+      pre += ww < w ? sw[ww] : 0u;
+      tot += sw[ww];
+    }
+    if (t == 0) sbase = tot ? atomicAdd(&plan->n_jump, tot) : 0u;
+    __syncthreads();
+    uint32_t at = sbase + pre + incl - cnt;
+    while (bits) {
+      const int q = __ffs(bits) - 1;
+      bits &= bits - 1;
+      jlist[at++] = (uint32_t)(g * 16 + q);
+    }
+    __syncthreads();   // sw and sbase are rewritten
+  }
+}
+
+// One pointer-jumping round over the listed leaders: the jump target moves to
+// the target's target and the distance adds up.  Roots point to themselves
+// with distance 0, so once every target is a root further rounds change
+// nothing; a round that finds this recorded by its predecessor only copies.
+__global__ __launch_bounds__(256) void k_jump(const uint32_t *__restrict__ jlist,
                                               Plan *__restrict__ plan, int round,
                                               const uint32_t *__restrict__ jin,
                                               const uint8_t *__restrict__ din,
                                               uint32_t *__restrict__ jout,
                                               uint8_t *__restrict__ dout) {
-  const uint64_t r = plan->r;
+  const uint64_t nj = plan->n_jump;
   const bool copy = round > 0 && plan->jump_more[round - 1] == 0;
   bool more = false;
-  // 16 boundaries per thread: one 16-byte load of their flags (sflag has
-  // rmax + 1 >= r entries, padded to 16 bytes by the workspace layout)
-  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g * 16 < r;
-       g += (uint64_t)gridDim.x * blockDim.x) {
-    const uint4 fv = reinterpret_cast<const uint4 *>(sflag)[g];
-    const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
-#pragma unroll
-    for (int q = 0; q < 16; q++) {
-      if (!((fw[q >> 2] >> ((q & 3) * 8)) & mask)) continue;
-      const uint32_t i = (uint32_t)(g * 16 + q);
-      if (i == 0 || i >= r) continue;
-      if (copy) {
-        jout[i] = jin[i];
-        dout[i] = din[i];
-        continue;
-      }
-      const uint32_t j = jin[i];
-      dout[i] = din[i] + din[j];
-      const uint32_t j2 = jin[j];
-      jout[i] = j2;
-      more = more || jin[j2] != j2;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nj;
+       x += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = jlist[x];
+    if (copy) {
+      jout[i] = jin[i];
+      dout[i] = din[i];
+      continue;
     }
+    const uint32_t j = jin[i];
+    dout[i] = din[i] + din[j];
+    const uint32_t j2 = jin[j];
+    jout[i] = j2;
+    more = more || jin[j2] != j2;
   }
   if (__syncthreads_or(more) && threadIdx.x == 0) atomicOr(&plan->jump_more[round], 1u);
 }
@@ -845,6 +887,7 @@ __global__ void k_tree_reset(Plan *plan) {
   plan->n_small = 0;
   plan->small_depth_end = 0;
   plan->merge_cost = 0;
+  plan->n_jump = 0;
   for (int i = 0; i < 8; i++) plan->jump_more[i] = 0;
 }
 
@@ -892,9 +935,10 @@ hipError_t launch_tree(const Work &w, int want_cost, uint64_t *lvl_tot, uint64_t
   else
     hipLaunchKernelGGL(k_nodes<false>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
   const uint8_t mask = full ? (uint8_t)(kBigLeader | kSmallNode) : (uint8_t)(kBigLeader | kSmallRoot);
+  hipLaunchKernelGGL(k_jump_list, g256, b256, 0, s, w.sflag, mask, w.plan, w.jlist);
   for (int round = 0; round < 6; round++) {  // depths < 64
     bool even = (round & 1) == 0;
-    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.sflag, mask, w.plan, round, even ? w.jump0 : w.jump1,
+    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.jlist, w.plan, round, even ? w.jump0 : w.jump1,
                        even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0, even ? w.dist1 : w.dist0);
   }
   {
@@ -938,9 +982,10 @@ hipError_t launch_tree_complete(const Work &w, bool nodes, unsigned gtree, hipSt
   if (!nodes) return hipGetLastError();
   hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, w.plan);
   hipLaunchKernelGGL(k_nodes<true>, g256, b256, 0, s, w.power, w.Ls, w.Rs, w.Le, w.Re, w.run_start, w.plan, w.k, w.nd_mem, w.nd_arity, w.jump0, w.dist0, w.sflag);
+  hipLaunchKernelGGL(k_jump_list, g256, b256, 0, s, w.sflag, (uint8_t)(kBigLeader | kSmallNode), w.plan, w.jlist);
   for (int round = 0; round < 6; round++) {
     bool even = (round & 1) == 0;
-    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.sflag, (uint8_t)(kBigLeader | kSmallNode), w.plan, round,
+    hipLaunchKernelGGL(k_jump, g256, b256, 0, s, w.jlist, w.plan, round,
                        even ? w.jump0 : w.jump1, even ? w.dist0 : w.dist1, even ? w.jump1 : w.jump0,
                        even ? w.dist1 : w.dist0);
   }
