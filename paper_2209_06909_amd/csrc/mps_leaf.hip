@@ -94,7 +94,8 @@ constexpr uint32_t kMkEnd = 1, kMkStart = 2, kMkOdd = 4;
 // Keys and tags are padded by one slot per kLeafItems, so the contiguous
 // per-thread write-backs spread over the LDS banks.
 constexpr int kLeafPad = kLeafCap + kLeafCap / kLeafItems;
-__device__ inline int lph(int p) { return p + p / kLeafItems; }
+static_assert(kLeafItems == 8, "lph divides by shifting");
+__device__ inline int lph(int p) { return p + (p >> 3); }   // p >= 0
 
 template <typename O, bool HV, typename V>
 struct LeafSmem {
@@ -121,6 +122,19 @@ __device__ inline int leaf_piece(const uint16_t *pinfo, int np, int p) {
     if ((int)(pinfo[mid] & kPcPos) <= p) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// Positions held by one wave (a thread holds kLeafItems consecutive ones).
+constexpr int kWaveSpan = 64 * kLeafItems;
+
+// Orders the LDS accesses of one wave around the call.  A wave's LDS
+// operations complete in the order they are issued, so lanes of one wave
+// exchange data through LDS with no hardware barrier; only the compiler has
+// to keep the accesses on their side of the call.
+__device__ inline void leaf_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Exclusive block scan of one u32 per thread; the total goes to *total (LDS,
@@ -339,9 +353,12 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
           if (HV) sm.tag[lph(p0 + q)] = it[q].g;
         }
       }
-      __syncthreads();
-      // ---- merge rounds: blocks of w sorted positions, merged in pairs
+      // ---- merge rounds: blocks of w sorted positions, merged in pairs.  A
+      // pair of 2w <= kWaveSpan positions lies in one wave's positions, so
+      // such a round exchanges data only among the lanes of one wave.
+      if (E < Tp) leaf_wave_sync(); else __syncthreads();
       for (int w = E; w < Tp; w <<= 1) {
+        const bool wave_round = 2 * w <= kWaveSpan;
         const int base = p0 & ~(2 * w - 1), m = base + w;
         int s = 0, e = 0;
         bool act = false;
@@ -357,49 +374,54 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
             act = p0 + E > s && p0 < e;
           }
         }
+        // this thread writes positions [p0 + q0, p0 + q0 + cnt) of [s, e)
+        const int q0 = s > p0 ? s - p0 : 0;
+        const int cnt = (e - p0 < E ? e - p0 : E) - q0;
         if (act) {
-          const int la = m - s, lb = e - m;   // both >= 1
-          const int q0 = s > p0 ? s - p0 : 0, q1 = e - p0 < E ? e - p0 : E;
-          const int d = p0 + q0 - s;
+          // merge path: the outputs of [s, e) before this thread's first take
+          // i from [s, m) and d - i from [m, e)
+          const int d = p0 + q0 - s, la = m - s, lb = e - m;   // la, lb >= 1
           int lo2 = d - lb > 0 ? d - lb : 0, hi2 = d < la ? d : la;
           while (lo2 < hi2) {
             const int mid = (lo2 + hi2) >> 1;
             if (sm.key[lph(m + d - 1 - mid)] < sm.key[lph(s + mid)]) hi2 = mid; else lo2 = mid + 1;
           }
-          int i = lo2, j = d - lo2;
-          int ai = s + (i < la ? i : la - 1), bj = m + (j < lb ? j : lb - 1);
-          It a, b;
-          a.k = sm.key[lph(ai)];
-          a.g = HV ? sm.tag[lph(ai)] : 0u;
-          b.k = sm.key[lph(bj)];
-          b.g = HV ? sm.tag[lph(bj)] : 0u;
+          // E merge steps without predication: ia / jb are the next positions
+          // of the two halves; steps past cnt are computed and not stored
+          int ia = s + lo2, jb = m + d - lo2;
+          O ak = sm.key[lph(ia < m ? ia : m - 1)], bk = sm.key[lph(jb < e ? jb : e - 1)];
+          int ix[E];
 #pragma unroll
           for (int q = 0; q < E; q++) {
-            if (q >= q0 && q < q1) {
-              const bool tb = j < lb && (i >= la || b.k < a.k);
-              it[q] = tb ? b : a;
-              if (q + 1 < q1) {
-                if (tb) j++; else i++;
-                const int src = tb ? m + (j < lb ? j : lb - 1) : s + (i < la ? i : la - 1);
-                It n;
-                n.k = sm.key[lph(src)];
-                n.g = HV ? sm.tag[lph(src)] : 0u;
-                if (tb) b = n; else a = n;
-              }
+            const bool tb = jb < e && (ia >= m || bk < ak);   // ties: the left half
+            it[q].k = tb ? bk : ak;
+            ix[q] = tb ? jb : (ia < m ? ia : m - 1);
+            if (q + 1 < E) {
+              jb += tb ? 1 : 0;
+              ia += tb ? 0 : 1;
+              const int src = tb ? (jb < e ? jb : e - 1) : (ia < m ? ia : m - 1);
+              const O nk = sm.key[lph(src)];
+              bk = tb ? nk : bk;
+              ak = tb ? ak : nk;
             }
           }
+          if (HV) {
+#pragma unroll
+            for (int q = 0; q < E; q++) it[q].g = sm.tag[lph(ix[q])];
+          }
         }
-        __syncthreads();
+        if (wave_round) leaf_wave_sync(); else __syncthreads();
         if (act) {
 #pragma unroll
           for (int q = 0; q < E; q++) {
-            if (p0 + q >= s && p0 + q < e) {
-              sm.key[lph(p0 + q)] = it[q].k;
-              if (HV) sm.tag[lph(p0 + q)] = it[q].g;
+            if (q < cnt) {
+              sm.key[lph(p0 + q0 + q)] = it[q].k;
+              if (HV) sm.tag[lph(p0 + q0 + q)] = it[q].g;
             }
           }
         }
-        __syncthreads();
+        // the next round reads only this wave's positions if it is a wave round
+        if (2 * w < Tp && 4 * w <= kWaveSpan) leaf_wave_sync(); else __syncthreads();
       }
       // ---- store every small root's span to the buffer of its depth parity
 #pragma unroll

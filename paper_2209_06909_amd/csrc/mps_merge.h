@@ -65,7 +65,10 @@ __device__ inline bool st_less(O x, int a, O y, int b) {
 // empty windows.  Sums, the split correction and the largest-taken /
 // smallest-untaken choice are group reductions over shuffles, so one round
 // costs a few instructions per lane and its probes are issued by different
-// lanes.  The loop condition is uniform within a group.  Returns lane j's cut.
+// lanes.  The loop condition is uniform within a group.  Returns lane j's cut;
+// `spent` becomes 1 if the round limit ended the search before a consistent
+// cut was found (never expected: the windows shrink by at least one position
+// per lane pair every round).
 template <int K>
 __device__ inline uint32_t gsum(uint32_t v) {
 #pragma unroll
@@ -101,15 +104,20 @@ __device__ inline uint64_t gshfl_up64(uint64_t v, int o) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+constexpr int kCorankRounds = 4096;
+constexpr uint32_t kErrCorankRounds = 8192u;   // plan->error bit: a co-rank search ran out of rounds
+
 template <typename O, int K, typename Get>
-__device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, int j, Get get) {
+__device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, int j, Get get,
+                                       uint32_t &spent) {
   uint32_t mm = 0;
-  for (int it = 0; it < 4096; it++) {
+  spent = 1;
+  for (int it = 0; it < kCorankRounds; it++) {
     const uint32_t w = hi - lo;
     const uint32_t slo = gsum<K>(lo), W = gsum<K>(w);
     const uint32_t rem = q - slo;
-    if (rem == 0) { mm = 0; break; }
-    if (rem == W) { mm = w; break; }
+    if (rem == 0) { mm = 0; spent = 0; break; }
+    if (rem == W) { mm = w; spent = 0; break; }
     const float f = (float)rem / (float)W;
     uint32_t v = (uint32_t)((float)w * f);
     v = v < w ? v : w;
@@ -140,7 +148,7 @@ __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, in
       if (ao >= 0 && (a < 0 || st_less(x, a, xo, ao))) { x = xo; a = ao; }
       if (bo >= 0 && (b < 0 || st_less(yo, bo, y, b))) { y = yo; b = bo; }
     }
-    if (a < 0 || b < 0 || a == b || st_less(x, a, y, b)) break;
+    if (a < 0 || b < 0 || a == b || st_less(x, a, y, b)) { spent = 0; break; }
     // Inconsistent: the true cut leaves x (child a) untaken and takes y
     // (child b), hence leaves everything after x untaken and takes everything
     // before y.  Every lane narrows its own window with that.
@@ -203,6 +211,7 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
         q = 0;
       }
       if (q > 0) {   // uniform within the group
+        uint32_t spent = 0, nspent = 0;   // uniform within the group
         const int d = nd.d;
         const bool live = j < d;
         const uint64_t cj = live ? nd.c[j] : 0, len = live ? nd.c[j + 1] - nd.c[j] : 0;
@@ -218,11 +227,13 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
           qlo = qlo < ms ? qlo : ms;
           const uint64_t qhi = qs + d + 1 < ms ? qs + d + 1 : ms;
           const uint32_t clo = corank_group<O, K>((uint32_t)qlo, 0u,
-                                                  m < qlo ? m : (uint32_t)qlo, j, gs);
+                                                  m < qlo ? m : (uint32_t)qlo, j, gs, spent);
+          nspent |= spent;
           // the cut at qhi contains the one at qlo and exceeds it by qhi - qlo in total
           const uint32_t dq = (uint32_t)(qhi - qlo);
           const uint32_t chi = corank_group<O, K>((uint32_t)qhi, clo,
-                                                  m - clo < dq ? m : clo + dq, j, gs);
+                                                  m - clo < dq ? m : clo + dq, j, gs, spent);
+          nspent |= spent;
           uint64_t nlo = clo >= 1 ? off + (uint64_t)(clo - 1) * S + 1 : 0;
           uint64_t nhi = chi < m ? off + (uint64_t)chi * S : len;
           if (nhi > hi) nhi = hi;
@@ -237,7 +248,9 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
           }
         }
         auto gk = [&](int, uint64_t x) { return Key<KT>::ord(in_keys[cj + x]); };
-        out = corank_group<O, K>((uint32_t)q, lo, hi, j, gk);
+        out = corank_group<O, K>((uint32_t)q, lo, hi, j, gk, spent);
+        nspent |= spent;
+        if (nspent && j == 0) atomicOr(&plan->error, kErrCorankRounds);
         if (!live) out = 0;
       }
     }
