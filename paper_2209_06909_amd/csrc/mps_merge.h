@@ -283,8 +283,7 @@ __device__ inline TileGeom tile_geom(uint64_t tile, int tsize, uint64_t L, uint6
   return g;
 }
 
-// Tables of a tile that touches at most two nodes (the common case once
-// nodes are larger than a tile), built by the descriptor kernel for the merge
+// Tables of a tile that touches at most PM nodes, built by the descriptor kernel for the merge
 // kernel, which copies them to LDS word by word: the tile's input slices are
 // staged back to back in LDS; slice s starts at LDS position sl_off[s], and
 // the global index of LDS position e of slice s is delta[s] + e.  Piece p (a
@@ -294,27 +293,39 @@ __device__ inline TileGeom tile_geom(uint64_t tile, int tsize, uint64_t L, uint6
 // general kernel; kTabBad: an inconsistent cut).
 enum { kTabNone = 0, kTabFast = 1, kTabGeneral = 2, kTabBad = 3 };
 
-template <int K>
+template <int K, int PM>
 struct TileTab {
-  uint64_t delta[2 * K];
-  uint64_t pc_out[2];
-  uint16_t sl_off[2 * K + 2];
-  uint16_t pc_loff[3];
-  uint16_t pc_sl[3];
+  static constexpr int kPieces = PM;
+  uint64_t delta[PM * K];
+  uint64_t pc_out[PM];
+  uint16_t sl_off[PM * K + 2];
+  uint16_t pc_loff[PM + 1];
+  uint16_t pc_sl[PM + 1];
   int32_t S, P, Tt, kind;
 };
-static_assert(sizeof(TileTab<8>) <= kTileDescBytes, "tile table slot too small");
-static_assert(sizeof(TileTab<8>) % 4 == 0 && sizeof(TileTab<8>) / 4 <= 64,
-              "a tile table is copied by the lanes of one wave, a word each");
+// PM: three pieces for 8-byte keys and k <= 4, else two.  Above the small
+// subtrees every node of a level is longer than half a 2048-position tile, so
+// such a tile never touches more than three nodes; the 4-byte-key kernels keep
+// two, which holds them within their register bound.
+template <typename O, int K>
+using TileTabFor = TileTab<K, (sizeof(O) == 8 && K <= 4) ? 3 : 2>;
+template <int K, int PM>
+constexpr bool tab_fits() {
+  return sizeof(TileTab<K, PM>) <= kTileDescBytes && sizeof(TileTab<K, PM>) % 4 == 0 &&
+         sizeof(TileTab<K, PM>) / 4 <= 64;
+}
+static_assert(tab_fits<2, 2>() && tab_fits<2, 3>() && tab_fits<4, 2>() && tab_fits<4, 3>() &&
+                  tab_fits<8, 2>(),
+              "a tile table fits its slot and is copied by the lanes of one wave, a word each");
 
-template <int K>
+template <int K, int PM>
 __global__ __launch_bounds__(256) void k_tile_desc(
     const uint64_t *__restrict__ rs, const uint32_t *__restrict__ Ls,
     const uint32_t *__restrict__ Rs, const uint32_t *__restrict__ mem,
     const uint8_t *__restrict__ arity, const uint32_t *__restrict__ list,
     const uint64_t *__restrict__ np, const uint32_t *__restrict__ tj,
     const uint64_t *__restrict__ tile_base, Plan *__restrict__ plan, int level, int tsize,
-    const uint32_t *__restrict__ cr, TileTab<K> *__restrict__ desc,
+    const uint32_t *__restrict__ cr, TileTab<K, PM> *__restrict__ desc,
     uint32_t *__restrict__ gen_list) {
   const uint64_t tiles = plan->lvl_tiles[level];
   if (tiles == 0) return;
@@ -326,18 +337,18 @@ __global__ __launch_bounds__(256) void k_tile_desc(
   const uint32_t *tjl = tj + tile_base[level];
   for (uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; tile < tiles;
        tile += (uint64_t)gridDim.x * blockDim.x) {
-    TileTab<K> X;
-    for (int s = 0; s < 2 * K; s++) X.delta[s] = 0;
-    for (int s = 0; s < 2 * K + 2; s++) X.sl_off[s] = 0;
-    for (int p = 0; p < 3; p++) { X.pc_loff[p] = 0; X.pc_sl[p] = 0; }
-    X.pc_out[0] = X.pc_out[1] = 0;
+    TileTab<K, PM> X;
+    for (int s = 0; s < PM * K; s++) X.delta[s] = 0;
+    for (int s = 0; s < PM * K + 2; s++) X.sl_off[s] = 0;
+    for (int p = 0; p < PM + 1; p++) { X.pc_loff[p] = 0; X.pc_sl[p] = 0; }
+    for (int p = 0; p < PM; p++) X.pc_out[p] = 0;
     X.S = 0;
     X.P = 0;
     TileGeom g = tile_geom(tile, tsize, L, nlev, np, lb, np0, tjl);
     X.Tt = (int32_t)(g.Q1 - g.Q0);
     if (!g.ok) {
       X.kind = kTabBad;
-    } else if (g.j1 - g.j0 + 1 <= 2) {
+    } else if (g.j1 - g.j0 + 1 <= (uint64_t)PM) {
       const int P = (int)(g.j1 - g.j0 + 1);
       int off = 0, s = 0;
       bool bad = false;
@@ -384,9 +395,10 @@ template <typename O, int K, int TILE, int VB = 4>
 struct FastSmem {
   static constexpr size_t kKeyBytes = (size_t)(TILE + 4) * 8;
   static constexpr size_t kBuf = kKeyBytes + (size_t)TILE * VB;
-  static constexpr int kTabWords = (int)(sizeof(TileTab<K>) / 4);
+  using Tab = TileTabFor<O, K>;
+  static constexpr int kTabWords = (int)(sizeof(Tab) / 4);
   alignas(16) unsigned char bufA[kBuf];
-  TileTab<K> tab[2];
+  Tab tab[2];
   uint32_t claim[2];   // tile indices taken from the work queue
 };
 
@@ -442,8 +454,8 @@ __device__ inline void addr_table(uint64_t (&g)[E], const uint16_t *pos_sl,
 // lie in one slice, found with one ballot over the slice starts (lane j holds
 // the start of slice j); only a wave whose positions cross a slice start
 // compares per lane.
-template <int E, int THREADS, int K>
-__device__ inline void addr_desc(uint64_t (&g)[E], const TileTab<K> &T, int t) {
+template <int E, int THREADS, typename Tab>
+__device__ inline void addr_desc(uint64_t (&g)[E], const Tab &T, int t) {
   const int lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int S = T.S, Tt = T.Tt;
@@ -590,7 +602,7 @@ __device__ inline int lift_search(const O *a, const O *b, int lo, int hi) {
   return lo;
 }
 
-// The same stages for a descriptor tile (at most two pieces, 2K slices), in
+// The same stages for a descriptor tile (at most PM pieces, PM*K slices), in
 // place in one LDS buffer.  A lane owns the E outputs [t*E, t*E+E) at every
 // stage: it merges them into registers, and after a barrier (every read of
 // the stage done) writes them back over the stage's input.  The slices holding
@@ -602,13 +614,24 @@ __device__ inline int lift_search(const O *a, const O *b, int lo, int hi) {
 // an unrolled E-step merge produce them.  Lanes spanning more units (only when
 // a unit is shorter than E) walk unit by unit.  The key buffer carries one element of padding,
 // so reading one past a unit is harmless.
-template <typename O, typename V, int K, int TILE, int THREADS, bool HV>
+template <typename O, typename V, int K, int TILE, int THREADS, bool HV, int PM>
 __device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off_l, int S,
                                             const uint16_t *pc_sl_l, int P, int Tt, int t) {
   constexpr int E = TILE / THREADS;
   constexpr int LOGK = K == 2 ? 1 : (K == 4 ? 2 : 3);
   constexpr int KS = (int)sizeof(O);
-  const int s1 = P == 2 ? (int)pc_sl_l[1] : S;   // first slice of the second piece
+  // first slices of the second and third pieces (S where there is none)
+  const int s1 = P >= 2 ? (int)pc_sl_l[1] : S;
+  const int s2 = PM >= 3 && P >= 3 ? (int)pc_sl_l[PM - 1] : S;
+  // first slice of the piece holding slice s, and the end of its slices
+  auto pstart = [&](int s) {
+    if constexpr (PM >= 3) return s >= s2 ? s2 : (s >= s1 ? s1 : 0);
+    else return s >= s1 ? s1 : 0;
+  };
+  auto pend = [&](int s) {
+    if constexpr (PM >= 3) return s >= s2 ? S : (s >= s1 ? s2 : s1);
+    else return s >= s1 ? S : s1;
+  };
   const int e0 = t * E;
   const int e1 = e0 + E < Tt ? e0 + E : Tt;
   const bool full = e1 - e0 == E;
@@ -620,7 +643,7 @@ __device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off
   if (e0 < e1) {
     if constexpr (sizeof(O) == 8) {
 #pragma unroll
-      for (int j = 1; j < 2 * K; j++) {
+      for (int j = 1; j < PM * K; j++) {
         const int so = __builtin_amdgcn_readfirstlane(j < S ? (int)sl_off_l[j] : 0x7FFFFFFF);
         sa += so <= e0 ? 1 : 0;
         sb += so <= e1 - 1 ? 1 : 0;
@@ -634,9 +657,9 @@ __device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off
 #pragma unroll
   for (int st = 1; st <= LOGK; st++) {
     const int h = 1 << (st - 1);
-    const int pa0 = sa >= s1 ? s1 : 0;
+    const int pa0 = pstart(sa);
     const int ga = pa0 + (((sa - pa0) >> st) << st);
-    const int pb0 = sb >= s1 ? s1 : 0;
+    const int pb0 = pstart(sb);
     const int gb = pb0 + (((sb - pb0) >> st) << st);
     O ok[E];
     uint32_t os[E];   // LDS byte offset of each output's source key
@@ -648,7 +671,7 @@ __device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off
     // unit A holds the lane's first output; a lane whose outputs run on into
     // the next unit B (it starts where A ends) takes the same path, switching
     // to B's start mid-merge
-    const int pendA = sa >= s1 ? S : s1;
+    const int pendA = pend(sa);
     const int iMA = ga + h < pendA ? ga + h : pendA;
     const int iRA = ga + 2 * h < pendA ? ga + 2 * h : pendA;
     const int u0 = sl_off_l[ga], u1 = sl_off_l[iMA], u2 = sl_off_l[iRA];
@@ -672,7 +695,7 @@ __device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off
         // switch for the others
         if (i > 0 && __any(i == swi)) {
           if (i == swi) {
-            const int pendB = sb >= s1 ? S : s1;
+            const int pendB = pend(sb);
             const int iMB = gb + h < pendB ? gb + h : pendB;
             const int iRB = gb + 2 * h < pendB ? gb + 2 * h : pendB;
             pa = (uint32_t)u2 * KS;
@@ -698,11 +721,11 @@ __device__ inline void merge_stages_inplace(O *ks, V *vs, const uint16_t *sl_off
       int e = e0;
       while (e < e1) {
         const int s = ub16(sl_off_l, S + 1, e) - 1;
-        const int s0 = s >= s1 ? s1 : 0;
-        const int pend = s >= s1 ? S : s1;
+        const int s0 = pstart(s);
+        const int pe = pend(s);
         const int g0 = s0 + (((s - s0) >> st) << st);
-        const int iM = g0 + h < pend ? g0 + h : pend;
-        const int iR = g0 + 2 * h < pend ? g0 + 2 * h : pend;
+        const int iM = g0 + h < pe ? g0 + h : pe;
+        const int iR = g0 + 2 * h < pe ? g0 + 2 * h : pe;
         const int u0 = sl_off_l[g0], u1 = sl_off_l[iM], u2 = sl_off_l[iR];
         const int nL = u1 - u0, nR = u2 - u1, diag = e - u0;
         int lo = diag - nR > 0 ? diag - nR : 0;
@@ -814,17 +837,18 @@ __device__ inline void store_tile(const O *ks, const V *vs, O *out_keys,
   }
 }
 
-// Coalesced stores of a descriptor tile (one or two pieces): the output index
-// of position e is base0 + e before the second piece and base1 + e from it on.
-// The base is chosen once per wave unless the piece split falls among the
-// wave's 64 positions.
-template <typename Kt, typename O, typename V, int E, int THREADS>
+// Coalesced stores of a descriptor tile (up to PM pieces): the output index
+// of position e is base_p + e in piece p.  The base is chosen once per wave
+// unless a piece split falls among the wave's 64 positions.
+template <typename Kt, typename O, typename V, int E, int THREADS, int PM>
 __device__ inline void store_fast(const O *ks, const V *vs, O *out_keys, V *out_vals,
                                   bool has_vals, const uint16_t *pc_loff, const uint64_t *pc_out,
                                   int P, int Tt, int t) {
-  const int split = P == 2 ? (int)pc_loff[1] : Tt;
+  const int sp1 = P >= 2 ? (int)pc_loff[1] : Tt;
+  const int sp2 = PM >= 3 && P >= 3 ? (int)pc_loff[PM - 1] : Tt;
   const uint64_t base0 = pc_out[0] - (uint64_t)pc_loff[0];
-  const uint64_t base1 = P == 2 ? pc_out[1] - (uint64_t)pc_loff[1] : base0;
+  const uint64_t base1 = P >= 2 ? pc_out[1] - (uint64_t)pc_loff[1] : base0;
+  const uint64_t base2 = PM >= 3 && P >= 3 ? pc_out[PM - 1] - (uint64_t)pc_loff[PM - 1] : base1;
   const int lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
 #pragma unroll
@@ -832,9 +856,16 @@ __device__ inline void store_fast(const O *ks, const V *vs, O *out_keys, V *out_
     const int x0 = (w + i * (THREADS / 64)) * 64;
     const int e = x0 + lane;
     uint64_t base;
-    if (x0 + 63 < split) base = base0;
-    else if (x0 >= split) base = base1;
-    else base = e < split ? base0 : base1;
+    if constexpr (PM >= 3) {
+      if (x0 + 63 < sp1) base = base0;
+      else if (x0 >= sp2) base = base2;
+      else if (x0 >= sp1 && x0 + 63 < sp2) base = base1;
+      else base = e < sp1 ? base0 : (e < sp2 ? base1 : base2);
+    } else {
+      if (x0 + 63 < sp1) base = base0;
+      else if (x0 >= sp1) base = base1;
+      else base = e < sp1 ? base0 : base1;
+    }
     if (e < Tt) {
       const uint64_t g = base + (uint64_t)e;
       out_keys[g] = Kt::unord(ks[e]);
@@ -845,10 +876,10 @@ __device__ inline void store_fast(const O *ks, const V *vs, O *out_keys, V *out_
 
 // The co-rank samples among a descriptor tile's outputs (every
 // kSampleStride-th global position), written by the lanes of one wave.
-template <typename O>
+template <typename O, int PM>
 __device__ inline void store_samples(const O *ks, const uint16_t *pc_loff, const uint64_t *pc_out,
                                      int P, int Tt, int lane, uint64_t *smp) {
-  for (int p = 0; p < P && p < 2; p++) {
+  for (int p = 0; p < P && p < PM; p++) {
     const int l0 = pc_loff[p], l1 = p + 1 < P ? (int)pc_loff[p + 1] : Tt;
     const uint64_t g0 = pc_out[p], g1 = g0 + (uint64_t)(l1 - l0);
     const uint64_t q0 = (g0 + kSampleStride - 1) / kSampleStride;
@@ -877,13 +908,14 @@ __global__ __launch_bounds__(THREADS, (sizeof(typename Key<KT>::U) == 4 && sizeo
 void k_merge_fast(
     const typename Key<KT>::U *__restrict__ in_keys, const V *__restrict__ in_vals,
     typename Key<KT>::U *__restrict__ out_keys, V *__restrict__ out_vals,
-    Plan *__restrict__ plan, int level, const TileTab<K> *__restrict__ desc,
+    Plan *__restrict__ plan, int level, const TileTabFor<typename Key<KT>::U, K> *__restrict__ desc,
     uint64_t *__restrict__ smp) {
   using Kt = Key<KT>;
   using O = typename Kt::U;
   using SM = FastSmem<O, K, TILE, (int)sizeof(V)>;
   constexpr int E = TILE / THREADS;
   constexpr int NW = SM::kTabWords;
+  constexpr int PM = SM::Tab::kPieces;
   __shared__ SM sm;
   O *kA = reinterpret_cast<O *>(sm.bufA + 16);
   V *vA = reinterpret_cast<V *>(sm.bufA + SM::kKeyBytes);
@@ -914,7 +946,7 @@ void k_merge_fast(
   lds_barrier();
   if (t < NW && nxt < tiles) dreg = descw[nxt * NW + t];
   if (sm.tab[0].kind == kTabFast) {
-    addr_desc<E, THREADS, K>(ga, sm.tab[0], t);
+    addr_desc<E, THREADS>(ga, sm.tab[0], t);
     issue_at<O, V, E, HV>(kreg, vreg, in_keys, in_vals, ga);
   }
   int cur = 0;
@@ -924,8 +956,8 @@ void k_merge_fast(
     const bool reclaim = cidx == kFastClaim;
     uint32_t claimed = 0;
     if (reclaim && t == 0) claimed = atomicAdd(queue, (uint32_t)kFastClaim);
-    TileTab<K> &T = sm.tab[cur];
-    TileTab<K> &N = sm.tab[cur ^ 1];
+    typename SM::Tab &T = sm.tab[cur];
+    typename SM::Tab &N = sm.tab[cur ^ 1];
     const int kind = T.kind;
     if (kind == kTabFast) commit_loads<Kt, O, V, E, THREADS>(kreg, vreg, kA, vA, HV, T.Tt, t);
     // next tile's table from its prefetched words (kTabNone past the end)
@@ -939,14 +971,15 @@ void k_merge_fast(
     const uint64_t after = cbase + (uint64_t)cidx++;
     if (t < NW && after < tiles) dreg = descw[after * NW + t];
     if (N.kind == kTabFast) {
-      addr_desc<E, THREADS, K>(ga, N, t);
+      addr_desc<E, THREADS>(ga, N, t);
       issue_at<O, V, E, HV>(kreg, vreg, in_keys, in_vals, ga);
     }
     if (kind == kTabFast) {
-      merge_stages_inplace<O, V, K, TILE, THREADS, HV>(kA, vA, T.sl_off, T.S, T.pc_sl, T.P, T.Tt, t);
-      store_fast<Kt, O, V, E, THREADS>(kA, vA, out_keys, out_vals, HV, T.pc_loff, T.pc_out, T.P,
-                                    T.Tt, t);
-      if (t >= THREADS - 64) store_samples<O>(kA, T.pc_loff, T.pc_out, T.P, T.Tt, lane, smp);
+      merge_stages_inplace<O, V, K, TILE, THREADS, HV, PM>(kA, vA, T.sl_off, T.S, T.pc_sl, T.P,
+                                                           T.Tt, t);
+      store_fast<Kt, O, V, E, THREADS, PM>(kA, vA, out_keys, out_vals, HV, T.pc_loff, T.pc_out,
+                                           T.P, T.Tt, t);
+      if (t >= THREADS - 64) store_samples<O, PM>(kA, T.pc_loff, T.pc_out, T.P, T.Tt, lane, smp);
     } else if (kind == kTabBad) {
       if (t == 0) atomicOr(&plan->error, 32u);
     }
@@ -1176,7 +1209,7 @@ template <int KT, int K, int TILE, int THREADS, bool HV, typename V>
 void launch_merges_v(const LevelArgs &a, const Work &w, const uint32_t *tj,
                      const uint64_t *tile_base, int level, hipStream_t s) {
   using U = typename Key<KT>::U;
-  const TileTab<K> *desc = reinterpret_cast<const TileTab<K> *>(w.tile_desc);
+  const TileTabFor<U, K> *desc = reinterpret_cast<const TileTabFor<U, K> *>(w.tile_desc);
   auto kf = k_merge_fast<KT, K, TILE, THREADS, HV, V>;
   auto kg = k_merge_general<KT, K, TILE, THREADS, HV, V>;
   unsigned gf = fill_grid((const void *)kf, THREADS, 1024);

@@ -289,8 +289,9 @@ static void launch_cuts_t(const LevelArgs &a, const Work &w, const uint32_t *tj,
   hipLaunchKernelGGL((k_corank<KT, K>), dim3(gk), dim3(256), 0, s, (const U *)a.in_keys,
                      w.run_start, w.Ls, w.Rs, w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj,
                      tile_base, w.plan, level, w.tile, w.corank, (const uint64_t *)w.samples);
-  TileTab<K> *desc = reinterpret_cast<TileTab<K> *>(w.tile_desc);
-  hipLaunchKernelGGL((k_tile_desc<K>), dim3(gc), dim3(256), 0, s, w.run_start, w.Ls, w.Rs,
+  using Tab = TileTabFor<U, K>;
+  Tab *desc = reinterpret_cast<Tab *>(w.tile_desc);
+  hipLaunchKernelGGL((k_tile_desc<K, Tab::kPieces>), dim3(gc), dim3(256), 0, s, w.run_start, w.Ls, w.Rs,
                      w.nd_mem, w.nd_arity, w.lvl_list, w.lvl_np, tj, tile_base, w.plan, level,
                      w.tile, w.corank, desc, w.gen_list);
 }
