@@ -312,6 +312,9 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_emit(
   __shared__ uint64_t sD[kDetThreads + 1], sSB[kDetThreads];
   __shared__ int64_t sScan[kDetThreads];
   __shared__ uint64_t sCarry[2];
+  // the block's runs in order: start position within the block | direction << 15
+  __shared__ uint16_t sRun[kDetBlockPos];
+  static_assert(kDetBlockPos <= (1u << 15), "block positions fit in 15 bits");
   const uint64_t nwords = (N + 63) / 64;
   const uint64_t word0 = (uint64_t)blockIdx.x * kDetThreads;
   const int t = threadIdx.x;
@@ -337,19 +340,26 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_emit(
   }
   uint64_t brk = word_breaks(wi.C, wi.SB, wi.valid, (int)(zin & 1));
   uint64_t total;
-  uint64_t pos = block_excl_sum(__popcll(brk), reinterpret_cast<uint64_t *>(sScan), &total);
-  pos += off_blk[blockIdx.x];
+  uint32_t q = (uint32_t)block_excl_sum(__popcll(brk), reinterpret_cast<uint64_t *>(sScan), &total);
   uint64_t nextD = sD[t + 1];
+  // a thread's runs go to LDS first; the block then writes its runs with
+  // consecutive lanes on consecutive entries (a thread's own runs would be
+  // stores whose lanes lie many entries apart)
   while (brk) {
     int j = __ffsll((long long)brk) - 1;
     brk &= brk - 1;
-    uint64_t p = wstart + j;
-    uint64_t dnext = j < 63 ? ((wi.D >> (j + 1)) & 1) : (nextD & 1);
+    uint32_t dnext = j < 63 ? (uint32_t)((wi.D >> (j + 1)) & 1) : (uint32_t)(nextD & 1);
+    sRun[q++] = (uint16_t)((uint32_t)(t * 64 + j) | dnext << 15);
+  }
+  __syncthreads();
+  const uint64_t base = off_blk[blockIdx.x];
+  for (uint32_t i = t; i < (uint32_t)total; i += kDetThreads) {
+    const uint64_t pos = base + i;
+    const uint32_t v = sRun[i];
     if (pos < rmax) {
-      run_start[pos] = p;
-      run_desc[pos] = (uint8_t)dnext;
+      run_start[pos] = word0 * 64 + (v & 0x7FFFu);
+      run_desc[pos] = (uint8_t)(v >> 15);
     }
-    pos++;
   }
 }
 

@@ -88,6 +88,11 @@ constexpr uint32_t kPcIn = 1;    // a small root's span
 constexpr uint32_t kPcOdd = 2;   // ... whose depth is odd
 constexpr int kPcShift = 13;
 constexpr uint32_t kPcPos = (1u << kPcShift) - 1;
+// Tags of the sort: source position | piece flags << kTagFlagShift.
+constexpr int kTagFlagShift = 16;
+static_assert(kChunkRec == 8, "a chunk record is read as two 16-byte words");
+constexpr uint32_t kTagPos = (1u << kTagFlagShift) - 1;
+static_assert(kLeafCap <= (int)kTagPos, "tag positions");
 // Mark bits per position (fallback path): one byte per position.
 constexpr uint32_t kMkEnd = 1, kMkStart = 2, kMkOdd = 4;
 
@@ -100,7 +105,7 @@ __device__ inline int lph(int p) { return p + (p >> 3); }   // p >= 0
 template <typename O, bool HV, typename V>
 struct LeafSmem {
   O key[kLeafPad];                   // order keys
-  uint32_t tag[kLeafPad];            // source positions; before the sort: the root list and marks
+  uint32_t tag[kLeafPad];            // source positions and piece flags; before the sort: the root list and marks
   V val[HV ? kLeafCap : 1];          // payloads in source order
   uint16_t pinfo[kLeafCap + 2];      // piece table
   uint32_t wsum[kLeafThreads / 64];
@@ -193,17 +198,23 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
     __syncthreads();
     const uint32_t ntodo = sm.misc[7];
     for (uint32_t ti = 0; ti < ntodo; ti++) {
-      const uint64_t c = sm.todo[ti];
+      const uint64_t c = (uint64_t)__builtin_amdgcn_readfirstlane((int)sm.todo[ti]);
       const uint64_t c0 = c * kLeafChunk, c1 = c0 + kLeafChunk;
-      const uint32_t *rec = croot + c * kChunkRec;
-      const uint32_t nrec = rec[0];
+      // the chunk's whole root record in one round trip (uniform: scalar loads)
+      const uint4 *rec4 = reinterpret_cast<const uint4 *>(croot + c * kChunkRec);
+      const uint4 rq0 = rec4[0], rq1 = rec4[1];
+      const uint32_t rv[kChunkRec] = {rq0.x, rq0.y, rq0.z, rq0.w, rq1.x, rq1.y, rq1.z, rq1.w};
+      const uint32_t nrec = rv[0];
       const bool inl = nrec < (uint32_t)kChunkRec;   // uniform
       uint32_t ra = 0xFFFFFFFFu, rb = 0;   // first root start, last root end (- c0)
       if (inl) {
-        for (uint32_t x = 0; x < nrec; x++) {
-          const uint32_t v = rec[1 + x];
-          ra = (v & 0x7FF) < ra ? (v & 0x7FF) : ra;
-          rb = ((v >> 11) & 0xFFF) > rb ? ((v >> 11) & 0xFFF) : rb;
+#pragma unroll
+        for (int x = 0; x + 1 < kChunkRec; x++) {
+          const uint32_t v = rv[1 + x];
+          if ((uint32_t)x < nrec) {
+            ra = (v & 0x7FF) < ra ? (v & 0x7FF) : ra;
+            rb = ((v >> 11) & 0xFFF) > rb ? ((v >> 11) & 0xFFF) : rb;
+          }
         }
       } else {
         // more roots than the record holds: leaders among the boundaries of
@@ -254,25 +265,32 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
       // ---- the piece table
       if (inl) {
         if (t == 0) {
-          // roots in position order (at most kChunkRec - 1: insertion sort)
-          uint32_t v[kChunkRec - 1];
-          int n = 0;
-          for (uint32_t x = 0; x < nrec; x++) {
-            const uint32_t y = rec[1 + x];
-            int z = n++;
-            while (z > 0 && (v[z - 1] & 0x7FF) > (y & 0x7FF)) {
-              v[z] = v[z - 1];
-              z--;
+          // roots in position order: odd-even transposition over the record's
+          // kChunkRec - 1 slots, absent ones (all ones) last; starts differ
+          constexpr int NR = kChunkRec - 1;
+          uint32_t v[NR];
+#pragma unroll
+          for (int x = 0; x < NR; x++) v[x] = (uint32_t)x < nrec ? rv[1 + x] : 0xFFFFFFFFu;
+#pragma unroll
+          for (int rnd = 0; rnd < NR; rnd++) {
+#pragma unroll
+            for (int x = rnd & 1; x + 1 < NR; x += 2) {
+              const uint32_t a = v[x], b = v[x + 1];
+              const bool sw = (b & 0x7FF) < (a & 0x7FF);
+              v[x] = sw ? b : a;
+              v[x + 1] = sw ? a : b;
             }
-            v[z] = y;
           }
           int np = 0;
           uint32_t prev = ra;
-          for (int x = 0; x < n; x++) {
-            const uint32_t st = v[x] & 0x7FF, en = (v[x] >> 11) & 0xFFF;
-            if (st > prev) sm.pinfo[np++] = (uint16_t)(prev - ra);   // a stretch
-            sm.pinfo[np++] = (uint16_t)((st - ra) | (kPcIn | (((v[x] >> 23) & 1) ? kPcOdd : 0u)) << kPcShift);
-            prev = en;
+#pragma unroll
+          for (int x = 0; x < NR; x++) {
+            if ((uint32_t)x < nrec) {
+              const uint32_t st = v[x] & 0x7FF, en = (v[x] >> 11) & 0xFFF;
+              if (st > prev) sm.pinfo[np++] = (uint16_t)(prev - ra);   // a stretch
+              sm.pinfo[np++] = (uint16_t)((st - ra) | (kPcIn | (((v[x] >> 23) & 1) ? kPcOdd : 0u)) << kPcShift);
+              prev = en;
+            }
           }
           sm.pinfo[np] = (uint16_t)Tt;       // padding piece
           sm.pinfo[np + 1] = (uint16_t)Tp;   // end
@@ -332,7 +350,10 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
           while (x < np && (int)(sm.pinfo[x + 1] & kPcPos) <= p) x++;
           pc[q] = x;
           it[q].k = p < Tt ? sm.key[lph(p)] : (O)~(O)0;
-          it[q].g = (uint32_t)p;
+          // the tag: source position, and the flags of its piece (an element
+          // never leaves its piece, so they travel with it to the store)
+          it[q].g = (uint32_t)p |
+                    (HV ? ((uint32_t)sm.pinfo[pc[q]] >> kPcShift) << kTagFlagShift : 0u);
         }
       }
 #pragma unroll
@@ -428,17 +449,22 @@ __global__ __launch_bounds__(kLeafThreads, 4) void k_leaf_pass(
       for (int q = 0; q < E; q++) {
         const int e = t + q * T;
         if (e < Tt) {
-          const uint32_t f = (uint32_t)sm.pinfo[leaf_piece(sm.pinfo, np, e)] >> kPcShift;
+          uint32_t f, src = 0;
+          if (HV) {
+            const uint32_t tg = sm.tag[lph(e)];
+            f = tg >> kTagFlagShift;
+            src = tg & kTagPos;
+          } else {
+            f = (uint32_t)sm.pinfo[leaf_piece(sm.pinfo, np, e)] >> kPcShift;
+          }
           if (f & kPcIn) {
             const uint64_t g = lo + (uint64_t)e;
             const O ok = sm.key[lph(e)];
-            const U k = Kt::unord(ok);
-            if (f & kPcOdd) {
-              akeys[g] = k;
-              if (HV) avals[g] = sm.val[sm.tag[lph(e)]];
-            } else {
-              keys[g] = k;
-              if (HV) vals[g] = sm.val[sm.tag[lph(e)]];
+            U *dk = (f & kPcOdd) ? akeys : keys;
+            dk[g] = Kt::unord(ok);
+            if (HV) {
+              V *dv = (f & kPcOdd) ? avals : vals;
+              dv[g] = sm.val[src];
             }
             if ((g & (kSampleStride - 1)) == 0) smp[g / kSampleStride] = (uint64_t)ok;
           }

@@ -35,6 +35,38 @@ __device__ inline uint32_t quot31(uint64_t a, uint64_t n, double inv) {
   return (uint32_t)q;
 }
 
+// Workgroup-wide fold of one value per thread (256 threads) into a plan
+// field with one atomic per workgroup.  Many atomics on one address are
+// serviced one after another, so a per-wave atomic at the end of a short
+// kernel costs more than the kernel's own work.  A maximum is only sent when
+// it would raise the field.
+template <typename T>
+__device__ inline void block_max_into(T v, T *dst) {
+  __shared__ T part[4];
+  for (int o = 32; o > 0; o >>= 1) {
+    const T y = __shfl_down(v, o);
+    v = y > v ? y : v;
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T m = part[0];
+    for (int w = 1; w < 4; w++) m = part[w] > m ? part[w] : m;
+    if (m > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, m);
+  }
+}
+
+__device__ inline void block_add_into(uint64_t v, uint64_t *dst) {
+  __shared__ uint64_t part[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t m = part[0] + part[1] + part[2] + part[3];
+    if (m) atomicAdd((unsigned long long *)dst, (unsigned long long)m);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
                                                 const uint64_t *__restrict__ off, uint64_t m,
                                                 Plan *__restrict__ plan, int logk,
@@ -67,11 +99,7 @@ __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
     P[i] = p;
     pmax = p > pmax ? p : pmax;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t y = __shfl_down(pmax, o);
-    pmax = y > pmax ? y : pmax;
-  }
-  if ((threadIdx.x & 63) == 0 && pmax) atomicMax(&plan->pmax, pmax);
+  block_max_into<uint32_t>(pmax, &plan->pmax);
 }
 
 // ---------------------------------------------------------------- ANSV
@@ -461,9 +489,7 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
     }
     sflag[i] = f;
   }
-  for (int o = 32; o > 0; o >>= 1) n_small += __shfl_down(n_small, o);
-  if ((threadIdx.x & 63) == 0 && n_small)
-    atomicAdd((unsigned long long *)&plan->n_small, (unsigned long long)n_small);
+  block_add_into(n_small, &plan->n_small);
 }
 
 // The boundaries whose sflag has a bit of `mask` (the leaders whose depth is
@@ -595,18 +621,9 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
     if (FULL && in_small && d > dend) dend = d;
     if (want_cost) cost += (uint64_t)d * (rs[j + 1] - rs[j]);
   }
-  if (FULL) {
-    // the deepest small node sits just above the deepest leaf of a small subtree
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint32_t y = __shfl_down(dend, o);
-      dend = y > dend ? y : dend;
-    }
-    if ((threadIdx.x & 63) == 0 && dend) atomicMax(&plan->small_depth_end, dend);
-  }
-  if (want_cost) {
-    for (int o = 32; o > 0; o >>= 1) cost += __shfl_down(cost, o);
-    if ((threadIdx.x & 63) == 0 && cost) atomicAdd((unsigned long long *)&plan->merge_cost, (unsigned long long)cost);
-  }
+  // the deepest small node sits just above the deepest leaf of a small subtree
+  if (FULL) block_max_into<uint32_t>(dend, &plan->small_depth_end);
+  if (want_cost) block_add_into(cost, &plan->merge_cost);
 }
 
 // ---------------------------------------------------------------- level lists
