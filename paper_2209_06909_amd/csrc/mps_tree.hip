@@ -437,12 +437,16 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
   for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
        ii += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t i = (uint32_t)ii;
+    // the loads at i, then those through them, each level issued together
     const uint32_t p = P[i];
+    const uint32_t l = Ls[i], rr = Rs[i], le = Le[i];
     uint8_t f = 0;
     if (p > 0) {
-      const uint32_t l = Ls[i], rr = Rs[i];
-      const bool small = rs[rr] - rs[l] <= (uint64_t)kSmallSpan;
-      const uint32_t pb = P[l] >= P[rr] ? l : rr;   // the parent's boundary
+      const uint64_t sl = rs[l], sr = rs[rr];
+      const uint32_t Pl = P[l], Pr = P[rr], Ple = P[le];
+      const bool small = sr - sl <= (uint64_t)kSmallSpan;
+      const uint32_t pb = Pl >= Pr ? l : rr;   // the parent's boundary
+      const uint32_t Ppb = Pl >= Pr ? Pl : Pr;
       if (FULL || !small) {
         uint32_t slot;
         const uint32_t lead = group_leader(P, Le, i, &slot);
@@ -453,7 +457,7 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
           if (P[Re[i]] < p) arity[lead] = (uint8_t)(slot + 2);
           if (slot == 0) {
             bool parent_small = false;
-            if (P[pb] == 0) {
+            if (Ppb == 0) {
               jump[i] = i;
               dist[i] = 0;
             } else {
@@ -471,9 +475,9 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
             }
           }
         }
-      } else if (P[Le[i]] < p) {   // the leader of a small node
+      } else if (Ple < p) {   // the leader of a small node
         n_small++;
-        if (P[pb] == 0) {
+        if (Ppb == 0) {
           f = kSmallNode | kSmallRoot;
           jump[i] = i;
           dist[i] = 0;
