@@ -73,18 +73,26 @@ __global__ __launch_bounds__(256) void k_powers(const uint64_t *__restrict__ rs,
                                                 uint8_t *__restrict__ P) {
   const uint64_t r = plan->r;
   uint32_t pmax = 0;
+  // the segment of the last boundary and its length's inverse (a division
+  // per segment change, not per boundary)
+  uint32_t sgc = 0xFFFFFFFFu;
+  uint64_t base = 0, n = 1;
+  double inv = 0.0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= r;
        i += (uint64_t)gridDim.x * blockDim.x) {
     uint8_t p = 0;
     if (i > 0 && i < r) {
-      uint64_t s = rs[i];
-      uint32_t sg = seg_of(off, m, s);
-      uint64_t base = off[sg];
+      const uint64_t s0 = rs[i - 1], s = rs[i], s2 = rs[i + 1];
+      const uint32_t sg = seg_of(off, m, s);
+      if (sg != sgc) {
+        sgc = sg;
+        base = off[sg];
+        n = off[sg + 1] - base;
+        inv = 2147483648.0 / (double)n;
+      }
       if (s != base) {
-        uint64_t n = off[sg + 1] - base;
-        uint64_t A = (rs[i - 1] - base) + (s - base);
-        uint64_t B = (s - base) + (rs[i + 1] - base);
-        const double inv = 2147483648.0 / (double)n;
+        uint64_t A = (s0 - base) + (s - base);
+        uint64_t B = (s - base) + (s2 - base);
         uint32_t x = quot31(A, n, inv);
         uint32_t y = quot31(B, n, inv);
         uint32_t p2 = (uint32_t)__clz(x ^ y) + 1;
@@ -604,11 +612,21 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
   uint32_t dend = 0;
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < r;
        j += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t pa = P[j], pb = P[j + 1];
-    uint32_t b = pa >= pb ? (uint32_t)j : (uint32_t)(j + 1);
+    // the run's larger delimiting boundary b: its node's span, or the node's
+    // leader; the entries of both candidates are loaded together
+    const uint32_t pa = P[j], pb = P[j + 1];
+    const bool left = pa >= pb;
+    const uint32_t b = left ? (uint32_t)j : (uint32_t)(j + 1);
+    const uint32_t Pb = left ? pa : pb;
+    uint32_t lb = 0, rb = 0;
+    if (!FULL) {
+      const uint32_t l0 = Ls[j], l1 = Ls[j + 1], r0 = Rs[j], r1 = Rs[j + 1];
+      lb = left ? l0 : l1;
+      rb = left ? r0 : r1;
+    }
     uint8_t d = 0, in_small = 0;
-    if (P[b] > 0) {
-      if (!FULL && rs[Rs[b]] - rs[Ls[b]] <= (uint64_t)kSmallSpan) {
+    if (Pb > 0) {
+      if (!FULL && rs[rb] - rs[lb] <= (uint64_t)kSmallSpan) {
         in_small = kLeafInSmall;
       } else {
         uint32_t s;
