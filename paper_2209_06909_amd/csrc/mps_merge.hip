@@ -112,7 +112,7 @@ __device__ inline void place_general(typename Key<KT>::U *__restrict__ keys,
   }
 }
 
-// Blocks that lie inside one run get that run's verdict (the leaf-depth pass
+// Blocks that lie inside one run get that run's flag (the leaf-depth pass
 // flagged only the first and last block of every run that moves).  One thread
 // per block, binary search in the run table.
 __global__ __launch_bounds__(256) void k_place_blocks(const uint64_t *__restrict__ rs,
