@@ -144,7 +144,10 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
   O prev_last = 0;
   if (wave_word0 < nwords && wave_word0 > 0) prev_last = K::ord(keys[wave_word0 * 64 - 1]);
   // 64 words per wave, eight at a time: the eight coalesced loads are issued
-  // together, then the words are processed in order.
+  // together, then the words are processed in order.  Positions past the end
+  // are clamped to the last key (loaded, never decisive: d is false there),
+  // and the keys are converted where they are used: a load under a branch,
+  // or one converted at once, would be waited for before the next is issued.
   constexpr int kU = 8;
   for (int i0 = 0; i0 < 64; i0 += kU) {
     if (wave_word0 + i0 >= nwords) break;  // uniform across the wave
@@ -152,13 +155,13 @@ __global__ __launch_bounds__(kDetThreads) void k_detect_bits(
 #pragma unroll
     for (int u = 0; u < kU; u++) {
       const uint64_t p = (wave_word0 + i0 + u) * 64 + lane;
-      xs[u] = p < N ? K::ord(keys[p]) : (O)0;
+      xs[u] = keys[p < N ? p : N - 1];
     }
 #pragma unroll
     for (int u = 0; u < kU; u++) {
       const int i = i0 + u;
       const uint64_t p = (wave_word0 + i) * 64 + lane;
-      const O x = xs[u];
+      const O x = K::ord(xs[u]);
       O xprev = shfl_any<O>(x, lane > 0 ? lane - 1 : 0);
       if (lane == 0) xprev = prev_last;
       prev_last = shfl_any<O>(x, 63);
