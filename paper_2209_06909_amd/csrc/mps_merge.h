@@ -107,9 +107,9 @@ __device__ inline uint64_t gshfl_up64(uint64_t v, int o) {
 constexpr int kCorankRounds = 4096;
 constexpr uint32_t kErrCorankRounds = 8192u;   // plan->error bit: a co-rank search ran out of rounds
 
-template <typename O, int K, typename Get>
+template <typename O, int K, typename Get, typename Conv>
 __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, int j, Get get,
-                                       uint32_t &spent) {
+                                       Conv conv, uint32_t &spent) {
   uint32_t mm = 0;
   spent = 1;
   for (int it = 0; it < kCorankRounds; it++) {
@@ -134,8 +134,13 @@ __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, in
     mm = v;
     // candidate largest taken (x) and smallest untaken (y) of this lane
     const bool hx = mm > 0, hy = mm < w;
-    O x = hx ? get(j, (uint64_t)(lo + mm - 1)) : (O)0;
-    O y = hy ? get(j, (uint64_t)(lo + mm)) : (O)0;
+    // both probes are loaded unconditionally (the getter clamps its index)
+    // and converted afterwards, so they are in flight together: a load under
+    // a branch is waited for before the branch joins
+    const auto xr = get(j, (uint64_t)(lo + (hx ? mm - 1 : 0)));
+    const auto yr = get(j, (uint64_t)(lo + mm));
+    O x = hx ? conv(xr) : (O)0;
+    O y = hy ? conv(yr) : (O)0;
     const O xj = x, yj = y;
     int a = hx ? j : -1, b = hy ? j : -1;
 #pragma unroll
@@ -172,7 +177,7 @@ __device__ inline uint32_t corank_group(uint32_t q, uint32_t lo, uint32_t hi, in
 // lower bound per child) and the one at Qhi >= Q* leaves only truly untaken
 // samples untaken (an upper bound).
 template <int KT, int K>
-__global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__restrict__ in_keys,
+__global__ __launch_bounds__(256, 8) void k_corank(const typename Key<KT>::U *__restrict__ in_keys,
                                                 const uint64_t *__restrict__ rs,
                                                 const uint32_t *__restrict__ Ls,
                                                 const uint32_t *__restrict__ Rs,
@@ -221,18 +226,22 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
           const uint32_t m = live ? (uint32_t)((nd.c[j + 1] + S - 1) / S - i0) : 0;
           const uint64_t off = live ? i0 * S - cj : 0;
           const uint32_t ms = gsum<K>(m);
-          auto gs = [&](int, uint64_t x) { return (O)smp[i0 + x]; };
+          // a lane's sample index stays in [i0, i0 + m - 1] (i0 alone when m
+          // is 0: smp has N / S + 2 entries)
+          const uint64_t m1 = m > 0 ? m - 1 : 0;
+          auto gs = [&](int, uint64_t x) { return smp[i0 + (x < m1 ? x : m1)]; };
+          auto cs = [](uint64_t v) { return (O)v; };
           const uint64_t qs = q / S;
           uint64_t qlo = qs > (uint64_t)d ? qs - d : 0;
           qlo = qlo < ms ? qlo : ms;
           const uint64_t qhi = qs + d + 1 < ms ? qs + d + 1 : ms;
           const uint32_t clo = corank_group<O, K>((uint32_t)qlo, 0u,
-                                                  m < qlo ? m : (uint32_t)qlo, j, gs, spent);
+                                                  m < qlo ? m : (uint32_t)qlo, j, gs, cs, spent);
           nspent |= spent;
           // the cut at qhi contains the one at qlo and exceeds it by qhi - qlo in total
           const uint32_t dq = (uint32_t)(qhi - qlo);
           const uint32_t chi = corank_group<O, K>((uint32_t)qhi, clo,
-                                                  m - clo < dq ? m : clo + dq, j, gs, spent);
+                                                  m - clo < dq ? m : clo + dq, j, gs, cs, spent);
           nspent |= spent;
           uint64_t nlo = clo >= 1 ? off + (uint64_t)(clo - 1) * S + 1 : 0;
           uint64_t nhi = chi < m ? off + (uint64_t)chi * S : len;
@@ -247,8 +256,12 @@ __global__ __launch_bounds__(256) void k_corank(const typename Key<KT>::U *__res
             atomicOr(&plan->error, 512u);   // never expected: keep the whole windows
           }
         }
-        auto gk = [&](int, uint64_t x) { return Key<KT>::ord(in_keys[cj + x]); };
-        out = corank_group<O, K>((uint32_t)q, lo, hi, j, gk, spent);
+        // a lane's key index stays in its child (a live child is never empty;
+        // an idle lane reads key 0)
+        const uint64_t l1 = len > 0 ? len - 1 : 0;
+        auto gk = [&](int, uint64_t x) { return in_keys[cj + (x < l1 ? x : l1)]; };
+        auto ck = [](O v) { return Key<KT>::ord(v); };
+        out = corank_group<O, K>((uint32_t)q, lo, hi, j, gk, ck, spent);
         nspent |= spent;
         if (nspent && j == 0) atomicOr(&plan->error, kErrCorankRounds);
         if (!live) out = 0;
