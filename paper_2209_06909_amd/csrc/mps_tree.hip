@@ -445,16 +445,24 @@ __global__ __launch_bounds__(256) void k_nodes(const uint8_t *__restrict__ P,
   for (uint64_t ii = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; ii < r;
        ii += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t i = (uint32_t)ii;
-    // the loads at i, then those through them, each level issued together
+    // The loads at i, then those through them, each level issued together and
+    // before any branch: indices are clamped into [0, r] (entries of boundaries
+    // of power 0 are never used).  A load issued under a branch is waited for
+    // before the branch joins, which made these a chain of single loads; the
+    // empty asm statement keeps the compiler from moving the second level
+    // into the branches that use it.
     const uint32_t p = P[i];
-    const uint32_t l = Ls[i], rr = Rs[i], le = Le[i];
+    const uint32_t l0 = Ls[i], r0 = Rs[i], le0 = Le[i];
+    const uint32_t l = l0 <= (uint32_t)r ? l0 : 0u, rr = r0 <= (uint32_t)r ? r0 : 0u;
+    const uint32_t le = le0 <= (uint32_t)r ? le0 : 0u;
+    const uint64_t sl = rs[l], sr = rs[rr];
+    const uint32_t Pl = P[l], Pr = P[rr], Ple = P[le];
+    asm volatile("" ::"v"(sl), "v"(sr), "v"(Pl), "v"(Pr), "v"(Ple));
+    const bool small = sr - sl <= (uint64_t)kSmallSpan;
+    const uint32_t pb = Pl >= Pr ? l : rr;   // the parent's boundary
+    const uint32_t Ppb = Pl >= Pr ? Pl : Pr;
     uint8_t f = 0;
     if (p > 0) {
-      const uint64_t sl = rs[l], sr = rs[rr];
-      const uint32_t Pl = P[l], Pr = P[rr], Ple = P[le];
-      const bool small = sr - sl <= (uint64_t)kSmallSpan;
-      const uint32_t pb = Pl >= Pr ? l : rr;   // the parent's boundary
-      const uint32_t Ppb = Pl >= Pr ? Pl : Pr;
       if (FULL || !small) {
         uint32_t slot;
         const uint32_t lead = group_leader(P, Le, i, &slot);
@@ -618,15 +626,21 @@ __global__ __launch_bounds__(256) void k_leaves(const uint8_t *__restrict__ P,
     const bool left = pa >= pb;
     const uint32_t b = left ? (uint32_t)j : (uint32_t)(j + 1);
     const uint32_t Pb = left ? pa : pb;
-    uint32_t lb = 0, rb = 0;
+    uint64_t span = 0;
     if (!FULL) {
+      // clamped into [0, r] (a boundary of power 0 has no node) and loaded
+      // before the branch that uses them, as in k_nodes
       const uint32_t l0 = Ls[j], l1 = Ls[j + 1], r0 = Rs[j], r1 = Rs[j + 1];
-      lb = left ? l0 : l1;
-      rb = left ? r0 : r1;
+      uint32_t lb = left ? l0 : l1, rb = left ? r0 : r1;
+      lb = lb <= (uint32_t)r ? lb : 0u;
+      rb = rb <= (uint32_t)r ? rb : 0u;
+      const uint64_t slb = rs[lb], srb = rs[rb];
+      asm volatile("" ::"v"(slb), "v"(srb));
+      span = srb - slb;
     }
     uint8_t d = 0, in_small = 0;
     if (Pb > 0) {
-      if (!FULL && rs[rb] - rs[lb] <= (uint64_t)kSmallSpan) {
+      if (!FULL && span <= (uint64_t)kSmallSpan) {
         in_small = kLeafInSmall;
       } else {
         uint32_t s;
