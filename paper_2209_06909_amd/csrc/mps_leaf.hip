@@ -60,7 +60,9 @@ __global__ __launch_bounds__(256) void k_chunk_runs(const uint64_t *__restrict__
   }
 }
 
-// Records every small root in the chunk where its span starts.
+// Records every small root in the chunk where its span starts.  A thread
+// takes 16 boundaries at a time, their flags in one 16-byte load (sflag holds
+// 16 bytes of slack past r).
 __global__ __launch_bounds__(256) void k_chunk_mark(const uint64_t *__restrict__ rs,
                                                     const uint32_t *__restrict__ Ls,
                                                     const uint32_t *__restrict__ Rs,
@@ -70,9 +72,21 @@ __global__ __launch_bounds__(256) void k_chunk_mark(const uint64_t *__restrict__
                                                     uint32_t *__restrict__ croot) {
   const uint64_t r = plan->r;
   if (plan->n_small == 0) return;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < r;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    if (sflag[i] & kSmallRoot) {
+  const uint64_t ng = (r + 15) / 16;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    const uint4 fv = reinterpret_cast<const uint4 *>(sflag)[g];
+    const uint32_t fw[4] = {fv.x, fv.y, fv.z, fv.w};
+    uint32_t bits = 0;   // bit q: boundary g*16+q is a small root
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      const uint64_t i = g * 16 + q;
+      if (((fw[q >> 2] >> ((q & 3) * 8)) & kSmallRoot) && i > 0 && i < r) bits |= 1u << q;
+    }
+    while (bits) {
+      const int q = __ffs(bits) - 1;
+      bits &= bits - 1;
+      const uint64_t i = g * 16 + q;
       const uint64_t st = rs[Ls[i]], en = rs[Rs[i]];
       const uint64_t c = st / kLeafChunk, c0 = c * kLeafChunk;
       const uint32_t slot = atomicAdd(&croot[c * kChunkRec], 1u);
